@@ -1,0 +1,306 @@
+"""Pins for the FP64 oracle: each check compares the oracle against something
+other than itself -- the definitions of Section 2.1 evaluated by brute force,
+library routines for special cases, identities the paper states (eqs. 1, 3,
+11, 14), the least-squares subproblem of eq. (6), and the structure of Q0
+stated in Section 3.2."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle as O
+import synthgen as G
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------- Section 2.1
+def test_ttm_matches_definition_by_loops():
+    r = rng(1)
+    X = r.standard_normal((3, 4, 5))
+    for n in range(3):
+        B = r.standard_normal((2, X.shape[n]))
+        Y = O.ttm(X, B, n)
+        dims = list(X.shape)
+        dims[n] = 2
+        assert Y.shape == tuple(dims)
+        for idx in itertools.product(*[range(d) for d in dims]):
+            s = 0.0
+            for i in range(X.shape[n]):
+                src = list(idx)
+                src[n] = i
+                s += X[tuple(src)] * B[idx[n], i]
+            assert abs(Y[idx] - s) < 1e-12
+
+
+def test_unfold_column_order_by_loops():
+    X = rng(2).standard_normal((3, 4, 5, 2))
+    for n in range(4):
+        U = O.unfold(X, n)
+        others = [k for k in range(4) if k != n]
+        for idx in itertools.product(*[range(d) for d in X.shape]):
+            col, stride = 0, 1
+            for k in others:               # smallest remaining mode fastest
+                col += idx[k] * stride
+                stride *= X.shape[k]
+            assert U[idx[n], col] == X[idx]
+        assert np.array_equal(O.fold(U, n, X.shape), X)
+
+
+def test_kron_matches_numpy():
+    r = rng(3)
+    A, B = r.standard_normal((3, 2)), r.standard_normal((4, 5))
+    assert np.array_equal(O.kron(A, B), np.kron(A, B))
+
+
+def test_khatri_rao_columns_are_kroneckers():
+    r = rng(4)
+    mats = [r.standard_normal((d, 3)) for d in (2, 4, 3)]
+    KR = O.khatri_rao(mats)
+    for c in range(3):
+        ref = np.kron(np.kron(mats[0][:, c], mats[1][:, c]), mats[2][:, c])
+        assert np.allclose(KR[:, c], ref, rtol=0, atol=1e-14)
+
+
+def test_mixed_product_identity_eq1():
+    r = rng(5)
+    A, B = r.standard_normal((3, 4)), r.standard_normal((5, 4))
+    C, D = r.standard_normal((2, 3)), r.standard_normal((6, 5))
+    lhs = np.kron(C, D) @ O.khatri_rao([A, B])
+    rhs = O.khatri_rao([C @ A, D @ B])
+    assert np.allclose(lhs, rhs, atol=1e-12)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_multi_ttm_unfolding_identity_eq3(N):
+    r = rng(6 + N)
+    dims = [3, 4, 2, 5][:N]
+    X = r.standard_normal(dims)
+    Bs = [r.standard_normal((2 + k % 2, dims[k])) for k in range(N)]
+    for n in range(N):
+        Y = X
+        for k in range(N):
+            if k != n:
+                Y = O.ttm(Y, Bs[k], k)
+        K = None
+        for k in reversed(range(N)):       # B_N kron ... kron B_1, skipping n
+            if k == n:
+                continue
+            K = Bs[k] if K is None else np.kron(K, Bs[k])
+        assert np.allclose(O.unfold(Y, n), O.unfold(X, n) @ K.T, atol=1e-12)
+
+
+# ---------------------------------------------------------------- Section 2.4
+@pytest.mark.parametrize("shape", [(7, 3), (40, 5), (64, 16), (5, 5), (130, 33)])
+def test_householder_matches_library_qr(shape):
+    A = rng(sum(shape)).standard_normal(shape)
+    Q, R = O.householder_qr(A)
+    Ql, Rl = np.linalg.qr(A)
+    s = np.sign(np.diag(Rl))
+    Ql, Rl = Ql * s, s[:, None] * Rl
+    assert np.all(np.diag(R) >= 0)
+    assert np.allclose(Q, Ql, atol=1e-12)
+    assert np.allclose(R, Rl, atol=1e-12)
+    assert np.linalg.norm(Q.T @ Q - np.eye(shape[1])) < 1e-13
+    assert np.allclose(Q @ R, A, atol=1e-12)
+    assert np.array_equal(R, np.triu(R))
+
+
+def test_householder_exact_e1_column():
+    A = rng(9).standard_normal((20, 4))
+    A[:, 0] = 0.0
+    A[0, 0] = 2.5
+    Q, R = O.householder_qr(A)
+    e1 = np.zeros(20)
+    e1[0] = 1.0
+    assert np.array_equal(Q[:, 0], e1)
+    assert np.all(Q[0, 1:] == 0.0)
+    assert R[0, 0] == 2.5
+
+
+def test_back_substitution_matches_library():
+    r = rng(10)
+    U = np.triu(r.standard_normal((6, 6))) + 4 * np.eye(6)
+    B = r.standard_normal((6, 9))
+    assert np.allclose(O.back_substitution(U, B),
+                       scipy.linalg.solve_triangular(U, B, lower=False), atol=1e-12)
+
+
+def _state(N=3, dims=(5, 6, 4), R=3, seed=11):
+    r = rng(seed)
+    A = [r.standard_normal((d, R)) for d in dims[:N]]
+    A = [a / np.linalg.norm(a, axis=0) for a in A]
+    QR = [O.householder_qr(a) for a in A]
+    return A, [q for q, _ in QR], [rr for _, rr in QR]
+
+
+@pytest.mark.parametrize("N,dims", [(3, (5, 6, 4)), (4, (4, 3, 5, 4))])
+def test_P_equals_kron_Q_times_Q0_R0_eq11(N, dims):
+    A, Qs, Rs = _state(N, dims, 3)
+    for n in range(N):
+        P = O.khatri_rao([A[k] for k in reversed(range(N)) if k != n])
+        Z = O.khatri_rao([Rs[k] for k in reversed(range(N)) if k != n])
+        Q0, R0 = O.householder_qr(Z)
+        K = None
+        for k in reversed(range(N)):
+            if k != n:
+                K = Qs[k] if K is None else np.kron(K, Qs[k])
+        assert np.allclose(P, K @ Q0 @ R0, atol=1e-13)
+        W = K @ Q0
+        assert np.linalg.norm(W.T @ W - np.eye(3)) < 1e-13
+
+
+@pytest.mark.parametrize("N,R", [(3, 4), (4, 3), (5, 3)])
+def test_Q0_first_row_and_column_structure(N, R):
+    """Section 3.2: Q0(1,1) = 1, the rest of row 1 and column 1 vanish; and
+    column r of Q0 lives on rows whose indices are all <= r."""
+    dims = [6, 5, 7, 4, 5][:N]
+    A, Qs, Rs = _state(N, dims, R, seed=20 + N)
+    for n in range(N):
+        Z = O.khatri_rao([Rs[k] for k in reversed(range(N)) if k != n])
+        Q0, R0 = O.householder_qr(Z)
+        assert Q0[0, 0] == 1.0
+        assert np.all(Q0[0, 1:] == 0.0) and np.all(Q0[1:, 0] == 0.0)
+        idx = np.array(list(itertools.product(*[range(R)] * (N - 1))))[:, ::-1]
+        rowmax = idx.max(axis=1)             # rows in Kolda order
+        for c in range(R):
+            assert np.all(Q0[rowmax > c, c] == 0.0)
+        # R0^T R0 equals the Hadamard product of the other Gram matrices
+        G_ = np.ones((R, R))
+        for k in range(N):
+            if k != n:
+                G_ *= A[k].T @ A[k]
+        assert np.allclose(R0.T @ R0, G_, atol=1e-12)
+
+
+def test_mode_update_solves_least_squares_eq6():
+    """With beta = 0 the update is the minimiser of ||X_(n) - Ahat P^T||."""
+    r = rng(30)
+    dims, R = (6, 5, 7), 3
+    X = r.standard_normal(dims)
+    A, Qs, Rs = _state(3, dims, R, seed=31)
+    for n in range(3):
+        Yn = O.unfold(O.multi_ttm_except(X, Qs, n), n)
+        An, lam, Q0, R0, Vp, Vu = O.mode_update(Yn, Rs, n, None, 0.0, 0.1)
+        P = O.khatri_rao([A[k] for k in reversed(range(3)) if k != n])
+        sol = np.linalg.lstsq(P, O.unfold(X, n).T, rcond=None)[0].T
+        assert np.allclose(An * lam, sol, atol=1e-11)
+        # well-conditioned: also the normal-equation update of Algorithm 1
+        Gam = np.ones((R, R))
+        for k in range(3):
+            if k != n:
+                Gam *= A[k].T @ A[k]
+        ne = np.linalg.solve(Gam.T, (O.unfold(X, n) @ P).T).T
+        assert np.allclose(An * lam, ne, atol=1e-9)
+
+
+def test_cheap_fit_matches_explicit_fit():
+    p = G.make_problem([9, 8, 7], 3, seed=40, rho=0.05)
+    res = O.cp_als_qr(p.X, 3, p.init, iters=6, explicit_every_sweep=True)
+    assert np.allclose(res["fits"], res["fitxs"], atol=1e-12)
+
+
+def test_fit_with_extrapolation_uses_plain_and_extrapolated_V():
+    """<X,K> = <Vp,Vu>, ||K||^2 = ||Vu||^2 matches the explicit residual; the
+    formula that uses Vu for both terms does not."""
+    p = G.make_problem([9, 8, 7], 3, seed=41, rho=0.05)
+    res = O.cp_als_qr(p.X, 3, p.init, iters=5, fix_beta=0.05, explicit_every_sweep=True)
+    assert np.allclose(res["fits"][1:], res["fitxs"][1:], atol=1e-12)
+    X = np.asarray(p.X, np.float64)
+    A, Qs, Rs = _state(3, (9, 8, 7), 3, seed=42)
+    Yn = O.unfold(O.multi_ttm_except(X, Qs, 2), 2)
+    Q0prev = O.householder_qr(O.khatri_rao([Rs[1], Rs[0]]) + 0.01)[0]
+    An, lam, Q0, R0, Vp, Vu = O.mode_update(Yn, Rs, 2, Q0prev, 0.05, 0.1)
+    facs = [A[0], A[1], An]
+    fx = O.explicit_fit(X, lam, facs)
+    nx2 = O.sum_squares(X)
+    assert abs(O.cheap_fit(nx2, Vp, Vu) - fx) < 1e-12
+    assert abs(O.cheap_fit(nx2, Vu, Vu) - fx) > 1e-6
+
+
+def test_beta_zero_is_bitwise_BR():
+    p = G.make_problem([8, 9, 10], 3, seed=43, rho=0.02)
+    a = O.cp_als_qr(p.X, 3, p.init, iters=6, tree="restructured", extrap="off")
+    b = O.cp_als_qr(p.X, 3, p.init, iters=6, tree="restructured", fix_beta=0.0)
+    for x, y in zip(a["factors"], b["factors"]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a["fits"], b["fits"])
+
+
+def test_classical_extrapolation_keeps_first_row_and_column():
+    """eq. (18) (alpha = 1) keeps Q0's first row/column; eq. (19) scales the
+    (1,1) entry to 1 + beta (1 - alpha) and keeps the zeros."""
+    A, Qs, Rs = _state(3, (5, 6, 4), 3, seed=44)
+    Z1 = O.khatri_rao([Rs[2], Rs[1]])
+    A2 = [a + 0.1 * rng(45).standard_normal(a.shape) for a in A]
+    Rs2 = [O.householder_qr(a / np.linalg.norm(a, axis=0))[1] for a in A2]
+    Q0a = O.householder_qr(Z1)[0]
+    Q0b = O.householder_qr(O.khatri_rao([Rs2[2], Rs2[1]]))[0]
+    beta = 0.3
+    classical = Q0b + beta * (Q0b - Q0a)
+    assert classical[0, 0] == 1.0 and np.all(classical[0, 1:] == 0) and np.all(classical[1:, 0] == 0)
+    custom = Q0b + beta * (Q0b - 0.1 * Q0a)
+    assert abs(custom[0, 0] - (1 + beta * 0.9)) < 1e-15
+    assert np.all(custom[0, 1:] == 0) and np.all(custom[1:, 0] == 0)
+
+
+@pytest.mark.parametrize("fit,beta", [(0.99, 1 / 20000), (0.9500001, 1 / 20000), (0.95, 1 / 2000),
+                                      (0.91, 1 / 2000), (0.90, 1 / 500), (0.7000001, 1 / 500),
+                                      (0.70, 1 / 250), (0.3, 1 / 250)])
+def test_beta_table(fit, beta):
+    assert O.beta_from_fit(fit) == beta
+
+
+def test_extrapolation_activation_rule():
+    p = G.make_problem([10, 11, 12], 3, seed=46, congruence=0.5, rho=0.05)
+    res = O.cp_als_qr(p.X, 3, p.init, iters=25, tree="restructured", extrap="paper")
+    f = res["fits"]
+    k = res["beta_sweep"]
+    assert k >= 2
+    assert abs(f[k - 1] - f[k - 2]) < 0.03
+    for j in range(2, k):
+        assert abs(f[j - 1] - f[j - 2]) >= 0.03
+    assert res["beta"] == O.beta_from_fit(f[k - 1])
+
+
+# ------------------------------------------------------- whole-method pins
+def test_planted_noiseless_recovery():
+    p = G.make_problem([12, 13, 14], 3, seed=50, rho=0.0)
+    res = O.cp_als_qr(p.X, 3, p.init, iters=150)
+    assert 1.0 - res["fitx"] < 1e-10
+    # components match the planted ones up to permutation and sign
+    for n in range(3):
+        C = np.abs(res["factors"][n].T @ (p.truth[n] / np.linalg.norm(p.truth[n], axis=0)))
+        assert np.all(C.max(axis=1) > 1 - 1e-8)
+    for q in res["Q"]:
+        assert np.linalg.norm(q.T @ q - np.eye(3)) < 1e-13
+
+
+def test_noisy_fit_matches_first_order_closed_form():
+    dims, R, rho = [30, 30, 30], 3, 0.05
+    p = G.make_problem(dims, R, seed=51, rho=rho)
+    res = O.cp_als_qr(p.X, R, p.init, iters=200, tol=1e-13)
+    X = p.X
+    X0 = G.tensor_from_factors(p.truth)
+    rho_eff = np.linalg.norm((X - X0).ravel()) / np.linalg.norm(X.ravel())
+    M = np.prod(dims)
+    d = R * (sum(dims) - len(dims) + 1)
+    pred = 1 - rho_eff * math.sqrt(1 - d / M)
+    assert abs(res["fitx"] - pred) < 3e-4
+
+
+def test_generator_congruence_and_noise_level():
+    r = np.random.default_rng(52)
+    B = G.congruent_factors(r, [50, 60], 5, 0.9)
+    K = 0.1 * np.eye(5) + 0.9
+    for b in B:
+        assert np.allclose(b.T @ b, K, atol=1e-14)
+    p = G.make_problem([10, 12, 9], 4, seed=53, rho=0.01)
+    X0 = G.tensor_from_factors(p.truth)
+    ratio = np.linalg.norm((p.X - X0).ravel()) / np.linalg.norm(X0.ravel())
+    assert abs(ratio - 0.01) < 1e-14
+    assert abs(G.rho_from_l1(50.0) - 1.0) < 1e-15
