@@ -1,0 +1,188 @@
+/*
+ * cpqr.h -- C ABI of the MI355X (gfx950) CP-ALS-QR library (libcpqr.so).
+ *
+ * The library computes a rank-R CP decomposition of a dense order-N tensor
+ * with the QR-based alternating least squares of arXiv 2503.18759:
+ * Algorithm 2 (CP-ALS-QR) and Algorithm 3 (ALS-QR-BRE), with the TTM chain
+ * organised by no tree, the standard dimension tree, or the restructured
+ * dimension tree of Section 3.1, and the customised Q0 extrapolation of
+ * eq. (19).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a cpqr_status: 0 on success, a negative code on
+ *    failure.  No C++ exception crosses the ABI.
+ *  - Dense tensors are column-major with mode 1 fastest: element
+ *    (i_1, ..., i_N) sits at i_1 + I_1 (i_2 + I_2 (i_3 + ...)), the
+ *    unfolding convention of Section 2.1.  Matrices are column-major.
+ *  - "device" pointers are HIP device allocations (for example torch CUDA
+ *    tensors on ROCm); "host" pointers are ordinary CPU memory.
+ *  - Validation of sizes and pointers happens before any device work; on a
+ *    validation error nothing is launched and outputs are untouched.
+ *  - A handle is bound to one device and one HIP stream.  Calls on a handle
+ *    are synchronous with respect to the host (they return after results
+ *    are copied out) and must not be made concurrently from several threads.
+ */
+#ifndef CPQR_H
+#define CPQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPQR_OK = 0,
+  CPQR_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad enum) */
+  CPQR_EUNSUPPORTED = -2, /* valid but outside what this build handles (see limits) */
+  CPQR_ENOMEM = -3,       /* device allocation failed */
+  CPQR_EHIP = -4,         /* a HIP runtime call failed; see cpqr_last_error */
+  CPQR_ERANKDEF = -5,     /* a column norm (lambda_r) or a diagonal of R0 / R_n is zero */
+  CPQR_ENONFINITE = -6    /* a NaN or Inf appeared in the fit or in lambda */
+} cpqr_status;
+
+/* TTM organisation (Section 3.1 / 3.4).  NONE contracts each leaf directly
+ * from X; STANDARD is the dimension tree of Figure 1 / Tables 1 and 4;
+ * RESTRUCTURED is the restructured dimension tree (Tables 2 and 5), which
+ * also permutes the per-sweep update order. */
+typedef enum { CPQR_TREE_NONE = 0, CPQR_TREE_STANDARD = 1, CPQR_TREE_RESTRUCTURED = 2 } cpqr_tree;
+
+/* Q0 extrapolation (Section 3.2, eq. (19), Algorithm 3).  OFF is beta = 0
+ * (ALS-QR-BR); PAPER activates beta once the fit change drops below
+ * switch_delta and picks it from the fit level (Section 4.3). */
+typedef enum { CPQR_EXTRAP_OFF = 0, CPQR_EXTRAP_PAPER = 1 } cpqr_extrap;
+
+/* Arithmetic of the TTM chain.  FP64 needs a float64 tensor; FP32 and
+ * BF16X3 need a float32 tensor.  BF16X3 computes each TTM product as
+ * x_hi q_hi + x_hi q_lo + x_lo q_hi on bf16 matrix cores with float32
+ * accumulation.  The QRs, the triangular solves, Y_(n) Q0 and the fit are
+ * float64 in every mode. */
+typedef enum { CPQR_PREC_FP64 = 0, CPQR_PREC_FP32 = 1, CPQR_PREC_BF16X3 = 2 } cpqr_prec;
+
+typedef enum { CPQR_DTYPE_F64 = 0, CPQR_DTYPE_F32 = 1 } cpqr_dtype;
+
+/* Option flags. */
+#define CPQR_FLAG_EXPLICIT_FIT 0x1u  /* also compute 1 - ||X - K|| / ||X|| explicitly at the end */
+#define CPQR_FLAG_TIME_KERNELS 0x2u  /* time every level-1 TTM (the TTM that reads X) with HIP events */
+#define CPQR_FLAG_NO_GRAPH     0x4u  /* launch kernels one by one instead of replaying HIP graphs */
+
+typedef struct cpqr_handle cpqr_handle;
+
+/* Create a handle on `device` that launches on `hip_stream` (a hipStream_t;
+ * NULL = the default stream).  The handle owns all device workspace, which
+ * is allocated on first use, grown on demand and freed by cpqr_destroy. */
+cpqr_status cpqr_create(cpqr_handle **handle, int device, void *hip_stream);
+cpqr_status cpqr_destroy(cpqr_handle *handle);
+
+/* Message describing the last error on this handle ("" if none).  The
+ * string is owned by the handle. */
+const char *cpqr_last_error(const cpqr_handle *handle);
+/* Static name of a status code. */
+const char *cpqr_status_string(int status);
+
+typedef struct {
+  int order;            /* 3 <= N <= 7 (N = 2 is accepted with CPQR_TREE_NONE) */
+  const int64_t *dims;  /* host, N mode sizes I_1..I_N, each >= 1 */
+  int dtype;            /* cpqr_dtype */
+  const void *data;     /* device, prod(dims) elements, column-major (mode 1 fastest) */
+} cpqr_tensor;
+
+typedef struct {
+  int tree;             /* cpqr_tree */
+  int extrapolate;      /* cpqr_extrap */
+  int prec;             /* cpqr_prec */
+  int iters;            /* number of sweeps m (Algorithm 2/3 input), >= 1 */
+  double tol;           /* stop when |fit_k - fit_{k-1}| < tol; 0 = run all sweeps */
+  double alpha;         /* eq. (19) alpha; the paper uses 0.1 */
+  double switch_delta;  /* activation threshold on the fit change; the paper uses 0.03 */
+  double fixed_beta;    /* if > 0 with CPQR_EXTRAP_PAPER: use this beta from sweep 2 on instead of the rule */
+  const double *const *init_factors; /* host, N pointers to I_n x R column-major float64 initial factors */
+  unsigned flags;       /* CPQR_FLAG_* */
+} cpqr_options;
+
+typedef struct {
+  double *const *factors;  /* host, N caller-owned I_n x R float64 outputs (unit-norm columns), or NULL */
+  double *lambda;          /* host, R weights, or NULL */
+  double *fit_history;     /* host, `iters` per-sweep fits (Section 4.1 formula), or NULL */
+  int *sweep_orders;       /* host, iters x N 0-based update orders, or NULL */
+  double fit;              /* fit after the last sweep (Section 4.1 formula) */
+  double fit_explicit;     /* explicit 1 - ||X-K||/||X|| if CPQR_FLAG_EXPLICIT_FIT, else NaN */
+  int sweeps_done;
+  double beta;             /* extrapolation weight in force at the end (0 if never active) */
+  int beta_sweep;          /* sweep after which beta was activated (0 if never) */
+  double ttm_flops;        /* TTM flops executed (2 |input| R per TTM) */
+  double ttm_bytes;        /* TTM algorithmic bytes (input read once + output written once) */
+  double seconds;          /* device wall time of the sweep loop */
+  double l1_ttm_seconds;   /* with CPQR_FLAG_TIME_KERNELS: summed duration of the level-1 TTMs */
+  int l1_ttm_launches;     /* number of level-1 TTMs timed */
+  double l1_ttm_bytes;     /* algorithmic bytes of one level-1 TTM per launch (averaged) */
+  double l1_ttm_flops;     /* flops of one level-1 TTM per launch (averaged) */
+} cpqr_result;
+
+/*
+ * cpqr_als_qr -- CP-ALS-QR / ALS-QR-BR / ALS-QR-BRE (Algorithms 2 and 3).
+ * Inputs: tensor X (device), rank R, options (iteration count, stopping
+ * tolerance, tree, extrapolation, precision, initial factors).  Outputs
+ * (host, caller-owned): factor matrices with unit-norm columns, lambda, the
+ * per-sweep fit history and update orders, and the final fit.
+ * Limits of this build: 1 <= R <= 32, R <= I_n <= 512 for every mode
+ * (I_n < R returns CPQR_EUNSUPPORTED), R^(N-1) <= 2^20.
+ * On a runtime error (CPQR_ERANKDEF, CPQR_ENONFINITE, CPQR_EHIP) the outputs
+ * are untouched except sweeps_done and fit_history up to the failure.
+ */
+cpqr_status cpqr_als_qr(cpqr_handle *handle, const cpqr_tensor *X, int rank,
+                        const cpqr_options *opts, cpqr_result *result);
+
+/*
+ * cpqr_check_args -- host-only: the argument checks that cpqr_als_qr makes
+ * before any device work (pointers, sizes, enums, precision/dtype match and
+ * the limits of this build).  Returns the status cpqr_als_qr would return
+ * for these arguments before launching anything; needs no device.
+ */
+cpqr_status cpqr_check_args(const cpqr_tensor *X, int rank, const cpqr_options *opts);
+
+/*
+ * cpqr_schedule -- host-only: the TTM schedule of `sweeps` sweeps of an
+ * order-`order` problem for `tree` (Section 3.1, Tables 1-6).
+ *  orders_out : host, sweeps x order ints (0-based mode update order), or NULL.
+ *  steps_out  : host, up to max_steps x 3 ints per step: {kind, src_mask, mode}
+ *               kind 0 = TTM contracting `mode` of Y{src_mask} (src_mask is
+ *               the bitmask of free modes; all bits set = X), kind 1 = mode
+ *               update consuming the leaf Y{mode}.  May be NULL.
+ *  n_steps    : host, receives the total number of steps.
+ *  flops_out  : host, 2^order x order doubles or NULL: coefficient of the
+ *               monomial prod_{k in mask} I_k * R^(order-|mask|+1) at index
+ *               mask * order + 0 summed over all sweeps (other entries 0).
+ * Returns CPQR_EINVAL for order < 2 or > 8, bad tree, sweeps < 1, or when
+ * max_steps is too small for steps_out.
+ */
+cpqr_status cpqr_schedule(int order, int tree, int sweeps, int *orders_out,
+                          int *steps_out, int max_steps, int *n_steps,
+                          double *flops_out);
+
+/*
+ * cpqr_ttm -- one mode-m product Y = X x_m Q^T (Section 2.1): the tensor
+ * `in` (device, dims[0..order-1], column-major) is contracted on mode `mode`
+ * (0-based) with Q (device, dims[mode] x R column-major, same precision as
+ * the TTM: float64 for FP64, float32 for FP32; for BF16X3 `q` is float32 and
+ * is split on the device).  `out` (device) receives the tensor with
+ * dims[mode] replaced by R.  in/out element type: float64 for FP64, float32
+ * otherwise.  Limits: 1 <= R <= 64, dims[mode] * roundup(R,16) * 4 <= 64 KiB.
+ */
+cpqr_status cpqr_ttm(cpqr_handle *handle, int prec, int order, const int64_t *dims,
+                     int mode, int rank, const void *in, const void *q, void *out);
+
+/*
+ * cpqr_qr -- compact Householder QR of an M x R float64 matrix held on the
+ * device (column-major): A = Q R with Q (device, M x R, orthonormal
+ * columns) and R (device, R x R, upper triangular, non-negative diagonal).
+ * Limits: 1 <= R <= 32, R <= M <= 2^20.
+ */
+cpqr_status cpqr_qr(cpqr_handle *handle, int64_t M, int R, const double *A,
+                    double *Q, double *Rout);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPQR_H */

@@ -1,0 +1,8 @@
+"""MI355X (gfx950) CP-ALS-QR: QR-based CP decomposition with the restructured
+dimension tree and customised Q0 extrapolation of arXiv 2503.18759.
+
+The compute path is libcpqr.so (hand-written HIP kernels behind a C ABI,
+``include/cpqr.h``); :mod:`paper_2503_18759_amd.cpqr` is its ctypes binding.
+"""
+from .cpqr import (CpqrError, Handle, check_args, cp_als_qr, default_handle,  # noqa: F401
+                   load_library, qr, schedule, to_device, ttm)

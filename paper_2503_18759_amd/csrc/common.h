@@ -1,0 +1,113 @@
+// Shared device helpers for the gfx950 CP-ALS-QR kernels: vector types, MFMA
+// operand types, wave-level reductions and error checking.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CPQR_WAVE 64
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace cpqr {
+
+// ---------------------------------------------------------------------------
+// Wave-level "transpose" reduction of V doubles (V a power of two, <= 32).
+//
+// On entry lane L holds a[0..V).  On exit a[0] of lane L holds the sum over
+// all 64 lanes of value index  L / (64 / V).  Each halving step pairs lanes
+// that differ in one lane-index bit: the lane with the bit set keeps the
+// upper half of its values, the other the lower half, and both add the
+// partner's copy of the half they keep.  Steps over bits 5 and 4 use the
+// gfx950 cross-row swap instructions (v_permlane32_swap / v_permlane16_swap);
+// the remaining bits use ds_bpermute shuffles.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void swap32_add(double& x, double& y) {
+  // lanes 0-31 end with x(L) + x(L+32); lanes 32-63 with y(L-32) + y(L)
+  unsigned xl = __double2loint(x), xh = __double2hiint(x);
+  unsigned yl = __double2loint(y), yh = __double2hiint(y);
+  auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+  auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+  double a = __hiloint2double((int)hi[0], (int)lo[0]);
+  double b = __hiloint2double((int)hi[1], (int)lo[1]);
+  x = a + b;
+}
+
+__device__ __forceinline__ void swap16_add(double& x, double& y) {
+  // rows (16 lanes) 0 and 2 end with x summed over rows {0,1} / {2,3};
+  // rows 1 and 3 with y summed likewise
+  unsigned xl = __double2loint(x), xh = __double2hiint(x);
+  unsigned yl = __double2loint(y), yh = __double2hiint(y);
+  auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+  auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+  double a = __hiloint2double((int)hi[0], (int)lo[0]);
+  double b = __hiloint2double((int)hi[1], (int)lo[1]);
+  x = a + b;
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  return __shfl_xor(v, m, CPQR_WAVE);
+}
+
+template <int V>
+__device__ __forceinline__ void wave_transpose_reduce(double (&a)[V]) {
+  static_assert(V >= 1 && V <= 32 && (V & (V - 1)) == 0, "V must be a power of two <= 32");
+  const int lane = threadIdx.x & 63;
+  int count = V;
+  // bit 5 (lanes 32-63 keep the upper half)
+  if (count >= 2) {
+#pragma unroll
+    for (int q = 0; q < V / 2; ++q) swap32_add(a[q], a[q + V / 2]);
+    count = V / 2;
+  } else {
+    a[0] += shfl_xor_d(a[0], 32);
+  }
+  // bit 4
+  if (V >= 4) {
+#pragma unroll
+    for (int q = 0; q < V / 4; ++q) swap16_add(a[q], a[q + V / 4]);
+    count = V / 4;
+  } else {
+    a[0] += shfl_xor_d(a[0], 16);
+  }
+  // bits 3..0
+#pragma unroll
+  for (int bit = 3; bit >= 0; --bit) {
+    const int m = 1 << bit;
+    const int half = V >> (6 - bit);   // values kept per lane after this step
+    if (half >= 1) {
+      const bool upper = (lane & m) != 0;
+#pragma unroll
+      for (int q = 0; q < half; ++q) {
+        double keep = upper ? a[q + half] : a[q];
+        double send = upper ? a[q] : a[q + half];
+        a[q] = keep + shfl_xor_d(send, m);
+      }
+    } else {
+      a[0] += shfl_xor_d(a[0], m);
+    }
+  }
+  (void)count;
+}
+
+// Plain all-lanes sum of one double over the wave.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, CPQR_WAVE);
+  return v;
+}
+
+// Round-to-nearest-even split of a float into bf16 hi + bf16 lo.
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+}  // namespace cpqr

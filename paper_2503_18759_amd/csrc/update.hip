@@ -1,0 +1,401 @@
+// Mode-update kernels of QR-based ALS (Algorithm 2 lines 6-9, Algorithm 3
+// lines 5 and 7-10) and the norm kernels of the fit (Section 4.1).
+//
+//  * apply_partial / apply_reduce:  [Vp | Vq] = Y_(n) [Q0 | Q0prev] in float64
+//    (Y_(n) columns in the Kolda order of the remaining modes, i.e. column
+//    l + L s of the leaf stored as [L, I_n, S]).  The K = R^(N-1) reduction is
+//    split over workgroups and the partial products are summed in a second
+//    pass in a fixed order.
+//  * finish_update: one workgroup per mode update.  Vu = (1+beta) Vp - alpha beta Vq
+//    (eq. 19 applied through V = Y_(n) Qhat0), <Vp,Vu> and ||Vu||^2 for the
+//    fit, back substitution of Ahat R0^T = Vu, lambda = column norms,
+//    A = Ahat / lambda, Householder QR of A -> Q_n, R_n; after the last update
+//    of a sweep the fit and the extrapolation activation rule.
+//  * sumsq / residual: ||X||^2 and ||X - K||^2 with float64 accumulation.
+#include "common.h"
+#include "kernels.h"
+#include "qr_device.h"
+
+namespace cpqr {
+
+static constexpr int AP_THREADS = 256;
+static constexpr int AP_ROWS = 64;
+static constexpr int AP_KT = 32;
+
+template <typename TY, int RMAX>
+__global__ __launch_bounds__(AP_THREADS) void apply_partial(
+    const TY* __restrict__ Y, int64_t L, int I, int64_t S, int R, const double* __restrict__ Q0,
+    const double* __restrict__ Q0prev, double* __restrict__ partial, int64_t chunk,
+    const DevState* __restrict__ st) {
+  __shared__ double sY[AP_KT][AP_ROWS + 1];
+  __shared__ double sQ[AP_KT][RMAX];
+  __shared__ double sP[AP_KT][RMAX];
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * AP_ROWS;
+  const int64_t M = L * S;
+  const int64_t k0 = (int64_t)blockIdx.y * chunk;
+  int64_t k1 = k0 + chunk;
+  if (k1 > M) k1 = M;
+  const bool use_prev = (Q0prev != nullptr) && st->active;
+  const int i = tid & 63, rg = tid >> 6;
+  constexpr int U = RMAX / 4;
+  double ap[U], aq[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) ap[u] = aq[u] = 0.0;
+  const int64_t LI = L * (int64_t)I;
+  for (int64_t kt = k0; kt < k1; kt += AP_KT) {
+    for (int e = tid; e < AP_ROWS * AP_KT; e += AP_THREADS) {
+      int ii, kk;
+      if (L == 1) { ii = e & 63; kk = e >> 6; }
+      else        { kk = e % AP_KT; ii = e / AP_KT; }
+      const int64_t k = kt + kk;
+      double y = 0.0;
+      if (i0 + ii < I && k < k1) {
+        const int64_t s = k / L, l = k - s * L;
+        y = (double)Y[l + L * (int64_t)(i0 + ii) + LI * s];
+      }
+      sY[kk][ii] = y;
+    }
+    for (int e = tid; e < AP_KT * RMAX; e += AP_THREADS) {
+      const int kk = e % AP_KT, c = e / AP_KT;
+      const int64_t k = kt + kk;
+      const bool in = (k < k1) && (c < R);
+      sQ[kk][c] = in ? Q0[k + M * c] : 0.0;
+      sP[kk][c] = (in && use_prev) ? Q0prev[k + M * c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < AP_KT; ++kk) {
+      const double y = sY[kk][i];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ap[u] = fma(y, sQ[kk][rg + 4 * u], ap[u]);
+        aq[u] = fma(y, sP[kk][rg + 4 * u], aq[u]);
+      }
+    }
+    __syncthreads();
+  }
+  if (i0 + i < I) {
+    double* out = partial + (int64_t)blockIdx.y * 2 * I * R;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = rg + 4 * u;
+      if (c < R) {
+        out[(i0 + i) + (int64_t)I * c] = ap[u];
+        out[(int64_t)I * R + (i0 + i) + (int64_t)I * c] = aq[u];
+      }
+    }
+  }
+}
+
+__global__ void apply_reduce(const double* __restrict__ partial, int nchunks, int64_t n,
+                             double* __restrict__ V) {
+  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * n + o];
+    V[o] = s;
+  }
+}
+
+int apply_num_chunks(int64_t M, int I) {
+  const int iblocks = (I + AP_ROWS - 1) / AP_ROWS;
+  int64_t want = (256 + iblocks - 1) / iblocks;            // about one workgroup per CU
+  int64_t maxc = (M + AP_KT - 1) / AP_KT;                   // at least one k-tile each
+  if (want > maxc) want = maxc;
+  if (want < 1) want = 1;
+  // chunk length must be a multiple of the k-tile
+  int64_t chunk = (M + want - 1) / want;
+  chunk = ((chunk + AP_KT - 1) / AP_KT) * AP_KT;
+  return (int)((M + chunk - 1) / chunk);
+}
+
+hipError_t launch_apply(const ApplyArgs& a, hipStream_t st) {
+  const int64_t M = a.L * a.S;
+  int64_t chunk = (M + a.nchunks - 1) / a.nchunks;
+  chunk = ((chunk + AP_KT - 1) / AP_KT) * AP_KT;
+  dim3 grid((a.I + AP_ROWS - 1) / AP_ROWS, a.nchunks);
+  const int rm = qr_rmax(a.R);
+#define CPQR_APPLY(RM)                                                                            \
+  if (a.y_f64)                                                                                    \
+    hipLaunchKernelGGL((apply_partial<double, RM>), grid, dim3(AP_THREADS), 0, st,                \
+                       (const double*)a.Y, a.L, a.I, a.S, a.R, a.Q0, a.Q0prev, a.partial, chunk, a.state); \
+  else                                                                                            \
+    hipLaunchKernelGGL((apply_partial<float, RM>), grid, dim3(AP_THREADS), 0, st,                 \
+                       (const float*)a.Y, a.L, a.I, a.S, a.R, a.Q0, a.Q0prev, a.partial, chunk, a.state);
+  if (rm == 8) { CPQR_APPLY(8) }
+  else if (rm == 16) { CPQR_APPLY(16) }
+  else if (rm == 32) { CPQR_APPLY(32) }
+  else return hipErrorInvalidValue;
+#undef CPQR_APPLY
+  const int64_t n = 2 * (int64_t)a.I * a.R;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(apply_reduce, dim3((unsigned)blocks), dim3(256), 0, st, a.partial, a.nchunks, n, a.V);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ finish
+__device__ inline double beta_from_fit(double fit) {
+  // Section 4.3: fit > 0.95 -> 1/20000; (0.90, 0.95] -> 1/2000;
+  // (0.70, 0.90] -> 1/500; otherwise 1/250
+  if (fit > 0.95) return 1.0 / 20000.0;
+  if (fit > 0.90) return 1.0 / 2000.0;
+  if (fit > 0.70) return 1.0 / 500.0;
+  return 1.0 / 250.0;
+}
+
+template <int RMAX, int RPT>
+__global__ __launch_bounds__(QR_THREADS) void finish_update(FinishArgs f) {
+  __shared__ QrSmem<RMAX> sm;
+  __shared__ QrWySmem<RMAX> wy;
+  __shared__ double sR0[RMAX][RMAX + 1];
+  __shared__ double sred2[QR_WAVES][2];
+  __shared__ double sredR[QR_WAVES][RMAX];
+  const int tid = threadIdx.x;
+  const int I = f.I, R = f.R;
+  DevState* st = f.state;
+  for (int e = tid; e < RMAX * RMAX; e += QR_THREADS) {
+    const int i = e / RMAX, c = e % RMAX;
+    sR0[i][c] = (i < R && c < R) ? f.R0[i + R * c] : 0.0;
+  }
+  const bool active = (f.extrap != 0) && st->active;
+  const double beta = active ? st->beta : 0.0;
+  const double cp = 1.0 + beta, cq = -f.alpha * beta;
+  __syncthreads();
+
+  int bad = 0;
+  for (int c = 0; c < R; ++c)
+    if (!(sR0[c][c] != 0.0)) bad |= FLAG_RANKDEF;   // singular Z_n (dependent R factors)
+  double a[RPT][RMAX];
+  double sc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < RPT; ++p) {
+    const int row = tid + QR_THREADS * p;
+    double vu[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+      double vp = 0.0, vq = 0.0;
+      if (row < I && c < R) {
+        vp = f.V[row + (int64_t)I * c];
+        vq = f.V[(int64_t)I * R + row + (int64_t)I * c];
+      }
+      vu[c] = active ? fma(cq, vq, cp * vp) : vp;
+      sc[0] = fma(vp, vu[c], sc[0]);
+      sc[1] = fma(vu[c], vu[c], sc[1]);
+    }
+    // back substitution of R0 ahat = vu (row of Ahat R0^T = Vu)
+#pragma unroll
+    for (int c = RMAX - 1; c >= 0; --c) {
+      double s = vu[c];
+#pragma unroll
+      for (int d = c + 1; d < RMAX; ++d) s = fma(-sR0[c][d], a[p][d], s);
+      a[p][c] = (c < R && row < I && sR0[c][c] != 0.0) ? s / sR0[c][c] : 0.0;
+    }
+  }
+  block_allreduce<2>(sc, sred2);
+  // lambda = column norms of Ahat
+  double cn[RMAX];
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) {
+    double s = 0.0;
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) s = fma(a[p][c], a[p][c], s);
+    cn[c] = s;
+  }
+  block_allreduce<RMAX>(cn, sredR);
+  double inv[RMAX];
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) {
+    const double lam = sqrt(cn[c]);
+    if (c < R) {
+      if (lam == 0.0) bad |= FLAG_RANKDEF;
+      if (!isfinite(lam)) bad |= FLAG_NONFINITE;
+    }
+    inv[c] = (c < R && lam != 0.0) ? 1.0 / lam : 0.0;
+    if (tid == 0 && c < R) f.lambda[c] = lam;
+  }
+#pragma unroll
+  for (int p = 0; p < RPT; ++p) {
+    const int row = tid + QR_THREADS * p;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+      a[p][c] *= inv[c];
+      if (row < I && c < R) f.A[row + (int64_t)I * c] = a[p][c];
+    }
+  }
+  block_qr<RMAX, RPT>(a, R, sm);
+  block_qr_publish<RMAX, RPT>(a, R, sm, wy, true);
+  block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
+  for (int e = tid; e < R * R; e += QR_THREADS) {
+    const int i = e % R, c = e / R;
+    f.Rn[e] = wy.Rm[i][c];
+  }
+#pragma unroll
+  for (int p = 0; p < RPT; ++p) {
+    const int row = tid + QR_THREADS * p;
+    double qq[RMAX];
+    block_qr_q_row<RMAX, RPT>(a, p, R, sm, wy, qq);
+    if (row < I) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) {
+        if (c < R) {
+          if (f.q64) f.q64[row + (int64_t)I * c] = qq[c];
+          if (f.q32) f.q32[row + (int64_t)I * c] = (float)qq[c];
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    if (!isfinite(sc[0]) || !isfinite(sc[1])) bad |= FLAG_NONFINITE;
+    for (int c = 0; c < R; ++c)
+      if (!(wy.Rm[c][c] > 0.0)) bad |= FLAG_RANKDEF;
+    if (bad) atomicOr(&st->flags, bad);
+    st->vpvu = sc[0];
+    st->vuvu = sc[1];
+    if (f.last_in_sweep) {
+      const double res2 = st->nx2 - 2.0 * sc[0] + sc[1];
+      const double fit = 1.0 - sqrt(res2 > 0.0 ? res2 : 0.0) / sqrt(st->nx2);
+      const int k0 = st->sweep;
+      f.fit_hist[k0] = fit;
+      if (!isfinite(fit)) atomicOr(&st->flags, FLAG_NONFINITE);
+      if (f.extrap != 0 && !st->active) {
+        if (f.fixed_beta > 0.0) {
+          if (k0 == 0) {
+            st->active = 1;
+            st->beta = f.fixed_beta;
+            st->beta_sweep = 1;
+          }
+        } else if (k0 >= 1 && fabs(fit - f.fit_hist[k0 - 1]) < f.delta) {
+          st->active = 1;
+          st->beta = beta_from_fit(fit);
+          st->beta_sweep = k0 + 1;
+        }
+      }
+      st->fit = fit;
+      st->sweep = k0 + 1;
+    }
+  }
+}
+
+hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
+  const int rm = qr_rmax(f.R);
+  if (rm == 8) hipLaunchKernelGGL((finish_update<8, 8>), dim3(1), dim3(QR_THREADS), 0, st, f);
+  else if (rm == 16) hipLaunchKernelGGL((finish_update<16, 4>), dim3(1), dim3(QR_THREADS), 0, st, f);
+  else if (rm == 32) hipLaunchKernelGGL((finish_update<32, 2>), dim3(1), dim3(QR_THREADS), 0, st, f);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- norms
+static constexpr int NORM_BLOCKS = 1024;
+static constexpr int NORM_THREADS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(NORM_THREADS) void sumsq_kernel(const T* __restrict__ x, int64_t n,
+                                                             double* __restrict__ part) {
+  __shared__ double red[NORM_THREADS / 64];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * NORM_THREADS) {
+    const double v = (double)x[i];
+    s = fma(v, v, s);
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NORM_THREADS / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+int sumsq_blocks(int64_t n) {
+  int64_t b = (n + NORM_THREADS - 1) / NORM_THREADS;
+  return (int)(b < NORM_BLOCKS ? (b < 1 ? 1 : b) : NORM_BLOCKS);
+}
+
+hipError_t launch_sumsq(const void* x, bool f64, int64_t n, double* part, hipStream_t st) {
+  const int b = sumsq_blocks(n);
+  if (f64) hipLaunchKernelGGL(sumsq_kernel<double>, dim3(b), dim3(NORM_THREADS), 0, st, (const double*)x, n, part);
+  else     hipLaunchKernelGGL(sumsq_kernel<float>, dim3(b), dim3(NORM_THREADS), 0, st, (const float*)x, n, part);
+  return hipGetLastError();
+}
+
+__global__ void state_init_kernel(DevState* s, const double* part, int nparts) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < nparts; ++i) t += part[i];
+    s->nx2 = t;
+    s->beta = 0.0;
+    s->vpvu = 0.0;
+    s->vuvu = 0.0;
+    s->fit = 0.0;
+    s->active = 0;
+    s->beta_sweep = 0;
+    s->sweep = 0;
+    s->flags = isfinite(t) ? 0 : FLAG_NONFINITE;
+  }
+}
+
+hipError_t launch_state_init(DevState* s, const double* part, int nparts, hipStream_t st) {
+  hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, st, s, part, nparts);
+  return hipGetLastError();
+}
+
+struct FactorPtrs {
+  const double* a[CPQR_MAX_ORDER];
+  int64_t dims[CPQR_MAX_ORDER];
+};
+
+template <typename T>
+__global__ __launch_bounds__(NORM_THREADS) void residual_kernel(const T* __restrict__ x, int N,
+                                                                FactorPtrs fp, const double* __restrict__ lam,
+                                                                int R, int64_t n, double* __restrict__ part) {
+  __shared__ double red[NORM_THREADS / 64];
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * NORM_THREADS) {
+    int64_t idx[CPQR_MAX_ORDER];
+    int64_t rem = e;
+    for (int k = 0; k < N; ++k) {
+      idx[k] = rem % fp.dims[k];
+      rem /= fp.dims[k];
+    }
+    double kv = 0.0;
+    for (int r = 0; r < R; ++r) {
+      double prod = lam[r];
+      for (int k = 0; k < N; ++k) prod *= fp.a[k][idx[k] + fp.dims[k] * r];
+      kv += prod;
+    }
+    const double d = (double)x[e] - kv;
+    s = fma(d, d, s);
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NORM_THREADS / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+hipError_t launch_residual(const void* x, bool f64, int N, const int64_t* dims_host,
+                           double* const* factors, const double* lambda, int R, double* part,
+                           hipStream_t st) {
+  FactorPtrs fp;
+  int64_t n = 1;
+  for (int k = 0; k < N; ++k) {
+    fp.a[k] = factors[k];
+    fp.dims[k] = dims_host[k];
+    n *= dims_host[k];
+  }
+  const int b = sumsq_blocks(n);
+  if (f64) hipLaunchKernelGGL(residual_kernel<double>, dim3(b), dim3(NORM_THREADS), 0, st, (const double*)x, N, fp, lambda, R, n, part);
+  else     hipLaunchKernelGGL(residual_kernel<float>, dim3(b), dim3(NORM_THREADS), 0, st, (const float*)x, N, fp, lambda, R, n, part);
+  return hipGetLastError();
+}
+
+}  // namespace cpqr

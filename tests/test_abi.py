@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (no device needed): the library loads, it
+exports every function that include/cpqr.h declares, its schedule engine
+agrees with the oracle's independent schedule, and its argument checks
+return the documented status codes."""
+import os
+import re
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2503_18759_amd as P
+from paper_2503_18759_amd import cpqr as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "cpqr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpqr_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_loads_and_exports_header_symbols():
+    lib = ctypes.CDLL(C.LIB_PATH)
+    names = _header_functions()
+    assert "cpqr_als_qr" in names and "cpqr_schedule" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in cpqr.h but not exported"
+    assert sorted(C.EXPORTS) == names
+
+
+def test_status_strings():
+    L = C.load_library()
+    for code, name in [(0, "CPQR_OK"), (-1, "CPQR_EINVAL"), (-2, "CPQR_EUNSUPPORTED"),
+                       (-5, "CPQR_ERANKDEF"), (-6, "CPQR_ENONFINITE")]:
+        assert L.cpqr_status_string(code).decode() == name
+
+
+def _oracle_steps(N, tree, sweeps):
+    out = []
+    for steps in O.tree_schedule(N, tree, sweeps):
+        for s in steps:
+            if s[0] == "ttm":
+                out.append((0, sum(1 << m for m in s[1]), s[2]))
+            else:
+                out.append((1, 0, s[1]))
+    return out
+
+
+@pytest.mark.parametrize("N", [3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tree", ["none", "standard", "restructured"])
+def test_engine_schedule_equals_oracle_schedule(N, tree):
+    orders, steps, poly = P.schedule(N, tree, 8)
+    assert steps == _oracle_steps(N, tree, 8)
+    for k in range(8):
+        assert orders[k] == O.sweep_order(N, tree, k + 1)
+    assert poly == O.schedule_flops(O.tree_schedule(N, tree, 8), N)
+
+
+def test_engine_three_sweep_cost_matches_table3():
+    # Table 3, restructured: 8 I1I2I3 R + 4 I1I2 R^2 + 8 I1I3 R^2 + 6 I2I3 R^2
+    _, _, poly = P.schedule(3, "restructured", 3)
+    assert poly == {((0, 1, 2), 1): 8, ((0, 1), 2): 4, ((0, 2), 2): 8, ((1, 2), 2): 6}
+
+
+def test_schedule_rejects_bad_arguments():
+    L = C.load_library()
+    n = ctypes.c_int(0)
+    assert L.cpqr_schedule(1, 2, 3, None, None, 0, ctypes.byref(n), None) == C.EINVAL
+    assert L.cpqr_schedule(3, 7, 3, None, None, 0, ctypes.byref(n), None) == C.EINVAL
+    assert L.cpqr_schedule(3, 2, 0, None, None, 0, ctypes.byref(n), None) == C.EINVAL
+    assert L.cpqr_schedule(3, 2, 3, None, None, 0, ctypes.byref(n), None) == C.OK
+    steps = (ctypes.c_int * 3)()
+    assert L.cpqr_schedule(3, 2, 3, None, steps, 1, ctypes.byref(n), None) == C.EINVAL
+
+
+@pytest.mark.parametrize("kwargs,expect", [
+    (dict(dims=[40, 40, 40], rank=5, dtype="f64", prec="fp64"), C.OK),
+    (dict(dims=[256, 256, 256], rank=32), C.OK),
+    (dict(dims=[40] * 5, rank=16), C.OK),
+    (dict(dims=[40, 40, 4], rank=5), C.EUNSUPPORTED),          # I_n < R
+    (dict(dims=[40, 40, 40], rank=33), C.EUNSUPPORTED),        # rank above this build's limit
+    (dict(dims=[600, 40, 40], rank=5), C.EUNSUPPORTED),        # mode above the single-block QR limit
+    (dict(dims=[40] * 5, rank=32), C.EUNSUPPORTED),            # R^(N-1) beyond two-level TSQR
+    (dict(dims=[40, 40, 40], rank=0), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, prec="fp64"), C.EINVAL),  # f32 data with fp64 precision
+    (dict(dims=[40, 40, 40], rank=5, dtype="f64"), C.EINVAL),  # f64 data with fp32 precision
+    (dict(dims=[40, 40, 40], rank=5, iters=0), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, tol=-1.0), C.EINVAL),
+    (dict(dims=[40, 40], rank=5, tree="restructured"), C.EINVAL),
+    (dict(dims=[40, 40], rank=5, tree="none"), C.OK),
+    (dict(dims=[40, 40, 40], rank=5, data_ptr=0), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, raw={"tree": 5}), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, raw={"prec": 3}), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, raw={"extrapolate": 4}), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, raw={"null_init": True}), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, raw={"null_init_k": 1}), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, raw={"null_dims": True}), C.EINVAL),
+    (dict(dims=[40, 0, 40], rank=5), C.EINVAL),
+    (dict(dims=[40] * 8, rank=2), C.EINVAL),                  # order above the limit
+])
+def test_argument_checks(kwargs, expect):
+    kw = dict(kwargs)
+    dims, rank = kw.pop("dims"), kw.pop("rank")
+    assert P.check_args(dims, rank, **kw) == expect
+
+
+def test_python_layer_fails_loudly_without_library(tmp_path):
+    with pytest.raises(RuntimeError, match="not found"):
+        C._lib_saved = C._lib
+        try:
+            C._lib = None
+            C.load_library(str(tmp_path / "missing.so"))
+        finally:
+            C._lib = C._lib_saved

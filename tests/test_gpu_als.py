@@ -1,0 +1,205 @@
+"""End-to-end GPU parity of cp_als_qr (through the C ABI) with the FP64
+oracle on the same seeded inputs and initial factors.
+
+Tolerances:
+  * float64 chain: per-sweep fit within 1e-10 and factors within 1e-8.
+  * float32 chain: the explicit fit 1 - ||X - K|| / ||X|| within 1e-6; the
+    per-sweep fit of Section 4.1 within 1e-6 + 5e-7 / (1 - fit), because it
+    subtracts ||Vu||^2 (float32-accurate to ~1e-7 relative) from ||X||^2,
+    which loses the leading digits when the fit is close to 1.
+  * bf16x3 chain: the explicit fit within 1e-4.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthgen as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2503_18759_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.load_library()
+    return P
+
+
+def _run(P, prob, iters, *, prec, tree, extrap="off", fixed_beta=0.0, **kw):
+    dt = np.float64 if prec == "fp64" else np.float32
+    x, dims = P.to_device(prob.X.astype(dt))
+    g = P.cp_als_qr(x, prob.rank, prob.init, iters, dims=dims, tree=tree, extrapolate=extrap,
+                    prec=prec, fixed_beta=fixed_beta, explicit_fit=True, **kw)
+    Xo = np.asarray(prob.X, dtype=dt).astype(np.float64)
+    o = O.cp_als_qr(Xo, prob.rank, prob.init, iters, tree=tree, extrap=extrap,
+                    fix_beta=(fixed_beta if fixed_beta > 0 else None))
+    return g, o
+
+
+def _fit_tol(fo):
+    return 1e-6 + 5e-7 / max(1e-12, 1.0 - fo)
+
+
+def _check_fp32(g, o, explicit_tol=1e-6):
+    assert g["orders"] == o["orders"]
+    assert g["sweeps"] == o["sweeps"]
+    for fg, fo in zip(g["fits"], o["fits"]):
+        assert abs(fg - fo) <= _fit_tol(fo), (fg, fo)
+    assert abs(g["fit_explicit"] - o["fitx"]) <= explicit_tol, (g["fit_explicit"], o["fitx"])
+    for a, b in zip(g["factors"], o["factors"]):
+        cos = np.abs(np.sum(a * b, axis=0))
+        assert np.all(cos > 1 - 1e-3), cos
+
+
+def test_fp64_standard_40cube_rank5_full_workload(P):
+    """Order-3 40x40x40 float64, rank 5, iid N(0,1) factors, 1% noise, 50 sweeps,
+    standard tree, no extrapolation (the float64 workload at full size)."""
+    prob = G.workload("fp64_40cube_r5")
+    g, o = _run(P, prob, 50, prec="fp64", tree="standard")
+    assert g["orders"] == o["orders"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+    assert np.max(np.abs(g["lam"] - o["lam"]) / o["lam"]) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["small_o3", "small_o4", "small_o5"])
+@pytest.mark.parametrize("tree", ["none", "standard", "restructured"])
+def test_fp64_trees(P, name, tree):
+    prob = G.workload(name, dtype=np.float64)
+    g, o = _run(P, prob, 12, prec="fp64", tree=tree)
+    assert g["orders"] == o["orders"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+
+
+def test_fp64_fixed_beta_extrapolation(P):
+    """eq. (19) with beta fixed from sweep 2 on: the GPU applies Qhat0 through
+    Y_(n) Qhat0 = (1+beta) Y_(n) Q0 - alpha beta Y_(n) Q0prev."""
+    prob = G.workload("small_o4", dtype=np.float64)
+    g, o = _run(P, prob, 15, prec="fp64", tree="restructured", extrap="paper", fixed_beta=0.02)
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+
+
+def test_fp64_paper_extrapolation_rule(P):
+    prob = G.make_problem([20, 22, 18], 4, seed=21, congruence=0.6, rho=0.05, dtype=np.float64)
+    g, o = _run(P, prob, 40, prec="fp64", tree="restructured", extrap="paper")
+    assert o["beta_sweep"] > 0
+    assert g["beta_sweep"] == o["beta_sweep"] and g["beta"] == o["beta"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["small_o3", "small_o4", "small_o5"])
+@pytest.mark.parametrize("tree", ["none", "standard", "restructured"])
+def test_fp32_trees(P, name, tree):
+    prob = G.workload(name)
+    g, o = _run(P, prob, 25, prec="fp32", tree=tree)
+    _check_fp32(g, o)
+
+
+def test_fp32_paper_extrapolation(P):
+    prob = G.make_problem([30, 26, 34], 5, seed=22, congruence=0.7, rho=0.02, dtype=np.float32)
+    g, o = _run(P, prob, 40, prec="fp32", tree="restructured", extrap="paper")
+    assert g["beta_sweep"] == o["beta_sweep"] and g["beta"] == o["beta"]
+    _check_fp32(g, o)
+
+
+@pytest.mark.parametrize("name", ["small_o3", "small_o4"])
+def test_bf16x3_restructured(P, name):
+    prob = G.workload(name)
+    g, o = _run(P, prob, 25, prec="bf16x3", tree="restructured")
+    assert g["orders"] == o["orders"]
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-4
+
+
+def test_graph_replay_matches_eager(P):
+    prob = G.workload("small_o4")
+    x, dims = P.to_device(prob.X)
+    a = P.cp_als_qr(x, prob.rank, prob.init, 9, dims=dims, tree="restructured", use_graph=True)
+    b = P.cp_als_qr(x, prob.rank, prob.init, 9, dims=dims, tree="restructured", use_graph=False)
+    assert np.array_equal(a["fits"], b["fits"])
+    for u, v in zip(a["factors"], b["factors"]):
+        assert np.array_equal(u, v)
+
+
+def test_tolerance_stop(P):
+    """Stopping rule |fit_k - fit_{k-1}| < tol (float64 chain, so that the
+    fit of Section 4.1 is accurate enough to settle below tol)."""
+    prob = G.workload("small_o3", dtype=np.float64)
+    x, dims = P.to_device(prob.X)
+    g = P.cp_als_qr(x, prob.rank, prob.init, 300, dims=dims, tree="restructured", prec="fp64",
+                    tol=1e-9)
+    o = O.cp_als_qr(prob.X, prob.rank, prob.init, 300, tree="restructured", tol=1e-9)
+    f = g["fits"]
+    assert g["sweeps"] < 300 and abs(g["sweeps"] - o["sweeps"]) <= 1
+    assert abs(f[-1] - f[-2]) < 1e-9
+
+
+@pytest.mark.parametrize("mode", ["nan", "zero", "zero_column", "small_mode"])
+def test_error_paths(P, mode):
+    import torch
+    prob = G.make_problem([12, 10, 9], 3, seed=30, rho=0.01, dtype=np.float32)
+    X = prob.X.copy()
+    init = [a.copy() for a in prob.init]
+    expect = None
+    if mode == "nan":
+        X[3, 2, 1] = np.nan
+        expect = P.cpqr.ENONFINITE
+    elif mode == "zero":
+        X[:] = 0
+        expect = P.cpqr.EINVAL
+    elif mode == "zero_column":
+        # a zero initial column makes R_2 and hence Z_1 = R_3 (.) R_2 lose a
+        # column exactly, so R0 has a zero diagonal at the first update
+        init[1][:, 2] = 0.0
+        expect = P.cpqr.ERANKDEF
+    else:
+        X = X[:, :, :2].copy()
+        init[2] = init[2][:2]
+        expect = P.cpqr.EUNSUPPORTED
+    x, dims = P.to_device(X)
+    with pytest.raises(P.CpqrError) as ei:
+        P.cp_als_qr(x, 3, init, 5, dims=dims, tree="restructured")
+    assert ei.value.status == expect
+    # the handle stays usable after an error
+    x2, d2 = P.to_device(prob.X)
+    P.cp_als_qr(x2, 3, prob.init, 2, dims=d2)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_full_size_256cube_rank32_first_sweeps(P, prec):
+    """The 256^3, rank-32, congruence-0.9 workload at full size: the first
+    three sweeps of the restructured tree against the oracle."""
+    prob = G.workload("fp32_256cube_r32")
+    x, dims = P.to_device(prob.X)
+    g = P.cp_als_qr(x, 32, prob.init, 3, dims=dims, tree="restructured", prec=prec)
+    o = O.cp_als_qr(prob.X.astype(np.float64), 32, prob.init, 3, tree="restructured")
+    assert g["orders"] == o["orders"]
+    tol = 1e-6 if prec == "fp32" else 1e-4
+    for fg, fo in zip(g["fits"], o["fits"]):
+        assert abs(fg - fo) <= tol + 5e-7 / (1 - fo)
+    for a, b in zip(g["factors"], o["factors"]):
+        cos = np.abs(np.sum(a * b, axis=0))
+        assert np.all(cos > 1 - (1e-4 if prec == "fp32" else 1e-2))
+
+
+def test_full_size_order4_and_order5_first_sweep(P):
+    """96^4 rank 20 and 40^5 rank 16 at full size: one sweep each."""
+    for name, R in [("fp32_96pow4_r20", 20), ("fp32_40pow5_r16", 16)]:
+        prob = G.workload(name)
+        x, dims = P.to_device(prob.X)
+        g = P.cp_als_qr(x, R, prob.init, 1, dims=dims, tree="restructured")
+        o = O.cp_als_qr(prob.X.astype(np.float64), R, prob.init, 1, tree="restructured")
+        assert abs(g["fits"][0] - o["fits"][0]) <= 1e-6 + 5e-7 / (1 - o["fits"][0])
+        for a, b in zip(g["factors"], o["factors"]):
+            cos = np.abs(np.sum(a * b, axis=0))
+            assert np.all(cos > 1 - 1e-4)
+        del x

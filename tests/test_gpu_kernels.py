@@ -1,0 +1,130 @@
+"""GPU parity of the individual kernels through the C ABI against the FP64
+oracle: the mode-m TTM (float64, float32 MFMA, bf16x3 MFMA) over every
+layout class with ragged tails, and the Householder TSQR."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2503_18759_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.load_library()
+    return P
+
+
+def _ttm_case(P, dims, mode, R, prec, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    dt = np.float64 if prec == "fp64" else np.float32
+    X = rng.standard_normal(dims).astype(dt)
+    Q = rng.standard_normal((dims[mode], R)).astype(dt)
+    x, _ = P.to_device(X)
+    q = torch.from_numpy(np.asfortranarray(Q).ravel(order="F")).cuda().reshape(R, dims[mode]).t()
+    out, od = P.ttm(x, q, mode, dims=dims, prec=prec)
+    got = out.cpu().numpy().reshape(od, order="F").astype(np.float64)
+    ref = O.ttm(X.astype(np.float64), Q.astype(np.float64).T, mode)
+    mag = O.ttm(np.abs(X.astype(np.float64)), np.abs(Q.astype(np.float64)).T, mode)
+    I = dims[mode]
+    if prec == "fp64":
+        tol = 2 * I * 2.0 ** -53 * mag + 1e-300
+    elif prec == "fp32":
+        tol = 2 * I * U32 * mag + 1e-30
+    else:
+        tol = (3 * 2.0 ** -17 + 2 * I * U32) * mag + 1e-30
+    err = np.abs(got - ref)
+    assert got.shape == ref.shape
+    assert np.all(err <= tol), f"max err/tol {np.max(err / tol):.3g}"
+
+
+TTM_SHAPES = [
+    # (dims, mode, R): first mode (L == 1), middle, last; tails in every index
+    ((37, 29, 41), 0, 6), ((37, 29, 41), 1, 6), ((37, 29, 41), 2, 6),
+    ((64, 48, 40), 0, 16), ((64, 48, 40), 1, 16), ((64, 48, 40), 2, 16),
+    ((130, 17, 33), 0, 32), ((130, 17, 33), 1, 20), ((36, 130, 9), 1, 32),
+    ((33, 20, 70), 2, 5), ((20, 33, 70), 2, 33), ((12, 13, 14, 15), 2, 7),
+    ((8, 16, 24, 4), 1, 12), ((7, 9, 8, 6, 10), 3, 4), ((100, 3, 50), 0, 64),
+    ((1, 40, 1), 1, 1),
+]
+
+
+@pytest.mark.parametrize("dims,mode,R", TTM_SHAPES)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_ttm_matches_oracle(P, dims, mode, R, prec):
+    if prec == "bf16x3" and dims[mode] * ((R + 15) // 16) * 16 * 4 > 65536:
+        pytest.skip("outside the bf16x3 kernel limits")
+    _ttm_case(P, list(dims), mode, R, prec, seed=sum(dims) + 7 * mode + R)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_ttm_level1_full_size_sampled(P, prec):
+    """256^3 x_1 Q^T, x_2, x_3 with R = 32 (the level-1 TTMs of the 256^3
+    workload) checked on 400 sampled outputs computed one by one."""
+    import torch
+    rng = np.random.default_rng(5)
+    dims, R = [256, 256, 256], 32
+    x = torch.randn(256 ** 3, device="cuda", dtype=torch.float32, generator=torch.Generator("cuda").manual_seed(1))
+    X = x.cpu().numpy().reshape(dims, order="F").astype(np.float64)
+    for mode in range(3):
+        Q = rng.standard_normal((256, R)).astype(np.float32)
+        q = torch.from_numpy(np.asfortranarray(Q).ravel(order="F")).cuda().reshape(R, 256).t()
+        out, od = P.ttm(x, q, mode, dims=dims, prec=prec)
+        got = out.cpu().numpy().reshape(od, order="F")
+        idx = rng.integers(0, 256, size=(400, 3))
+        idx[:, mode] = rng.integers(0, R, size=400)
+        Qd = Q.astype(np.float64)
+        for (a, b, c) in idx:
+            sl = [a, b, c]
+            sl[mode] = slice(None)
+            fib = X[tuple(sl)]
+            r = [a, b, c][mode]
+            ref = float(fib @ Qd[:, r])
+            mag = float(np.abs(fib) @ np.abs(Qd[:, r]))
+            tol = (2 * 256 * U32 if prec == "fp32" else 3 * 2.0 ** -17 + 2 * 256 * U32) * mag
+            g = float(got[a if mode != 0 else r, b if mode != 1 else r, c if mode != 2 else r])
+            assert abs(g - ref) <= tol
+
+
+@pytest.mark.parametrize("M,R", [(5, 5), (40, 3), (300, 7), (1000, 16), (1024, 32), (5000, 20),
+                                  (8192, 32), (65536, 16), (100000, 8)])
+def test_tsqr_matches_oracle(P, M, R):
+    import torch
+    rng = np.random.default_rng(M + R)
+    A = rng.standard_normal((M, R))
+    A[:, 1] += 3 * A[:, 0]                      # mildly ill-conditioned
+    a = torch.from_numpy(np.asfortranarray(A).ravel(order="F")).cuda().reshape(R, M).t()
+    Q, Rm = P.qr(a)
+    Qg = Q.cpu().numpy()
+    Rg = Rm.cpu().numpy()
+    Qo, Ro = O.householder_qr(A)
+    assert np.all(np.diag(Rg) >= 0)
+    assert np.allclose(np.triu(Rg), Rg)
+    assert np.linalg.norm(Qg.T @ Qg - np.eye(R)) < 1e-13 * np.sqrt(M)
+    assert np.linalg.norm(Qg @ Rg - A) <= 1e-13 * np.linalg.norm(A) * np.sqrt(M)
+    assert np.max(np.abs(Rg - Ro)) <= 1e-12 * np.max(np.abs(Ro))
+    assert np.max(np.abs(Qg - Qo)) <= 1e-11
+
+
+def test_tsqr_exact_e1_structure(P):
+    """A first column c e1 gives Q[:,0] = e1 and Q[0,1:] = 0 exactly (the Q0
+    structure of Section 3.2)."""
+    import torch
+    M, R = 2000, 16
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((M, R))
+    A[:, 0] = 0.0
+    A[0, 0] = 1.75
+    a = torch.from_numpy(np.asfortranarray(A).ravel(order="F")).cuda().reshape(R, M).t()
+    Q, Rm = P.qr(a)
+    Qg = Q.cpu().numpy()
+    e1 = np.zeros(M)
+    e1[0] = 1.0
+    assert np.array_equal(Qg[:, 0], e1)
+    assert np.all(Qg[0, 1:] == 0.0)
