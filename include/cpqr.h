@@ -125,13 +125,44 @@ typedef struct {
  * tolerance, tree, extrapolation, precision, initial factors).  Outputs
  * (host, caller-owned): factor matrices with unit-norm columns, lambda, the
  * per-sweep fit history and update orders, and the final fit.
- * Limits of this build: 1 <= R <= 32, R <= I_n <= 512 for every mode
- * (I_n < R returns CPQR_EUNSUPPORTED), R^(N-1) <= 2^20.
+ * Limits of this build: 1 <= R <= 32; R <= I_n <= 512 for every mode
+ * (I_n < R returns CPQR_EUNSUPPORTED); Z_n (R^(N-1) x R) must fit a
+ * two-level TSQR: ceil(R^(N-1) / B) * R <= B with B = 2048, 1024, 512 rows
+ * for R <= 8, 16, 32 (for example 40^5 at R = 16 and 256^3 at R = 32 fit).
  * On a runtime error (CPQR_ERANKDEF, CPQR_ENONFINITE, CPQR_EHIP) the outputs
  * are untouched except sweeps_done and fit_history up to the failure.
  */
 cpqr_status cpqr_als_qr(cpqr_handle *handle, const cpqr_tensor *X, int rank,
                         const cpqr_options *opts, cpqr_result *result);
+
+/*
+ * Step-wise form of cpqr_als_qr.  A session holds one decomposition in
+ * progress on the device; cpqr_als_qr is create + sweeps(iters) + result +
+ * destroy.  A handle has at most one live session (its workspace is shared).
+ *
+ * cpqr_session_create -- validate as cpqr_check_args, allocate workspace,
+ *   upload and QR-factor the initial factors (Algorithm 2 "Initialize") and
+ *   compute ||X||^2.  X must stay allocated and unchanged until the session
+ *   is destroyed.  opts->iters is the maximum number of sweeps.  Errors as
+ *   cpqr_als_qr, plus CPQR_EINVAL if the handle already has a live session.
+ * cpqr_session_sweeps -- enqueue the next `nsweeps` sweeps on the handle's
+ *   stream.  Asynchronous unless opts->tol > 0, in which case the fit is read
+ *   back after each sweep and the session stops once the tolerance is met
+ *   (later calls then do nothing).  CPQR_EINVAL if the total would exceed
+ *   opts->iters.
+ * cpqr_session_sync -- wait for the enqueued sweeps.
+ * cpqr_session_result -- wait, then fill `result` (caller-owned host
+ *   buffers, as for cpqr_als_qr) for the sweeps run so far; `seconds` is the
+ *   device time since the first cpqr_session_sweeps call.
+ * cpqr_session_destroy -- wait and release the session.
+ */
+typedef struct cpqr_session cpqr_session;
+cpqr_status cpqr_session_create(cpqr_handle *handle, const cpqr_tensor *X, int rank,
+                                const cpqr_options *opts, cpqr_session **session);
+cpqr_status cpqr_session_sweeps(cpqr_session *session, int nsweeps);
+cpqr_status cpqr_session_sync(cpqr_session *session);
+cpqr_status cpqr_session_result(cpqr_session *session, cpqr_result *result);
+cpqr_status cpqr_session_destroy(cpqr_session *session);
 
 /*
  * cpqr_check_args -- host-only: the argument checks that cpqr_als_qr makes

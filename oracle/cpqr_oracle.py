@@ -294,13 +294,15 @@ def mode_update(Yn: np.ndarray, Rfs: Sequence[np.ndarray], n: int,
 def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
               tree: str = "none", extrap: str = "off", alpha: float = 0.1,
               delta: float = 0.03, tol: float = 0.0, fix_beta: Optional[float] = None,
-              explicit_every_sweep: bool = False) -> Dict:
+              explicit_every_sweep: bool = False, explicit_final: bool = True,
+              sweep_callback=None) -> Dict:
     """CP-ALS-QR (Algorithm 2) / ALS-QR-BR(E) (Algorithm 3) in FP64 with
     direct multi-TTMs from X.  ``tree`` only selects the update order.
 
     ``extrap``: "off" (beta = 0) or "paper" (eq. 19 with the activation rule).
     ``fix_beta`` (test hook): apply this beta from sweep 2 onward instead of
-    the rule.
+    the rule.  ``sweep_callback(k, fit)`` (instrumentation hook) is called
+    after each sweep; ``explicit_final=False`` skips the final explicit fit.
     """
     X = np.asarray(X, F64)
     N = X.ndim
@@ -338,11 +340,14 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
         if extrap == "paper" and fix_beta is None and not active and k >= 2 \
                 and abs(fit - fits[-2]) < delta:
             beta, active, beta_sweep = beta_from_fit(fit), True, k
+        if sweep_callback is not None:
+            sweep_callback(k, fit)
         if tol > 0.0 and k >= 2 and abs(fit - fits[-2]) < tol:
             break
     return {
         "factors": A, "lam": lam, "Q": Qs, "R": Rfs, "fits": np.array(fits),
-        "fitx": explicit_fit(X, lam, A), "fitxs": np.array(fitxs),
+        "fitx": explicit_fit(X, lam, A) if explicit_final else float("nan"),
+        "fitxs": np.array(fitxs),
         "orders": orders, "beta": beta if fix_beta is None else fix_beta,
         "beta_sweep": beta_sweep, "sweeps": len(fits), "nx2": nx2,
     }

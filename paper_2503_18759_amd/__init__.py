@@ -4,5 +4,5 @@ dimension tree and customised Q0 extrapolation of arXiv 2503.18759.
 The compute path is libcpqr.so (hand-written HIP kernels behind a C ABI,
 ``include/cpqr.h``); :mod:`paper_2503_18759_amd.cpqr` is its ctypes binding.
 """
-from .cpqr import (CpqrError, Handle, check_args, cp_als_qr, default_handle,  # noqa: F401
-                   load_library, qr, schedule, to_device, ttm)
+from .cpqr import (CpqrError, Handle, Session, check_args, cp_als_qr,  # noqa: F401
+                   default_handle, load_library, qr, schedule, to_device, ttm)

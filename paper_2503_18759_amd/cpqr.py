@@ -61,7 +61,9 @@ class _Result(ctypes.Structure):
 
 
 EXPORTS = ["cpqr_create", "cpqr_destroy", "cpqr_last_error", "cpqr_status_string",
-           "cpqr_check_args", "cpqr_als_qr", "cpqr_schedule", "cpqr_ttm", "cpqr_qr"]
+           "cpqr_check_args", "cpqr_als_qr", "cpqr_session_create", "cpqr_session_sweeps",
+           "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy",
+           "cpqr_schedule", "cpqr_ttm", "cpqr_qr"]
 
 _lib = None
 
@@ -84,13 +86,20 @@ def load_library(path: str = LIB_PATH):
     L.cpqr_status_string.restype = ctypes.c_char_p
     L.cpqr_als_qr.argtypes = [vp, ctypes.POINTER(_Tensor), i32, ctypes.POINTER(_Options),
                               ctypes.POINTER(_Result)]
+    L.cpqr_session_create.argtypes = [vp, ctypes.POINTER(_Tensor), i32, ctypes.POINTER(_Options),
+                                      ctypes.POINTER(vp)]
+    L.cpqr_session_sweeps.argtypes = [vp, i32]
+    L.cpqr_session_sync.argtypes = [vp]
+    L.cpqr_session_result.argtypes = [vp, ctypes.POINTER(_Result)]
+    L.cpqr_session_destroy.argtypes = [vp]
     L.cpqr_check_args.argtypes = [ctypes.POINTER(_Tensor), i32, ctypes.POINTER(_Options)]
     L.cpqr_schedule.argtypes = [i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), i32,
                                 ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.cpqr_ttm.argtypes = [vp, i32, i32, ctypes.POINTER(i64), i32, i32, vp, vp, vp]
     L.cpqr_qr.argtypes = [vp, i64, i32, vp, vp, vp]
     for f in ("cpqr_create", "cpqr_destroy", "cpqr_check_args", "cpqr_als_qr", "cpqr_schedule",
-              "cpqr_ttm", "cpqr_qr"):
+              "cpqr_ttm", "cpqr_qr", "cpqr_session_create", "cpqr_session_sweeps",
+              "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -186,6 +195,56 @@ def to_device(X: np.ndarray, dtype=None, device: int = 0):
     return torch.from_numpy(flat).to(f"cuda:{device}"), [int(d) for d in arr.shape]
 
 
+def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, switch_delta,
+             fixed_beta, explicit_fit, time_kernels, use_graph):
+    dims, dt, ptr = _dims_and_ptr(x, dims)
+    N = len(dims)
+    inits = [np.asfortranarray(np.asarray(a, dtype=np.float64)) for a in init]
+    if len(inits) != N:
+        raise ValueError("need one initial factor per mode")
+    for k, a in enumerate(inits):
+        if a.shape != (dims[k], rank):
+            raise ValueError(f"init factor {k} must be {dims[k]} x {rank}")
+    keep = {"dims_c": (ctypes.c_int64 * N)(*dims), "inits": inits}
+    keep["ten"] = _Tensor(N, keep["dims_c"], dt, ctypes.c_void_p(ptr))
+    keep["init_ptrs"] = (ctypes.POINTER(ctypes.c_double) * N)(
+        *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in inits])
+    flags = (FLAG_EXPLICIT_FIT if explicit_fit else 0) | (FLAG_TIME_KERNELS if time_kernels else 0) \
+        | (0 if use_graph else FLAG_NO_GRAPH)
+    keep["opts"] = _Options(TREES[tree], EXTRAP[extrapolate], PRECS[prec], int(iters), float(tol),
+                            float(alpha), float(switch_delta), float(fixed_beta),
+                            keep["init_ptrs"], flags)
+    return dims, keep
+
+
+def _result_buffers(dims, rank, iters):
+    N = len(dims)
+    outs = [np.zeros((dims[k], rank), order="F") for k in range(N)]
+    lam = np.zeros(rank)
+    fits = np.full(max(iters, 1), np.nan)
+    orders = np.zeros((max(iters, 1), N), dtype=np.int32)
+    res = _Result()
+    res.factors = (ctypes.POINTER(ctypes.c_double) * N)(
+        *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for o in outs])
+    res.lambda_ = lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    res.fit_history = fits.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    res.sweep_orders = orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    return res, (outs, lam, fits, orders)
+
+
+def _result_dict(res, bufs):
+    outs, lam, fits, orders = bufs
+    n = res.sweeps_done
+    return {
+        "factors": outs, "lam": lam, "fits": fits[:n].copy(), "fit": res.fit,
+        "fit_explicit": res.fit_explicit, "orders": orders[:n].tolist(), "beta": res.beta,
+        "beta_sweep": res.beta_sweep, "sweeps": n, "seconds": res.seconds,
+        "ttm_flops": res.ttm_flops, "ttm_bytes": res.ttm_bytes,
+        "l1_ttm_seconds": res.l1_ttm_seconds, "l1_ttm_launches": res.l1_ttm_launches,
+        "l1_ttm_bytes": res.l1_ttm_bytes, "l1_ttm_flops": res.l1_ttm_flops,
+    }
+
+
 def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
               dims: Optional[Sequence[int]] = None, tree: str = "restructured",
               extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
@@ -199,45 +258,65 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
     sweeps, seconds, ttm_flops, ttm_bytes and the level-1 TTM timing fields.
     """
     L = load_library()
-    dims, dt, ptr = _dims_and_ptr(x, dims)
-    N = len(dims)
+    dims, keep = _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha,
+                          switch_delta, fixed_beta, explicit_fit, time_kernels, use_graph)
     h = handle or default_handle(x.device.index or 0)
-    dims_c = (ctypes.c_int64 * N)(*dims)
-    ten = _Tensor(N, dims_c, dt, ctypes.c_void_p(ptr))
-    inits = [np.asfortranarray(np.asarray(a, dtype=np.float64)) for a in init]
-    if len(inits) != N:
-        raise ValueError("need one initial factor per mode")
-    for k, a in enumerate(inits):
-        if a.shape != (dims[k], rank):
-            raise ValueError(f"init factor {k} must be {dims[k]} x {rank}")
-    init_ptrs = (ctypes.POINTER(ctypes.c_double) * N)(
-        *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in inits])
-    flags = (FLAG_EXPLICIT_FIT if explicit_fit else 0) | (FLAG_TIME_KERNELS if time_kernels else 0) \
-        | (0 if use_graph else FLAG_NO_GRAPH)
-    opts = _Options(TREES[tree], EXTRAP[extrapolate], PRECS[prec], int(iters), float(tol),
-                    float(alpha), float(switch_delta), float(fixed_beta), init_ptrs, flags)
-    outs = [np.zeros((dims[k], rank), order="F") for k in range(N)]
-    out_ptrs = (ctypes.POINTER(ctypes.c_double) * N)(
-        *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for o in outs])
-    lam = np.zeros(rank)
-    fits = np.full(iters, np.nan)
-    orders = np.zeros((iters, N), dtype=np.int32)
-    res = _Result()
-    res.factors = out_ptrs
-    res.lambda_ = lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    res.fit_history = fits.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    res.sweep_orders = orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
-    st = L.cpqr_als_qr(h._h, ctypes.byref(ten), int(rank), ctypes.byref(opts), ctypes.byref(res))
+    res, bufs = _result_buffers(dims, rank, iters)
+    st = L.cpqr_als_qr(h._h, ctypes.byref(keep["ten"]), int(rank), ctypes.byref(keep["opts"]),
+                       ctypes.byref(res))
     h.check(st)
-    n = res.sweeps_done
-    return {
-        "factors": outs, "lam": lam, "fits": fits[:n], "fit": res.fit,
-        "fit_explicit": res.fit_explicit, "orders": orders[:n].tolist(), "beta": res.beta,
-        "beta_sweep": res.beta_sweep, "sweeps": n, "seconds": res.seconds,
-        "ttm_flops": res.ttm_flops, "ttm_bytes": res.ttm_bytes,
-        "l1_ttm_seconds": res.l1_ttm_seconds, "l1_ttm_launches": res.l1_ttm_launches,
-        "l1_ttm_bytes": res.l1_ttm_bytes, "l1_ttm_flops": res.l1_ttm_flops,
-    }
+    return _result_dict(res, bufs)
+
+
+class Session:
+    """Step-wise decomposition: ``Session(x, R, init, max_sweeps, ...)``,
+    then ``sweeps(n)`` (asynchronous), ``sync()``, ``result()``, ``close()``."""
+
+    def __init__(self, x, rank: int, init: Sequence[np.ndarray], max_sweeps: int, *,
+                 dims: Optional[Sequence[int]] = None, tree: str = "restructured",
+                 extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
+                 alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
+                 explicit_fit: bool = False, time_kernels: bool = False,
+                 use_graph: bool = True, handle: Optional[Handle] = None):
+        L = load_library()
+        self._x = x
+        self.rank = rank
+        self.max_sweeps = max_sweeps
+        self.dims, self._keep = _prepare(x, rank, init, max_sweeps, dims, tree, extrapolate, prec,
+                                         tol, alpha, switch_delta, fixed_beta, explicit_fit,
+                                         time_kernels, use_graph)
+        self.h = handle or default_handle(x.device.index or 0)
+        self._s = ctypes.c_void_p()
+        self.h.check(L.cpqr_session_create(self.h._h, ctypes.byref(self._keep["ten"]), int(rank),
+                                           ctypes.byref(self._keep["opts"]), ctypes.byref(self._s)))
+
+    def sweeps(self, n: int):
+        self.h.check(load_library().cpqr_session_sweeps(self._s, int(n)))
+
+    def sync(self):
+        self.h.check(load_library().cpqr_session_sync(self._s))
+
+    def result(self) -> Dict:
+        res, bufs = _result_buffers(self.dims, self.rank, self.max_sweeps)
+        self.h.check(load_library().cpqr_session_result(self._s, ctypes.byref(res)))
+        return _result_dict(res, bufs)
+
+    def close(self):
+        if self._s:
+            load_library().cpqr_session_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def check_args(dims: Sequence[int], rank: int, *, dtype: str = "f32", iters: int = 1,

@@ -5,12 +5,25 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define CPQR_WAVE 64
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 namespace cpqr {
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E).  Used
+// where register arrays are indexed by the loop variable, so that every index
+// is a constant and the arrays stay in registers.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Wave-level "transpose" reduction of V doubles (V a power of two, <= 32).
@@ -21,7 +34,7 @@ namespace cpqr {
 // upper half of its values, the other the lower half, and both add the
 // partner's copy of the half they keep.  Steps over bits 5 and 4 use the
 // gfx950 cross-row swap instructions (v_permlane32_swap / v_permlane16_swap);
-// the remaining bits use ds_bpermute shuffles.
+// the remaining bits use DPP lane permutations within rows.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void swap32_add(double& x, double& y) {
   // lanes 0-31 end with x(L) + x(L+32); lanes 32-63 with y(L-32) + y(L)
@@ -46,6 +59,14 @@ __device__ __forceinline__ void swap16_add(double& x, double& y) {
   x = a + b;
 }
 
+// Value of `v` in the lane selected by the DPP control CTRL (row-local).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, CPQR_WAVE);
 }
@@ -54,41 +75,54 @@ template <int V>
 __device__ __forceinline__ void wave_transpose_reduce(double (&a)[V]) {
   static_assert(V >= 1 && V <= 32 && (V & (V - 1)) == 0, "V must be a power of two <= 32");
   const int lane = threadIdx.x & 63;
-  int count = V;
-  // bit 5 (lanes 32-63 keep the upper half)
-  if (count >= 2) {
-#pragma unroll
-    for (int q = 0; q < V / 2; ++q) swap32_add(a[q], a[q + V / 2]);
-    count = V / 2;
+  // bit 5: lanes 32-63 keep the upper half
+  if constexpr (V >= 2) {
+    static_for<0, V / 2>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      swap32_add(a[q], a[q + V / 2]);
+    });
   } else {
     a[0] += shfl_xor_d(a[0], 32);
   }
   // bit 4
-  if (V >= 4) {
-#pragma unroll
-    for (int q = 0; q < V / 4; ++q) swap16_add(a[q], a[q + V / 4]);
-    count = V / 4;
+  if constexpr (V >= 4) {
+    static_for<0, V / 4>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      swap16_add(a[q], a[q + V / 4]);
+    });
   } else {
     a[0] += shfl_xor_d(a[0], 16);
   }
-  // bits 3..0
-#pragma unroll
-  for (int bit = 3; bit >= 0; --bit) {
-    const int m = 1 << bit;
-    const int half = V >> (6 - bit);   // values kept per lane after this step
-    if (half >= 1) {
+  // bits 3..0 within each row of 16 lanes, by DPP: the partner of lane i is
+  // 15-i (row mirror), then 7-i within each half row (half mirror), then the
+  // quad permutations i^2 and i^1.  Each partner differs from the lane in the
+  // bit that decides which half is kept, which is all the reduction needs.
+  static_for<0, 4>([&](auto bc) {
+    constexpr int bit = 3 - decltype(bc)::value;
+    constexpr int m = 1 << bit;
+    constexpr int ctrl = (bit == 3) ? 0x140 : (bit == 2) ? 0x141 : (bit == 1) ? 0x4E : 0xB1;
+    constexpr int half = V >> (6 - bit);   // values kept per lane after this step
+    if constexpr (half >= 1) {
       const bool upper = (lane & m) != 0;
-#pragma unroll
-      for (int q = 0; q < half; ++q) {
-        double keep = upper ? a[q + half] : a[q];
-        double send = upper ? a[q] : a[q + half];
-        a[q] = keep + shfl_xor_d(send, m);
-      }
+      static_for<0, half>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const double keep = upper ? a[q + half] : a[q];
+        const double send = upper ? a[q] : a[q + half];
+        a[q] = keep + dpp_d<ctrl>(send);
+      });
     } else {
-      a[0] += shfl_xor_d(a[0], m);
+      a[0] += dpp_d<ctrl>(a[0]);
     }
-  }
-  (void)count;
+  });
+}
+
+// Copy of a wave-uniform integer held in a vector register, so that
+// comparisons against it are lane-wise selects (v_cndmask) rather than
+// scalar branches; used for masked access to register arrays.
+__device__ __forceinline__ int to_vgpr(int x) {
+  int v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+  return v;
 }
 
 // Plain all-lanes sum of one double over the wave.

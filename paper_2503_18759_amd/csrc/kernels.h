@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #define CPQR_MAX_ORDER 7
+#define CPQR_MAX_FACTOR_ROWS 512   // largest mode size I_n handled by the factor QR kernels
 
 namespace cpqr {
 
@@ -33,7 +34,19 @@ hipError_t launch_ttm_f64(const double* in, const double* Q, double* out, int64_
 
 // --- QR -------------------------------------------------------------------
 int qr_rmax(int R);
-int64_t qr_leaf_rows(int R);
+int64_t qr_leaf_rows(int R);   // largest TSQR leaf at rank R
+// TSQR of an M x R matrix: leaves of leaf_rows rows (leaf_rpt rows per
+// thread), P leaves, and a top block of top_rpt rows per thread (P > 1).
+struct TsqrPlan {
+  bool ok;
+  int leaf_rpt;
+  int64_t leaf_rows;
+  int P;
+  int top_rpt;
+};
+TsqrPlan tsqr_plan(int64_t M, int R);
+int factor_rpt(int I);
+int qr_max_order(int R);   // largest order whose Khatri-Rao QR fits the kernels at rank R
 
 struct TsqrArgs {
   int N, n, R;          // order, skipped mode (Khatri-Rao source), rank

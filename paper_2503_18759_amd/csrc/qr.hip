@@ -18,59 +18,59 @@
 
 namespace cpqr {
 
+// Largest number of other modes whose Khatri-Rao product can fit a two-level
+// TSQR at this column count (R^N <= leaf_rows^2 with the smallest R of the
+// class: R = 17 for 32 columns, 9 for 16, 2 for 8; capped by the order limit).
+constexpr int qr_max_other_modes(int rmax) { return rmax >= 32 ? 3 : (rmax >= 16 ? 5 : CPQR_MAX_ORDER - 1); }
+int qr_max_order(int R) { return qr_max_other_modes(qr_rmax(R)) + 1; }
+
 // ----------------------------------------------------------------- leaves
 // src == nullptr: build rows of Z from the R factors in `rf` (N x R x R,
 // column-major, factor n skipped).  Otherwise read rows of the M x R
 // column-major matrix `src`.
 template <int RMAX, int RPT>
-__global__ __launch_bounds__(QR_THREADS) void zqr_leaf(
+__global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(
     int N, int n, int R, const double* __restrict__ rf, const double* __restrict__ src,
     int64_t M, double* __restrict__ V, double* __restrict__ Tbuf, double* __restrict__ stack,
-    int64_t ldstack) {
+    int64_t ldstack, double* __restrict__ R0, double* __restrict__ Qtop) {
   __shared__ QrSmem<RMAX> sm;
-  __shared__ double srf[(CPQR_MAX_ORDER - 1) * RMAX * RMAX];
-  constexpr int B = QR_THREADS * RPT;
+  __shared__ double srf[qr_max_other_modes(RMAX) * RMAX * RMAX];
+  constexpr int B = QrCfg<RMAX>::NT * RPT;
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
-  int modes[CPQR_MAX_ORDER];
-  int nm = 0;
+  const int nm = (src == nullptr) ? N - 1 : 0;
   if (src == nullptr) {
-    for (int k = 0; k < N; ++k)
-      if (k != n) modes[nm++] = k;
-    for (int e = tid; e < nm * R * R; e += QR_THREADS) {
-      const int q = e / (R * R), rem = e % (R * R);
-      srf[e] = rf[(int64_t)modes[q] * R * R + rem];
+    // R factors of the other modes (ascending mode order), zero-padded to
+    // RMAX x RMAX so that columns c >= R of every product vanish
+    for (int e = tid; e < nm * RMAX * RMAX; e += QrCfg<RMAX>::NT) {
+      const int q = e / (RMAX * RMAX), rem = e % (RMAX * RMAX);
+      const int i = rem % RMAX, c = rem / RMAX;
+      const int mode = (q < n) ? q : q + 1;
+      srf[e] = (i < R && c < R) ? rf[(int64_t)mode * R * R + i + (int64_t)R * c] : 0.0;
     }
     __syncthreads();
   }
-  double a[RPT][RMAX];
+  QrRow<RMAX> a[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = (int64_t)p * B + tid + QR_THREADS * q;
+    const int64_t row = (int64_t)p * B + tid + QrCfg<RMAX>::NT * q;
+    const bool in = row < M;
+    if (src == nullptr) {
+      // Z[row][c] = prod_k R_k[digit_k(row)][c], digits of row in base R with
+      // the first remaining mode fastest
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) a[q][c] = 0.0;
-    if (row < M) {
-      if (src == nullptr) {
-        // digits of row in base R, first remaining mode fastest
-        int dig[CPQR_MAX_ORDER];
-        int64_t rr = row;
-        for (int k = 0; k < nm; ++k) {
-          dig[k] = (int)(rr % R);
-          rr /= R;
-        }
+      for (int c = 0; c < RMAX; ++c) a[q].set(c, in ? 1.0 : 0.0);
+      int64_t rr = row;
+      for (int k = 0; k < nm; ++k) {
+        const int d = (int)(rr % R);
+        rr /= R;
+        const double* rk = srf + k * RMAX * RMAX + d;
 #pragma unroll
-        for (int c = 0; c < RMAX; ++c) {
-          if (c < R) {
-            double prod = 1.0;
-            for (int k = 0; k < nm; ++k) prod *= srf[k * R * R + dig[k] + R * c];
-            a[q][c] = prod;
-          }
-        }
-      } else {
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c)
-          if (c < R) a[q][c] = src[row + M * c];
+        for (int c = 0; c < RMAX; ++c) a[q].set(c, a[q].get(c) * rk[RMAX * c]);
       }
+    } else {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) a[q].set(c, (in && c < R) ? src[row + M * c] : 0.0);
     }
   }
   block_qr<RMAX, RPT>(a, R, sm);
@@ -78,23 +78,36 @@ __global__ __launch_bounds__(QR_THREADS) void zqr_leaf(
   const int64_t ldv = (int64_t)gridDim.x * B;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int lr = tid + QR_THREADS * q;
+    const int lr = tid + QrCfg<RMAX>::NT * q;
     const int64_t row = (int64_t)p * B + lr;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
       if (c < R) {
-        const double v = (lr > c) ? a[q][c] : ((lr == c) ? 1.0 : 0.0);
+        const double v = block_qr_v<RMAX, RPT>(a, q, lr, c, sm);
         V[row + ldv * c] = v;
       }
     }
   }
-  // leaf R (no sign fix) into the stack, T into Tbuf
-  if (tid < R) {
+  if (R0 != nullptr) {
+    // single leaf: this is the whole QR.  R0 = D R with D = sign(diag R) and
+    // the (trivial) stack factor Qtop = D.
+    if (tid < R) {
+      const double sg = (sm.beta[tid] < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) {
+        if (c < R) {
+          R0[tid + R * c] = sg * block_qr_r<RMAX>(a[0], tid, c, sm);
+          Qtop[tid + R * c] = (c == tid) ? sg : 0.0;
+        }
+      }
+    }
+  } else if (tid < R) {
+    // leaf R (no sign fix) into the stack of leaf triangles
 #pragma unroll
     for (int c = 0; c < RMAX; ++c)
-      if (c < R) stack[(int64_t)p * R + tid + ldstack * c] = (c >= tid) ? a[0][c] : 0.0;
+      if (c < R) stack[(int64_t)p * R + tid + ldstack * c] = block_qr_r<RMAX>(a[0], tid, c, sm);
   }
-  for (int e = tid; e < R * R; e += QR_THREADS) {
+  for (int e = tid; e < R * R; e += QrCfg<RMAX>::NT) {
     const int k = e % R, c = e / R;
     Tbuf[(int64_t)p * R * R + e] = sm.T[k][c];
   }
@@ -104,43 +117,38 @@ __global__ __launch_bounds__(QR_THREADS) void zqr_leaf(
 // QR of the P*R x R stack.  Writes R0 (R x R column-major, diag >= 0) and
 // Qtop (P*R x R column-major) = explicit Q of the stack times the sign fix.
 template <int RMAX, int RPT>
-__global__ __launch_bounds__(QR_THREADS) void zqr_top(
+__global__ CPQR_QR_KERNEL(RMAX) void zqr_top(
     int R, int64_t rows, const double* __restrict__ stack, double* __restrict__ R0,
     double* __restrict__ Qtop) {
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   const int tid = threadIdx.x;
-  double a[RPT][RMAX];
+  QrRow<RMAX> a[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = tid + QR_THREADS * q;
+    const int64_t row = tid + QrCfg<RMAX>::NT * q;
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) a[q][c] = (row < rows && c < R) ? stack[row + rows * c] : 0.0;
+    for (int c = 0; c < RMAX; ++c) a[q].set(c, (row < rows && c < R) ? stack[row + rows * c] : 0.0);
   }
   block_qr<RMAX, RPT>(a, R, sm);
   block_qr_publish<RMAX, RPT>(a, R, sm, wy, true);
   block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
-  for (int e = tid; e < R * R; e += QR_THREADS) {
+  for (int e = tid; e < R * R; e += QrCfg<RMAX>::NT) {
     const int i = e % R, c = e / R;
     R0[e] = wy.Rm[i][c];
   }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int64_t row = tid + QR_THREADS * q;
-    double qq[RMAX];
-    block_qr_q_row<RMAX, RPT>(a, q, R, sm, wy, qq);
-    if (row < rows) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c)
-        if (c < R) Qtop[row + rows * c] = qq[c];
-    }
+    const int64_t row = tid + QrCfg<RMAX>::NT * q;
+    if (row < rows)
+      block_qr_q_row<RMAX, RPT>(a, q, R, sm, wy, [&](int c, double val) { Qtop[row + rows * c] = val; });
   }
 }
 
 // ------------------------------------------------------------------ form Q0
 // One workgroup per 256-row chunk.  Chunk rows lie inside one leaf p.
 template <int RMAX>
-__global__ __launch_bounds__(QR_THREADS) void form_q0(
+__global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(
     int R, int64_t M, int leaf_rows, const double* __restrict__ V, int64_t ldv,
     const double* __restrict__ Tbuf, const double* __restrict__ Qtop, int64_t ldq,
     double* __restrict__ Q0) {
@@ -148,11 +156,11 @@ __global__ __launch_bounds__(QR_THREADS) void form_q0(
   __shared__ QrWySmem<RMAX> wy;
   __shared__ double sQt[RMAX * RMAX];
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * QR_THREADS;
+  const int64_t row0 = (int64_t)blockIdx.x * QrCfg<RMAX>::NT;
   const int p = (int)(row0 / leaf_rows);
   const int64_t leaf0 = (int64_t)p * leaf_rows;
   // V1 of the leaf, T of the leaf, Qtop block p (row-major in LDS)
-  for (int e = tid; e < RMAX * RMAX; e += QR_THREADS) {
+  for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
     const int i = e / RMAX, c = e % RMAX;
     const bool in = i < R && c < R;
     wy.V1[i][c] = in ? V[leaf0 + i + ldv * c] : 0.0;
@@ -185,75 +193,127 @@ __global__ __launch_bounds__(QR_THREADS) void form_q0(
 // Writes Rn (R x R col-major, diag >= 0) and the explicit Q in the requested
 // forms (any pointer may be null).
 template <int RMAX, int RPT>
-__global__ __launch_bounds__(QR_THREADS) void factor_qr(
+__global__ CPQR_QR_KERNEL(RMAX) void factor_qr(
     int I, int R, const double* __restrict__ A, double* __restrict__ Rn, double* __restrict__ q64,
     float* __restrict__ q32) {
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   const int tid = threadIdx.x;
-  double a[RPT][RMAX];
+  QrRow<RMAX> a[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int row = tid + QR_THREADS * q;
+    const int row = tid + QrCfg<RMAX>::NT * q;
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) a[q][c] = (row < I && c < R) ? A[row + (int64_t)I * c] : 0.0;
+    for (int c = 0; c < RMAX; ++c) a[q].set(c, (row < I && c < R) ? A[row + (int64_t)I * c] : 0.0);
   }
   block_qr<RMAX, RPT>(a, R, sm);
   block_qr_publish<RMAX, RPT>(a, R, sm, wy, true);
   block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
-  for (int e = tid; e < R * R; e += QR_THREADS) {
+  for (int e = tid; e < R * R; e += QrCfg<RMAX>::NT) {
     const int i = e % R, c = e / R;
     Rn[e] = wy.Rm[i][c];
   }
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int row = tid + QR_THREADS * q;
-    double qq[RMAX];
-    block_qr_q_row<RMAX, RPT>(a, q, R, sm, wy, qq);
-    if (row < I) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        if (c < R) {
-          if (q64) q64[row + (int64_t)I * c] = qq[c];
-          if (q32) q32[row + (int64_t)I * c] = (float)qq[c];
-        }
-      }
-    }
+    const int row = tid + QrCfg<RMAX>::NT * q;
+    if (row < I)
+      block_qr_q_row<RMAX, RPT>(a, q, R, sm, wy, [&](int c, double val) {
+        if (q64) q64[row + (int64_t)I * c] = val;
+        if (q32) q32[row + (int64_t)I * c] = (float)val;
+      });
   }
 }
 
 // ---------------------------------------------------------------- launchers
 int qr_rmax(int R) { return R <= 8 ? 8 : (R <= 16 ? 16 : (R <= 32 ? 32 : 0)); }
-int qr_rpt(int rmax) { return rmax == 8 ? 8 : (rmax == 16 ? 4 : 2); }
-int64_t qr_leaf_rows(int R) { const int rm = qr_rmax(R); return rm ? (int64_t)QR_THREADS * qr_rpt(rm) : 0; }
+// largest rows-per-thread instantiated at this column count (register budget)
+static int qr_max_rpt(int rmax) { return rmax == 8 ? 8 : (rmax == 16 ? 4 : 2); }
 
-#define CPQR_QR_DISPATCH(R, BODY)                   \
-  do {                                              \
-    const int rm__ = qr_rmax(R);                    \
-    if (rm__ == 8) { constexpr int RM = 8, RP = 8; BODY; }        \
-    else if (rm__ == 16) { constexpr int RM = 16, RP = 4; BODY; } \
-    else if (rm__ == 32) { constexpr int RM = 32, RP = 2; BODY; } \
-    else return hipErrorInvalidValue;               \
+TsqrPlan tsqr_plan(int64_t M, int R) {
+  TsqrPlan pl{};
+  const int rm = qr_rmax(R);
+  if (rm == 0 || M < R) return pl;
+  const int maxr = qr_max_rpt(rm);
+  for (int rpt = 1; rpt <= maxr; rpt *= 2) {
+    const int64_t rows = (int64_t)QrCfg<32>::NT * rpt;
+    const int64_t P = (M + rows - 1) / rows;
+    int top = 0;
+    if (P > 1) {
+      for (int t = 1; t <= maxr; t *= 2)
+        if ((int64_t)QrCfg<32>::NT * t >= P * R) { top = t; break; }
+      if (top == 0) continue;
+    }
+    pl.ok = true;
+    pl.leaf_rpt = rpt;
+    pl.leaf_rows = rows;
+    pl.P = (int)P;
+    pl.top_rpt = top;
+    return pl;
+  }
+  return pl;
+}
+
+int64_t qr_leaf_rows(int R) { return (int64_t)QrCfg<32>::NT * qr_max_rpt(qr_rmax(R)); }
+
+// Instantiated (RMAX, RPT) pairs.
+#define CPQR_QR_SWITCH(RMAXV, RPTV, BODY)                                              \
+  do {                                                                                 \
+    if (RMAXV == 32) {                                                                 \
+      constexpr int RM = 32;                                                           \
+      if (RPTV == 1) { constexpr int RP = 1; BODY; }                                   \
+      else if (RPTV == 2) { constexpr int RP = 2; BODY; }                              \
+      else return hipErrorInvalidValue;                                                \
+    } else if (RMAXV == 16) {                                                          \
+      constexpr int RM = 16;                                                           \
+      if (RPTV == 1) { constexpr int RP = 1; BODY; }                                   \
+      else if (RPTV == 2) { constexpr int RP = 2; BODY; }                              \
+      else if (RPTV == 4) { constexpr int RP = 4; BODY; }                              \
+      else return hipErrorInvalidValue;                                                \
+    } else if (RMAXV == 8) {                                                           \
+      constexpr int RM = 8;                                                            \
+      if (RPTV == 1) { constexpr int RP = 1; BODY; }                                   \
+      else if (RPTV == 2) { constexpr int RP = 2; BODY; }                              \
+      else if (RPTV == 4) { constexpr int RP = 4; BODY; }                              \
+      else if (RPTV == 8) { constexpr int RP = 8; BODY; }                              \
+      else return hipErrorInvalidValue;                                                \
+    } else {                                                                           \
+      return hipErrorInvalidValue;                                                     \
+    }                                                                                  \
   } while (0)
 
 hipError_t launch_tsqr(const TsqrArgs& t, hipStream_t st) {
-  CPQR_QR_DISPATCH(t.R, {
-    hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3(t.P), dim3(QR_THREADS), 0, st, t.N, t.n, t.R, t.rf,
-                       t.src, t.M, t.V, t.T, t.stack, (int64_t)t.P * t.R);
-    hipLaunchKernelGGL((zqr_top<RM, RP>), dim3(1), dim3(QR_THREADS), 0, st, t.R, (int64_t)t.P * t.R,
-                       t.stack, t.R0, t.Qtop);
-    const unsigned chunks = (unsigned)((t.M + QR_THREADS - 1) / QR_THREADS);
-    hipLaunchKernelGGL((form_q0<RM>), dim3(chunks), dim3(QR_THREADS), 0, st, t.R, t.M,
-                       (int)qr_leaf_rows(t.R), t.V, (int64_t)t.P * qr_leaf_rows(t.R), t.T, t.Qtop,
+  const TsqrPlan pl = tsqr_plan(t.M, t.R);
+  if (!pl.ok || pl.P != t.P) return hipErrorInvalidValue;
+  const int rm = qr_rmax(t.R);
+  const bool single = (t.P == 1);
+  CPQR_QR_SWITCH(rm, pl.leaf_rpt, {
+    hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3(t.P), dim3(QrCfg<RM>::NT), 0, st, t.N, t.n, t.R, t.rf,
+                       t.src, t.M, t.V, t.T, t.stack, (int64_t)t.P * t.R,
+                       single ? t.R0 : nullptr, single ? t.Qtop : nullptr);
+  });
+  if (!single) {
+    CPQR_QR_SWITCH(rm, pl.top_rpt, {
+      hipLaunchKernelGGL((zqr_top<RM, RP>), dim3(1), dim3(QrCfg<RM>::NT), 0, st, t.R,
+                         (int64_t)t.P * t.R, t.stack, t.R0, t.Qtop);
+    });
+  }
+  CPQR_QR_SWITCH(rm, 1, {
+    (void)RP;
+    const unsigned chunks = (unsigned)((t.M + QrCfg<RM>::NT - 1) / QrCfg<RM>::NT);
+    hipLaunchKernelGGL((form_q0<RM>), dim3(chunks), dim3(QrCfg<RM>::NT), 0, st, t.R, t.M,
+                       (int)pl.leaf_rows, t.V, (int64_t)t.P * pl.leaf_rows, t.T, t.Qtop,
                        (int64_t)t.P * t.R, t.Q0);
   });
   return hipGetLastError();
 }
 
+int factor_rpt(int I) { return I <= QrCfg<32>::NT ? 1 : 2; }
+
 hipError_t launch_factor_qr(int I, int R, const double* A, double* Rn, double* q64, float* q32,
                             hipStream_t st) {
-  CPQR_QR_DISPATCH(R, {
-    hipLaunchKernelGGL((factor_qr<RM, RP>), dim3(1), dim3(QR_THREADS), 0, st, I, R, A, Rn, q64, q32);
+  if (I > CPQR_MAX_FACTOR_ROWS) return hipErrorInvalidValue;
+  CPQR_QR_SWITCH(qr_rmax(R), factor_rpt(I), {
+    hipLaunchKernelGGL((factor_qr<RM, RP>), dim3(1), dim3(QrCfg<RM>::NT), 0, st, I, R, A, Rn, q64, q32);
   });
   return hipGetLastError();
 }

@@ -1,36 +1,86 @@
 // Workgroup-level Householder QR of a tall block held in registers, with the
-// compact WY factor T accumulated on the fly (Section 2.4 asks for compact QRs
-// of the factor matrices and of Z_n; the sign convention is a non-negative
-// diagonal of R).
+// compact WY factor T (Section 2.4 asks for compact QRs of the factor
+// matrices and of Z_n; the sign convention is a non-negative diagonal of R).
 //
-// Layout: 256 threads; thread t owns block rows t + 256 p (p < RPT) and keeps
-// the row's RMAX columns in a[p][0..RMAX).  Rows outside the matrix must be
-// zero.  For column j the workgroup reduces, over the rows below the pivot,
-// the R values  sum_i x_i a_i[s]  (s = j gives the squared tail norm, s > j
-// the dot products with the trailing columns, s < j the dot products with the
-// earlier reflectors, which build column j of T).  One wave-level transpose
-// reduction, one LDS exchange and one barrier per column.
+// Layout: NT threads; thread t owns block rows t + NT p (p < RPT) and keeps
+// each row's RMAX columns in vector registers (QrRow), so that the column of
+// the current reflector can be read with one indexed register move.  Rows
+// outside the matrix must be zero.  For column j the workgroup reduces, over
+// the rows below the pivot, the RMAX values  sum_i x_i a_i[s]  (s = j gives
+// the squared tail norm, s > j the dot products with the trailing columns,
+// s < j the dot products with the earlier reflectors, which build T).  Per
+// column: one wave-level transpose reduction, an LDS exchange, the reflector
+// scalars computed once by wave 0, and two barriers.
 //
 // Reflector convention: x = column j from row j down; if the part below the
 // pivot is exactly zero the reflector is the identity (tau = 0); otherwise
 // beta = -sign(x0) ||x||, v = x / (x0 - beta) with v_j = 1, tau = (beta - x0) / beta.
 // Then H_1 ... H_R = I - V T V^T with T upper triangular.
+//
+// Storage after the factorisation: below the diagonal, column j keeps x (the
+// column as it was when its reflector was formed); the reflector is
+// v = x * scale_j with scale_j = 1 / (x0 - beta) kept in LDS.  The pivot row j
+// holds R[j][c] for c > j; R[j][j] = beta_j is kept in LDS.
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 
 namespace cpqr {
 
-static constexpr int QR_THREADS = 256;
-static constexpr int QR_WAVES = QR_THREADS / 64;
+// Workgroup size of the QR kernels: 256 threads, one wave per SIMD, so that
+// each wave may use the whole register file (architectural plus accumulation
+// registers) to keep its rows of the block resident.
+template <int RMAX>
+struct QrCfg {
+  static constexpr int NT = 256;
+  static constexpr int NW = NT / 64;
+};
+static constexpr int QR_MAX_WAVES = 4;
+
+// Kernel attributes of the QR kernels: the workgroup size above, and the
+// register budget of one workgroup per CU (the factorisation keeps its whole
+// block in registers).
+#define CPQR_QR_KERNEL(RMAX)                        \
+  __launch_bounds__(QrCfg<RMAX>::NT)                \
+  __attribute__((amdgpu_waves_per_eu(1, 1)))
+
+typedef double f64x8 __attribute__((ext_vector_type(8)));
+typedef double f64x16 __attribute__((ext_vector_type(16)));
+
+// One row of the block: RMAX doubles in one or two register vectors of at
+// most 16 elements (the largest the indexed register moves handle).
+template <int RMAX>
+struct QrRow {
+  static constexpr int HW = RMAX > 16 ? 16 : RMAX;
+  static constexpr int NH = RMAX / HW;
+  using Vec = typename std::conditional<HW == 16, f64x16, f64x8>::type;
+  Vec h[NH];
+  __device__ __forceinline__ double get(int c) const {
+    if constexpr (NH == 1) return h[0][c];
+    else return (c < HW) ? h[0][c & (HW - 1)] : h[1][c & (HW - 1)];
+  }
+  __device__ __forceinline__ void set(int c, double x) {
+    if constexpr (NH == 1) h[0][c] = x;
+    else {
+      if (c < HW) h[0][c & (HW - 1)] = x;
+      else h[1][c & (HW - 1)] = x;
+    }
+  }
+};
 
 // LDS used by the factorisation itself.
 template <int RMAX>
 struct QrSmem {
   double piv[2][RMAX];
-  double red[2][QR_WAVES][RMAX];
+  double red[2][QR_MAX_WAVES][RMAX];
+  double w[2][RMAX + 4];       // w_c (zero for c <= j), then tau, beta, scale
+  double U[RMAX][RMAX + 1];    // U[m][j] = (V^T v_j)_m for m < j
   double T[RMAX][RMAX + 1];
+  double tau[RMAX];
   double beta[RMAX];
+  double scale[RMAX];
   double sgn[RMAX];
 };
 
@@ -43,46 +93,45 @@ struct QrWySmem {
   double M[RMAX][RMAX + 1];    // T V1^T B
 };
 
-// Factor the block in a[][] (R <= RMAX columns).  On return:
-//   a[p][c] for rows i > c holds V[i][c]; the pivot row j holds beta_j at
-//   column j and R[j][c] for c > j;  sm.T = T, sm.beta[j] = beta_j.
+// Factor the block (R <= RMAX columns); see the storage note above.
 template <int RMAX, int RPT>
-__device__ void block_qr(double (&a)[RPT][RMAX], int R, QrSmem<RMAX>& sm) {
+__device__ __forceinline__ void block_qr(QrRow<RMAX> (&a)[RPT], int R, QrSmem<RMAX>& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < RMAX * (RMAX + 1); e += QR_THREADS) (&sm.T[0][0])[e] = 0.0;
-  __syncthreads();
+  constexpr int NT = QrCfg<RMAX>::NT;
+  for (int j = 0; j < R; ++j) {
+    const int buf = j & 1;
+    if (tid == j) {
 #pragma unroll
-  for (int j = 0; j < RMAX; ++j) {
-    if (j < R) {
-      const int buf = j & 1;
-      if (tid == j) {
+      for (int c = 0; c < RMAX; ++c) sm.piv[buf][c] = a[0].get(c);
+    }
+    // x = column j below the pivot (indexed register read)
+    double x[RPT];
 #pragma unroll
-        for (int c = 0; c < RMAX; ++c) sm.piv[buf][c] = a[0][c];
+    for (int p = 0; p < RPT; ++p) {
+      const double v = a[p].get(j);
+      x[p] = (tid + NT * p > j) ? v : 0.0;
+    }
+    double part[RMAX];
+#pragma unroll
+    for (int s = 0; s < RMAX; ++s) {
+      double acc = 0.0;
+#pragma unroll
+      for (int p = 0; p < RPT; ++p) acc = fma(x[p], a[p].get(s), acc);
+      part[s] = acc;
+    }
+    wave_transpose_reduce<RMAX>(part);
+    constexpr int G = 64 / RMAX;
+    if ((lane % G) == 0) sm.red[buf][wave][lane / G] = part[0];
+    __syncthreads();
+    if (wave == 0) {
+      // lane c < RMAX: tot = sum_i x_i a_i[c] over the rows below the pivot
+      double tot = 0.0;
+      if (lane < RMAX) {
+#pragma unroll
+        for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
       }
-      double part[RMAX];
-#pragma unroll
-      for (int s = 0; s < RMAX; ++s) part[s] = 0.0;
-#pragma unroll
-      for (int p = 0; p < RPT; ++p) {
-        const int row = tid + QR_THREADS * p;
-        const double x = (row > j) ? a[p][j] : 0.0;
-#pragma unroll
-        for (int s = 0; s < RMAX; ++s) part[s] = fma(x, a[p][s], part[s]);
-      }
-      wave_transpose_reduce<RMAX>(part);
-      constexpr int G = 64 / RMAX;
-      if ((lane % G) == 0) sm.red[buf][wave][lane / G] = part[0];
-      __syncthreads();
-      double tot[RMAX], pv[RMAX];
-#pragma unroll
-      for (int s = 0; s < RMAX; ++s) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < QR_WAVES; ++w) t += sm.red[buf][w][s];
-        tot[s] = t;
-        pv[s] = sm.piv[buf][s];
-      }
-      const double x0 = pv[j], st = tot[j];
+      const double st = __shfl(tot, j, 64);
+      const double x0 = sm.piv[buf][j];
       double tau, beta, scale;
       if (st == 0.0) {
         tau = 0.0;
@@ -91,62 +140,92 @@ __device__ void block_qr(double (&a)[RPT][RMAX], int R, QrSmem<RMAX>& sm) {
       } else {
         const double nrm = sqrt(fma(x0, x0, st));
         beta = (x0 >= 0.0) ? -nrm : nrm;
-        tau = (beta - x0) / beta;
-        scale = 1.0 / (x0 - beta);
+        const double d = x0 - beta;   // nonzero: |d| >= nrm
+        tau = -d / beta;
+        scale = 1.0 / d;
       }
-      double w[RMAX];
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) w[c] = (c > j) ? fma(scale, tot[c], pv[c]) : 0.0;
-#pragma unroll
-      for (int p = 0; p < RPT; ++p) {
-        const int row = tid + QR_THREADS * p;
-        if (row > j) {
-          const double v = a[p][j] * scale;
-          a[p][j] = v;
-          const double tv = tau * v;
-#pragma unroll
-          for (int c = j + 1; c < RMAX; ++c) a[p][c] = fma(-tv, w[c], a[p][c]);
-        } else if (row == j) {
-          a[p][j] = beta;
-#pragma unroll
-          for (int c = j + 1; c < RMAX; ++c) a[p][c] = fma(-tau, w[c], a[p][c]);
-        }
+      if (lane < RMAX) {
+        // c > j: w_c = a_j[c] + scale * sum_{i>j} x_i a_i[c]  (v^T a_c with v_j = 1)
+        // m < j: u_m = (V^T v_j)_m = scale_m (x_m[j] + scale * sum_{i>j} x_i x_m[i])
+        const double pc = sm.piv[buf][lane];
+        const double wu = fma(scale, tot, pc);
+        sm.w[buf][lane] = (lane > j) ? wu : 0.0;
+        sm.U[lane][j] = (lane < j) ? wu * sm.scale[lane] : 0.0;
       }
-      // column j of T:  T[k][j] = -tau sum_{m<j} T[k][m] u_m,  u_m = (V^T v_j)_m
-      if (tid < j) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < j; ++m) acc = fma(sm.T[tid][m], fma(scale, tot[m], pv[m]), acc);
-        sm.T[tid][j] = -tau * acc;
-      }
-      if (tid == j) {
-        sm.T[j][j] = tau;
+      if (lane == 0) {
+        sm.w[buf][RMAX] = tau;
+        sm.w[buf][RMAX + 1] = beta;
+        sm.w[buf][RMAX + 2] = scale;
+        sm.tau[j] = tau;
         sm.beta[j] = beta;
+        sm.scale[j] = scale;
       }
+    }
+    __syncthreads();
+    const double tau = sm.w[buf][RMAX];
+    const double scale = sm.w[buf][RMAX + 2];
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) {
+      // rows below the pivot: a -= tau v w^T with v = x scale; the pivot
+      // row: a -= tau w^T (v_j = 1); w vanishes for c <= j
+      const int row = tid + NT * p;
+      const double coef = (row > j) ? tau * x[p] * scale : ((row == j) ? tau : 0.0);
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) a[p].set(c, fma(-coef, sm.w[buf][c], a[p].get(c)));
+    }
+  }
+  __syncthreads();
+  // T (upper triangular), row by row: T[k][k] = tau_k,
+  // T[k][j] = -tau_j sum_{m=k}^{j-1} T[k][m] U[m][j]  (j > k)
+  for (int e = tid; e < RMAX * (RMAX + 1); e += NT) (&sm.T[0][0])[e] = 0.0;
+  __syncthreads();
+  if (tid < R) {
+    const int k = tid;
+    sm.T[k][k] = sm.tau[k];
+    for (int j = k + 1; j < R; ++j) {
+      double acc = 0.0;
+      for (int m = k; m < j; ++m) acc = fma(sm.T[k][m], sm.U[m][j], acc);
+      sm.T[k][j] = -sm.tau[j] * acc;
     }
   }
   __syncthreads();
 }
 
+// Element (row, c) of the reflector matrix V (unit lower trapezoidal) for a
+// row held by this thread as a[p].
+template <int RMAX, int RPT>
+__device__ __forceinline__ double block_qr_v(const QrRow<RMAX> (&a)[RPT], int p, int row, int c,
+                                             const QrSmem<RMAX>& sm) {
+  return (row > c) ? a[p].get(c) * sm.scale[c] : ((row == c) ? 1.0 : 0.0);
+}
+
+// Element (j, c) of the R factor (before the sign fix), from the thread that
+// holds row j in `row0`.
+template <int RMAX>
+__device__ __forceinline__ double block_qr_r(const QrRow<RMAX>& row0, int j, int c,
+                                             const QrSmem<RMAX>& sm) {
+  return (c > j) ? row0.get(c) : ((c == j) ? sm.beta[j] : 0.0);
+}
+
 // After block_qr: publish the first R rows of V and the R factor to LDS,
 // optionally fixing signs so that diag(R) >= 0 (sm.sgn holds the signs).
 template <int RMAX, int RPT>
-__device__ void block_qr_publish(const double (&a)[RPT][RMAX], int R, QrSmem<RMAX>& sm,
-                                 QrWySmem<RMAX>& wy, bool fix_sign) {
+__device__ __forceinline__ void block_qr_publish(const QrRow<RMAX> (&a)[RPT], int R, QrSmem<RMAX>& sm,
+                                                 QrWySmem<RMAX>& wy, bool fix_sign) {
   const int tid = threadIdx.x;
   if (tid < RMAX) {
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
       const bool in = (tid < R) && (c < R);
-      wy.V1[tid][c] = !in ? 0.0 : (c < tid ? a[0][c] : (c == tid ? 1.0 : 0.0));
+      wy.V1[tid][c] = in ? block_qr_v<RMAX, RPT>(a, 0, tid, c, sm) : 0.0;
     }
     double sg = 1.0;
     if (fix_sign && tid < R && sm.beta[tid] < 0.0) sg = -1.0;
     sm.sgn[tid] = sg;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
-      const bool in = (tid < R) && (c < R) && (c >= tid);
-      wy.Rm[tid][c] = in ? sg * a[0][c] : 0.0;
+      const bool in = (tid < R) && (c < R);
+      wy.Rm[tid][c] = in ? sg * block_qr_r<RMAX>(a[0], tid, c, sm) : 0.0;
     }
   }
   __syncthreads();
@@ -155,10 +234,10 @@ __device__ void block_qr_publish(const double (&a)[RPT][RMAX], int R, QrSmem<RMA
 // wy.M = T * (V1^T * B) where B (R x R) is row-major in LDS with leading
 // dimension ldb, or B = I when B == nullptr.
 template <int RMAX>
-__device__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWySmem<RMAX>& wy, int R,
-                                    const double* B, int ldb) {
+__device__ __forceinline__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWySmem<RMAX>& wy, int R,
+                                                    const double* B, int ldb) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < RMAX * RMAX; e += QR_THREADS) {
+  for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
     const int k = e / RMAX, c = e % RMAX;
     double acc = 0.0;
     if (k < R && c < R) {
@@ -171,7 +250,7 @@ __device__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWySmem<RMAX>& wy, 
     wy.W[k][c] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < RMAX * RMAX; e += QR_THREADS) {
+  for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
     const int k = e / RMAX, c = e % RMAX;
     double acc = 0.0;
     for (int m = k; m < R; ++m) acc = fma(sm.T[k][m], wy.W[m][c], acc);
@@ -180,35 +259,28 @@ __device__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWySmem<RMAX>& wy, 
   __syncthreads();
 }
 
-// Row i (block-local) of the explicit Q = (E - V M) with E the first R
-// columns of the identity, M = T V1^T (B = I case), times the sign fix.
-template <int RMAX, int RPT>
-__device__ inline void block_qr_q_row(const double (&a)[RPT][RMAX], int p, int R,
-                                      const QrSmem<RMAX>& sm, const QrWySmem<RMAX>& wy,
-                                      double (&q)[RMAX]) {
-  const int row = threadIdx.x + QR_THREADS * p;
+// Row `row` (block-local) of the explicit Q = (E - V M) * diag(sgn) with
+// M = T V1^T: store(c, value) for c < R; run-time loop over c.
+template <int RMAX, int RPT, typename Store>
+__device__ __forceinline__ void block_qr_q_row(const QrRow<RMAX> (&a)[RPT], int p, int R,
+                                               const QrSmem<RMAX>& sm, const QrWySmem<RMAX>& wy,
+                                               Store&& store) {
+  const int row = threadIdx.x + QrCfg<RMAX>::NT * p;
+  double v[RMAX];
 #pragma unroll
-  for (int c = 0; c < RMAX; ++c) q[c] = (row == c) ? 1.0 : 0.0;
+  for (int m = 0; m < RMAX; ++m) v[m] = (m < R) ? block_qr_v<RMAX, RPT>(a, p, row, m, sm) : 0.0;
+  for (int c = 0; c < R; ++c) {
+    double acc = (row == c) ? 1.0 : 0.0;
 #pragma unroll
-  for (int m = 0; m < RMAX; ++m) {
-    const double v = (row > m) ? a[p][m] : ((row == m) ? 1.0 : 0.0);
-    if (m < R) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) q[c] = fma(-v, wy.M[m][c], q[c]);
-    }
+    for (int m = 0; m < RMAX; ++m) acc = fma(-v[m], wy.M[m][c], acc);
+    store(c, acc * sm.sgn[c]);
   }
-#pragma unroll
-  for (int c = 0; c < RMAX; ++c) q[c] *= sm.sgn[c];
 }
 
-}  // namespace cpqr
-
-namespace cpqr {
-
 // Sum V doubles over the whole workgroup; every thread receives the totals.
-// `red` is LDS scratch of QR_WAVES x V doubles.
-template <int V>
-__device__ void block_allreduce(double (&v)[V], double (*red)[V]) {
+// `red` is LDS scratch of NW x V doubles (NW = waves in the workgroup).
+template <int V, int NW>
+__device__ __forceinline__ void block_allreduce(double (&v)[V], double (*red)[V]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   wave_transpose_reduce<V>(v);
   constexpr int G = 64 / V;
@@ -218,7 +290,7 @@ __device__ void block_allreduce(double (&v)[V], double (*red)[V]) {
   for (int s = 0; s < V; ++s) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < QR_WAVES; ++w) t += red[w][s];
+    for (int w = 0; w < NW; ++w) t += red[w][s];
     v[s] = t;
   }
   __syncthreads();

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -40,6 +41,7 @@ struct cpqr_handle {
   hipEvent_t ready = nullptr;
   std::string err;
   std::map<std::string, DevBuf> bufs;
+  bool busy = false;                  // a session is using the workspace
 };
 
 namespace {
@@ -137,6 +139,33 @@ int64_t inter_elems(const Problem& p, uint32_t mask) {
   return n;
 }
 
+}  // namespace
+
+struct cpqr_session {
+  cpqr_handle* h = nullptr;
+  cpqr_options opts;
+  Problem p;
+  std::vector<std::vector<Step>> sched;
+  int64_t nelem = 0;
+  double nx2 = 0.0;
+  int k = 0;                  // sweeps enqueued
+  bool stopped = false;       // tolerance reached
+  double ttm_flops = 0, ttm_bytes = 0, l1_bytes = 0, l1_flops = 0;
+  int l1_count = 0;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  bool t0_recorded = false;
+  std::vector<hipEvent_t> evs;
+  std::map<std::string, hipGraphExec_t> graphs;
+  ~cpqr_session() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+  }
+};
+
+namespace {
+
 cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
                   const std::vector<std::vector<Step>>& sched) {
   const int N = p.N, R = p.R;
@@ -152,8 +181,10 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   WS(h, "rf", (size_t)N * R * R * 8, p.rf);
   WS(h, "lambda", (size_t)R * 8, p.lambda);
   p.M = ipow(R, N - 1);
-  p.leaf_rows = qr_leaf_rows(R);
-  p.P = (int)((p.M + p.leaf_rows - 1) / p.leaf_rows);
+  const TsqrPlan pl = tsqr_plan(p.M, R);
+  if (!pl.ok) return fail(h, CPQR_EUNSUPPORTED, "no TSQR plan for %lld x %d", (long long)p.M, R);
+  p.leaf_rows = pl.leaf_rows;
+  p.P = pl.P;
   for (int k = 0; k < N; ++k) WS(h, "q0_" + std::to_string(k), (size_t)2 * p.M * R * 8, p.q0buf[k]);
   WS(h, "tsqrV", (size_t)p.P * p.leaf_rows * R * 8, p.tV);
   WS(h, "tsqrT", (size_t)p.P * R * R * 8, p.tT);
@@ -293,14 +324,11 @@ cpqr_status check_args(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpq
   if (rank > 32) return fail(h, CPQR_EUNSUPPORTED, "rank > 32 is not supported by this build");
   for (int k = 0; k < N; ++k) {
     if (X->dims[k] < rank) return fail(h, CPQR_EUNSUPPORTED, "mode %d has size %lld < rank %d", k, (long long)X->dims[k], rank);
-    if (X->dims[k] > 512) return fail(h, CPQR_EUNSUPPORTED, "mode size > 512 is not supported by this build");
+    if (X->dims[k] > CPQR_MAX_FACTOR_ROWS)
+      return fail(h, CPQR_EUNSUPPORTED, "mode size > %d is not supported by this build", CPQR_MAX_FACTOR_ROWS);
   }
-  {
-    const int64_t M = ipow(rank, N - 1);
-    const int64_t leaf = qr_leaf_rows(rank);
-    const int64_t P = (M + leaf - 1) / leaf;
-    if (P * rank > leaf) return fail(h, CPQR_EUNSUPPORTED, "R^(N-1) too large for a two-level TSQR at this rank");
-  }
+  if (N > qr_max_order(rank) || !tsqr_plan(ipow(rank, N - 1), rank).ok)
+    return fail(h, CPQR_EUNSUPPORTED, "R^(N-1) too large for a two-level TSQR at this rank");
   if (o->prec == CPQR_PREC_BF16X3)
     for (int k = 0; k < N; ++k)
       if (!ttm_mfma_supported((int)X->dims[k], rank)) return fail(h, CPQR_EUNSUPPORTED, "bf16x3 TTM limits");
@@ -444,9 +472,10 @@ cpqr_status cpqr_qr(cpqr_handle* h, int64_t M, int R, const double* A, double* Q
   if (!A || !Q || !Rout) return fail(h, CPQR_EINVAL, "null pointer");
   if (R < 1 || M < R) return fail(h, CPQR_EINVAL, "need 1 <= R <= M");
   if (R > 32) return fail(h, CPQR_EUNSUPPORTED, "R > 32");
-  const int64_t leaf = qr_leaf_rows(R);
-  const int64_t P = (M + leaf - 1) / leaf;
-  if (P * R > leaf) return fail(h, CPQR_EUNSUPPORTED, "M too large for a two-level TSQR at this R");
+  const TsqrPlan pl = tsqr_plan(M, R);
+  if (!pl.ok) return fail(h, CPQR_EUNSUPPORTED, "M too large for a two-level TSQR at this R");
+  const int64_t leaf = pl.leaf_rows;
+  const int64_t P = pl.P;
   HIP_TRY(h, hipSetDevice(h->device));
   HIP_TRY(h, order_after_user(h));
   TsqrArgs t;
@@ -472,24 +501,29 @@ cpqr_status cpqr_check_args(const cpqr_tensor* X, int rank, const cpqr_options* 
   return check_args(nullptr, X, rank, o);
 }
 
-cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpqr_options* o,
-                        cpqr_result* res) {
+cpqr_status cpqr_session_create(cpqr_handle* h, const cpqr_tensor* X, int rank,
+                                const cpqr_options* o, cpqr_session** out) {
   if (!h) return CPQR_EINVAL;
   h->err.clear();
-  if (!res) return fail(h, CPQR_EINVAL, "null argument");
+  if (!out) return fail(h, CPQR_EINVAL, "null session pointer");
+  *out = nullptr;
   {
     cpqr_status v = check_args(h, X, rank, o);
     if (v != CPQR_OK) return v;
   }
+  if (h->busy) return fail(h, CPQR_EINVAL, "the handle already has a live session");
   const int N = X->order;
-  std::vector<std::vector<Step>> sched;
-  if (!build_schedule(N, o->tree, o->iters, sched) || !validate_schedule(N, sched))
+  std::unique_ptr<cpqr_session> ss(new cpqr_session());
+  cpqr_session& S = *ss;
+  S.h = h;
+  S.opts = *o;
+  S.opts.init_factors = nullptr;
+  if (!build_schedule(N, o->tree, o->iters, S.sched) || !validate_schedule(N, S.sched))
     return fail(h, CPQR_EINVAL, "schedule construction failed");
-
   HIP_TRY(h, hipSetDevice(h->device));
   HIP_TRY(h, order_after_user(h));
   hipStream_t s = h->stream;
-  Problem p;
+  Problem& p = S.p;
   p.N = N;
   p.R = rank;
   p.prec = o->prec;
@@ -497,62 +531,69 @@ cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cp
   p.X = X->data;
   p.f64 = (o->prec == CPQR_PREC_FP64);
   p.elem = p.f64 ? 8 : 4;
-  cpqr_status stt = setup(h, p, o->iters, sched);
+  cpqr_status stt = setup(h, p, o->iters, S.sched);
   if (stt != CPQR_OK) return stt;
-
-  int64_t nelem = 1;
-  for (int k = 0; k < N; ++k) nelem *= p.dims[k];
-  // ||X||^2 and state
-  HIP_TRY(h, launch_sumsq(p.X, p.f64, nelem, p.norm_part, s));
-  HIP_TRY(h, launch_state_init(p.state, p.norm_part, sumsq_blocks(nelem), s));
-  // initial factors and their QRs
+  S.nelem = 1;
+  for (int k = 0; k < N; ++k) S.nelem *= p.dims[k];
+  // ||X||^2 and the device state
+  HIP_TRY(h, launch_sumsq(p.X, p.f64, S.nelem, p.norm_part, s));
+  HIP_TRY(h, launch_state_init(p.state, p.norm_part, sumsq_blocks(S.nelem), s));
+  // initial factors and their QRs (Algorithm 2, "Initialize")
   for (int k = 0; k < N; ++k) {
-    HIP_TRY(h, hipMemcpyAsync(p.A[k], o->init_factors[k], (size_t)p.dims[k] * rank * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(p.A[k], o->init_factors[k], (size_t)p.dims[k] * rank * 8,
+                              hipMemcpyHostToDevice, s));
     HIP_TRY(h, launch_factor_qr((int)p.dims[k], rank, p.A[k], p.rf + (size_t)k * rank * rank,
                                 p.f64 ? (double*)p.Q[k] : nullptr, p.f64 ? nullptr : (float*)p.Q[k], s));
   }
-  {
-    DevState hs;
-    HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(h, hipStreamSynchronize(s));
-    if (!(hs.nx2 > 0.0)) {
-      if (hs.flags & FLAG_NONFINITE) return fail(h, CPQR_ENONFINITE, "tensor contains NaN or Inf");
-      return fail(h, CPQR_EINVAL, "||X|| = 0");
-    }
+  DevState hs;
+  HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  if (!(hs.nx2 > 0.0)) {
+    if (hs.flags & FLAG_NONFINITE) return fail(h, CPQR_ENONFINITE, "tensor contains NaN or Inf");
+    return fail(h, CPQR_EINVAL, "||X|| = 0");
   }
+  S.nx2 = hs.nx2;
+  HIP_TRY(h, hipEventCreate(&S.t0));
+  HIP_TRY(h, hipEventCreate(&S.t1));
+  h->busy = true;
+  *out = ss.release();
+  return CPQR_OK;
+}
 
+cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
+  if (!S) return CPQR_EINVAL;
+  cpqr_handle* h = S->h;
+  h->err.clear();
+  if (nsweeps < 0) return fail(h, CPQR_EINVAL, "nsweeps must be >= 0");
+  if (S->stopped) return CPQR_OK;
+  if (S->k + nsweeps > S->opts.iters)
+    return fail(h, CPQR_EINVAL, "session was created for %d sweeps", S->opts.iters);
+  HIP_TRY(h, hipSetDevice(h->device));
+  HIP_TRY(h, order_after_user(h));
+  hipStream_t s = h->stream;
+  const cpqr_options* o = &S->opts;
+  Problem& p = S->p;
+  const int N = p.N;
   const bool timing = (o->flags & CPQR_FLAG_TIME_KERNELS) != 0;
   const bool use_graph = !timing && !(o->flags & CPQR_FLAG_NO_GRAPH);
   const uint32_t full = (1u << N) - 1u;
-  std::vector<hipEvent_t> evs;
-  hipEvent_t t0, t1;
-  HIP_TRY(h, hipEventCreate(&t0));
-  HIP_TRY(h, hipEventCreate(&t1));
-  double ttm_flops = 0, ttm_bytes = 0, l1_bytes = 0, l1_flops = 0;
-  int l1_count = 0;
-  int sweeps_done = 0;
-  std::vector<double> fits(o->iters, std::nan(""));
-  cpqr_status result = CPQR_OK;
-  // sweeps with the same step list and Q0 ping-pong parity share one graph;
-  // graphs live for this call only (they bake in workspace pointers)
-  struct GraphCache {
-    std::map<std::string, hipGraphExec_t> g;
-    ~GraphCache() { for (auto& kv : g) (void)hipGraphExecDestroy(kv.second); }
-  } graphs;
-  HIP_TRY(h, hipEventRecord(t0, s));
-  for (int k = 1; k <= o->iters; ++k) {
-    const auto& sw = sched[k - 1];
-    // statistics
+  if (!S->t0_recorded) {
+    HIP_TRY(h, hipEventRecord(S->t0, s));
+    S->t0_recorded = true;
+  }
+  for (int it = 0; it < nsweeps; ++it) {
+    const int k = S->k + 1;
+    const auto& sw = S->sched[k - 1];
     for (const Step& st : sw)
       if (st.kind == STEP_TTM) {
         const int64_t in = inter_elems(p, st.src);
-        const int64_t out = in / p.dims[st.mode] * p.R;
-        ttm_flops += 2.0 * in * p.R;
-        ttm_bytes += (double)(in + out) * p.elem;
+        const int64_t outn = in / p.dims[st.mode] * p.R;
+        S->ttm_flops += 2.0 * in * p.R;
+        S->ttm_bytes += (double)(in + outn) * p.elem;
         if (st.src == full) {
-          l1_bytes += (double)(in + out) * p.elem;
-          l1_flops += 2.0 * in * p.R;
-          ++l1_count;
+          S->l1_bytes += (double)(in + outn) * p.elem;
+          S->l1_flops += 2.0 * in * p.R;
+          ++S->l1_count;
         }
       }
     int last_update = -1;
@@ -567,8 +608,8 @@ cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cp
             hipEvent_t a, b;
             if ((e = hipEventCreate(&a)) != hipSuccess) return e;
             if ((e = hipEventCreate(&b)) != hipSuccess) return e;
-            evs.push_back(a);
-            evs.push_back(b);
+            S->evs.push_back(a);
+            S->evs.push_back(b);
             if ((e = hipEventRecord(a, q)) != hipSuccess) return e;
             if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
             if ((e = hipEventRecord(b, q)) != hipSuccess) return e;
@@ -582,9 +623,10 @@ cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cp
       return hipSuccess;
     };
     if (use_graph) {
+      // sweeps with the same step list and Q0 ping-pong parity share a graph
       const std::string key = sweep_key(sw, k == 1 ? 2 : (k % 2), o->extrapolate != 0);
-      auto it = graphs.g.find(key);
-      if (it == graphs.g.end()) {
+      auto itg = S->graphs.find(key);
+      if (itg == S->graphs.end()) {
         hipGraph_t g;
         HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         hipError_t e = enqueue(s);
@@ -592,76 +634,95 @@ cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cp
         if (e != hipSuccess) return fail(h, CPQR_EHIP, "kernel launch during capture failed: %s", hipGetErrorString(e));
         if (e2 != hipSuccess) return fail(h, CPQR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
         hipGraphExec_t ge;
-        HIP_TRY(h, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
-        HIP_TRY(h, hipGraphDestroy(g));
-        it = graphs.g.emplace(key, ge).first;
+        hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) return fail(h, CPQR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+        itg = S->graphs.emplace(key, ge).first;
       }
-      HIP_TRY(h, hipGraphLaunch(it->second, s));
+      HIP_TRY(h, hipGraphLaunch(itg->second, s));
     } else {
       hipError_t e = enqueue(s);
       if (e != hipSuccess) return fail(h, CPQR_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
     }
-    sweeps_done = k;
+    S->k = k;
     if (o->tol > 0.0 && k >= 2) {
       DevState hs;
       HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
       double fk[2];
       HIP_TRY(h, hipMemcpyAsync(fk, p.fit_hist + (k - 2), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(h, hipStreamSynchronize(s));
-      if (hs.flags) break;
-      if (std::fabs(fk[1] - fk[0]) < o->tol) break;
+      if (hs.flags || std::fabs(fk[1] - fk[0]) < o->tol) {
+        S->stopped = true;
+        break;
+      }
     }
   }
-  HIP_TRY(h, hipEventRecord(t1, s));
-  HIP_TRY(h, hipEventSynchronize(t1));
+  return CPQR_OK;
+}
+
+cpqr_status cpqr_session_sync(cpqr_session* S) {
+  if (!S) return CPQR_EINVAL;
+  cpqr_handle* h = S->h;
+  HIP_TRY(h, hipSetDevice(h->device));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return CPQR_OK;
+}
+
+cpqr_status cpqr_session_result(cpqr_session* S, cpqr_result* res) {
+  if (!S || !res) return CPQR_EINVAL;
+  cpqr_handle* h = S->h;
+  h->err.clear();
+  HIP_TRY(h, hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  Problem& p = S->p;
+  const int N = p.N, rank = p.R;
+  const int done = S->k;
+  HIP_TRY(h, hipEventRecord(S->t1, s));
+  HIP_TRY(h, hipEventSynchronize(S->t1));
   float ms = 0.f;
-  HIP_TRY(h, hipEventElapsedTime(&ms, t0, t1));
+  if (S->t0_recorded) HIP_TRY(h, hipEventElapsedTime(&ms, S->t0, S->t1));
   double l1_sec = 0.0;
-  for (size_t i = 0; i + 1 < evs.size(); i += 2) {
+  for (size_t i = 0; i + 1 < S->evs.size(); i += 2) {
     float e = 0.f;
-    HIP_TRY(h, hipEventElapsedTime(&e, evs[i], evs[i + 1]));
+    HIP_TRY(h, hipEventElapsedTime(&e, S->evs[i], S->evs[i + 1]));
     l1_sec += e * 1e-3;
   }
-  for (hipEvent_t e : evs) (void)hipEventDestroy(e);
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
-
   DevState hs;
   HIP_TRY(h, hipMemcpy(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost));
-  HIP_TRY(h, hipMemcpy(fits.data(), p.fit_hist, (size_t)sweeps_done * 8, hipMemcpyDeviceToHost));
-  res->sweeps_done = sweeps_done;
+  std::vector<double> fits(done > 0 ? done : 1);
+  if (done > 0) HIP_TRY(h, hipMemcpy(fits.data(), p.fit_hist, (size_t)done * 8, hipMemcpyDeviceToHost));
+  res->sweeps_done = done;
   if (res->fit_history)
-    for (int k = 0; k < sweeps_done; ++k) res->fit_history[k] = fits[k];
-  if (hs.flags & FLAG_NONFINITE) result = fail(h, CPQR_ENONFINITE, "non-finite value in the fit or lambda");
-  else if (hs.flags & FLAG_RANKDEF) result = fail(h, CPQR_ERANKDEF, "zero column norm or zero diagonal in R0/R_n");
-  if (result != CPQR_OK) return result;
-
+    for (int k = 0; k < done; ++k) res->fit_history[k] = fits[k];
+  if (hs.flags & FLAG_NONFINITE) return fail(h, CPQR_ENONFINITE, "non-finite value in the fit or lambda");
+  if (hs.flags & FLAG_RANKDEF) return fail(h, CPQR_ERANKDEF, "zero column norm or zero diagonal in R0/R_n");
   if (res->factors)
     for (int k = 0; k < N; ++k)
       if (res->factors[k])
         HIP_TRY(h, hipMemcpy(res->factors[k], p.A[k], (size_t)p.dims[k] * rank * 8, hipMemcpyDeviceToHost));
   if (res->lambda) HIP_TRY(h, hipMemcpy(res->lambda, p.lambda, (size_t)rank * 8, hipMemcpyDeviceToHost));
   if (res->sweep_orders)
-    for (int k = 0; k < sweeps_done; ++k) {
+    for (int k = 0; k < done; ++k) {
       int u = 0;
-      for (const Step& st : sched[k])
+      for (const Step& st : S->sched[k])
         if (st.kind == STEP_UPDATE) res->sweep_orders[k * N + (u++)] = st.mode;
     }
   res->fit = hs.fit;
   res->beta = hs.active ? hs.beta : 0.0;
   res->beta_sweep = hs.active ? hs.beta_sweep : 0;
-  res->ttm_flops = ttm_flops;
-  res->ttm_bytes = ttm_bytes;
+  res->ttm_flops = S->ttm_flops;
+  res->ttm_bytes = S->ttm_bytes;
   res->seconds = ms * 1e-3;
+  const bool timing = (S->opts.flags & CPQR_FLAG_TIME_KERNELS) != 0;
   res->l1_ttm_seconds = l1_sec;
-  res->l1_ttm_launches = timing ? l1_count : 0;
-  res->l1_ttm_bytes = l1_count ? l1_bytes / l1_count : 0.0;
-  res->l1_ttm_flops = l1_count ? l1_flops / l1_count : 0.0;
+  res->l1_ttm_launches = timing ? (int)(S->evs.size() / 2) : 0;
+  res->l1_ttm_bytes = S->l1_count ? S->l1_bytes / S->l1_count : 0.0;
+  res->l1_ttm_flops = S->l1_count ? S->l1_flops / S->l1_count : 0.0;
   res->fit_explicit = std::nan("");
-  if (o->flags & CPQR_FLAG_EXPLICIT_FIT) {
+  if (S->opts.flags & CPQR_FLAG_EXPLICIT_FIT) {
     std::vector<double*> fac(p.A.begin(), p.A.end());
     HIP_TRY(h, launch_residual(p.X, p.f64, N, p.dims.data(), fac.data(), p.lambda, rank, p.norm_part, s));
-    const int nb = sumsq_blocks(nelem);
+    const int nb = sumsq_blocks(S->nelem);
     std::vector<double> part(nb);
     HIP_TRY(h, hipMemcpyAsync(part.data(), p.norm_part, nb * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
@@ -670,6 +731,41 @@ cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cp
     res->fit_explicit = 1.0 - std::sqrt(r2) / std::sqrt(hs.nx2);
   }
   return CPQR_OK;
+}
+
+cpqr_status cpqr_session_destroy(cpqr_session* S) {
+  if (!S) return CPQR_EINVAL;
+  cpqr_handle* h = S->h;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  delete S;
+  h->busy = false;
+  return CPQR_OK;
+}
+
+cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpqr_options* o,
+                        cpqr_result* res) {
+  if (!h) return CPQR_EINVAL;
+  if (!res) return fail(h, CPQR_EINVAL, "null argument");
+  cpqr_session* S = nullptr;
+  cpqr_status st = cpqr_session_create(h, X, rank, o, &S);
+  if (st != CPQR_OK) return st;
+  st = cpqr_session_sweeps(S, o->iters);
+  if (st == CPQR_OK) st = cpqr_session_result(S, res);
+  else {
+    // keep the per-sweep fits reached before the failure
+    const std::string msg = h->err;
+    cpqr_result tmp = *res;
+    tmp.factors = nullptr;
+    tmp.lambda = nullptr;
+    (void)cpqr_session_result(S, &tmp);
+    res->sweeps_done = tmp.sweeps_done;
+    h->err = msg;
+  }
+  std::string msg = h->err;
+  cpqr_session_destroy(S);
+  h->err = msg;
+  return st;
 }
 
 }  // extern "C"

@@ -146,16 +146,17 @@ __device__ inline double beta_from_fit(double fit) {
 }
 
 template <int RMAX, int RPT>
-__global__ __launch_bounds__(QR_THREADS) void finish_update(FinishArgs f) {
+__global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f) {
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   __shared__ double sR0[RMAX][RMAX + 1];
-  __shared__ double sred2[QR_WAVES][2];
-  __shared__ double sredR[QR_WAVES][RMAX];
+  constexpr int NT = QrCfg<RMAX>::NT, NW = QrCfg<RMAX>::NW;
+  __shared__ double sred2[NW][2];
+  __shared__ double sredR[NW][RMAX];
   const int tid = threadIdx.x;
   const int I = f.I, R = f.R;
   DevState* st = f.state;
-  for (int e = tid; e < RMAX * RMAX; e += QR_THREADS) {
+  for (int e = tid; e < RMAX * RMAX; e += NT) {
     const int i = e / RMAX, c = e % RMAX;
     sR0[i][c] = (i < R && c < R) ? f.R0[i + R * c] : 0.0;
   }
@@ -167,11 +168,11 @@ __global__ __launch_bounds__(QR_THREADS) void finish_update(FinishArgs f) {
   int bad = 0;
   for (int c = 0; c < R; ++c)
     if (!(sR0[c][c] != 0.0)) bad |= FLAG_RANKDEF;   // singular Z_n (dependent R factors)
-  double a[RPT][RMAX];
+  QrRow<RMAX> a[RPT];
   double sc[2] = {0.0, 0.0};
 #pragma unroll
   for (int p = 0; p < RPT; ++p) {
-    const int row = tid + QR_THREADS * p;
+    const int row = tid + NT * p;
     double vu[RMAX];
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
@@ -185,25 +186,28 @@ __global__ __launch_bounds__(QR_THREADS) void finish_update(FinishArgs f) {
       sc[1] = fma(vu[c], vu[c], sc[1]);
     }
     // back substitution of R0 ahat = vu (row of Ahat R0^T = Vu)
-#pragma unroll
-    for (int c = RMAX - 1; c >= 0; --c) {
+    static_for<0, RMAX>([&](auto ic) {
+      constexpr int c = RMAX - 1 - decltype(ic)::value;
       double s = vu[c];
-#pragma unroll
-      for (int d = c + 1; d < RMAX; ++d) s = fma(-sR0[c][d], a[p][d], s);
-      a[p][c] = (c < R && row < I && sR0[c][c] != 0.0) ? s / sR0[c][c] : 0.0;
-    }
+      static_for<c + 1, RMAX>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
+        s = fma(-sR0[c][d], a[p].get(d), s);
+      });
+      a[p].set(c, (c < R && row < I && sR0[c][c] != 0.0) ? s / sR0[c][c] : 0.0);
+      __builtin_amdgcn_sched_barrier(0);
+    });
   }
-  block_allreduce<2>(sc, sred2);
+  block_allreduce<2, NW>(sc, sred2);
   // lambda = column norms of Ahat
   double cn[RMAX];
 #pragma unroll
   for (int c = 0; c < RMAX; ++c) {
     double s = 0.0;
 #pragma unroll
-    for (int p = 0; p < RPT; ++p) s = fma(a[p][c], a[p][c], s);
+    for (int p = 0; p < RPT; ++p) s = fma(a[p].get(c), a[p].get(c), s);
     cn[c] = s;
   }
-  block_allreduce<RMAX>(cn, sredR);
+  block_allreduce<RMAX, NW>(cn, sredR);
   double inv[RMAX];
 #pragma unroll
   for (int c = 0; c < RMAX; ++c) {
@@ -217,34 +221,28 @@ __global__ __launch_bounds__(QR_THREADS) void finish_update(FinishArgs f) {
   }
 #pragma unroll
   for (int p = 0; p < RPT; ++p) {
-    const int row = tid + QR_THREADS * p;
+    const int row = tid + NT * p;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
-      a[p][c] *= inv[c];
-      if (row < I && c < R) f.A[row + (int64_t)I * c] = a[p][c];
+      a[p].set(c, a[p].get(c) * inv[c]);
+      if (row < I && c < R) f.A[row + (int64_t)I * c] = a[p].get(c);
     }
   }
   block_qr<RMAX, RPT>(a, R, sm);
   block_qr_publish<RMAX, RPT>(a, R, sm, wy, true);
   block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
-  for (int e = tid; e < R * R; e += QR_THREADS) {
+  for (int e = tid; e < R * R; e += NT) {
     const int i = e % R, c = e / R;
     f.Rn[e] = wy.Rm[i][c];
   }
 #pragma unroll
   for (int p = 0; p < RPT; ++p) {
-    const int row = tid + QR_THREADS * p;
-    double qq[RMAX];
-    block_qr_q_row<RMAX, RPT>(a, p, R, sm, wy, qq);
-    if (row < I) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        if (c < R) {
-          if (f.q64) f.q64[row + (int64_t)I * c] = qq[c];
-          if (f.q32) f.q32[row + (int64_t)I * c] = (float)qq[c];
-        }
-      }
-    }
+    const int row = tid + NT * p;
+    if (row < I)
+      block_qr_q_row<RMAX, RPT>(a, p, R, sm, wy, [&](int c, double val) {
+        if (f.q64) f.q64[row + (int64_t)I * c] = val;
+        if (f.q32) f.q32[row + (int64_t)I * c] = (float)val;
+      });
   }
   if (tid == 0) {
     if (!isfinite(sc[0]) || !isfinite(sc[1])) bad |= FLAG_NONFINITE;
@@ -279,11 +277,14 @@ __global__ __launch_bounds__(QR_THREADS) void finish_update(FinishArgs f) {
 }
 
 hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
-  const int rm = qr_rmax(f.R);
-  if (rm == 8) hipLaunchKernelGGL((finish_update<8, 8>), dim3(1), dim3(QR_THREADS), 0, st, f);
-  else if (rm == 16) hipLaunchKernelGGL((finish_update<16, 4>), dim3(1), dim3(QR_THREADS), 0, st, f);
-  else if (rm == 32) hipLaunchKernelGGL((finish_update<32, 2>), dim3(1), dim3(QR_THREADS), 0, st, f);
+  const int rm = qr_rmax(f.R), rp = factor_rpt(f.I);
+  if (f.I > CPQR_MAX_FACTOR_ROWS) return hipErrorInvalidValue;
+#define CPQR_FIN(RM, RP) hipLaunchKernelGGL((finish_update<RM, RP>), dim3(1), dim3(QrCfg<RM>::NT), 0, st, f)
+  if (rm == 8) { if (rp == 1) CPQR_FIN(8, 1); else CPQR_FIN(8, 2); }
+  else if (rm == 16) { if (rp == 1) CPQR_FIN(16, 1); else CPQR_FIN(16, 2); }
+  else if (rm == 32) { if (rp == 1) CPQR_FIN(32, 1); else CPQR_FIN(32, 2); }
   else return hipErrorInvalidValue;
+#undef CPQR_FIN
   return hipGetLastError();
 }
 

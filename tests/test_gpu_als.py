@@ -133,7 +133,7 @@ def test_graph_replay_matches_eager(P):
 def test_tolerance_stop(P):
     """Stopping rule |fit_k - fit_{k-1}| < tol (float64 chain, so that the
     fit of Section 4.1 is accurate enough to settle below tol)."""
-    prob = G.workload("small_o3", dtype=np.float64)
+    prob = G.make_problem([20, 22, 18], 3, seed=31, rho=0.01, dtype=np.float64)
     x, dims = P.to_device(prob.X)
     g = P.cp_als_qr(x, prob.rank, prob.init, 300, dims=dims, tree="restructured", prec="fp64",
                     tol=1e-9)
