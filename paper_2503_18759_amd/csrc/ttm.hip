@@ -10,11 +10,20 @@
 // For a fixed s this is a skinny GEMM (L x I) * (I x R).  Each kernel streams
 // the input once from HBM with 16-byte loads straight into MFMA operand
 // registers and keeps Q in LDS, staged once per workgroup in MFMA lane order.
-// The grid is persistent: every wave owns one 64-row output tile at a time and
-// runs the whole reduction over I for it in registers (no cross-wave
-// reduction, no barrier after the staging), with the loads of the next chunk
-// of k issued before the MFMAs of the current one, and stores its tile
-// directly from the accumulator layout with 16-byte stores.
+//
+// Work decomposition.  The output is cut into tiles of 64 rows.  A workgroup
+// (4 waves) takes 4/KS tiles per pass and gives each tile KS waves, which
+// split the reduction over I into KS contiguous ranges of 32-wide k chunks
+// (KS = 1, 2 or 4, chosen per shape so that tiles x KS fills the chip); the
+// KS partial tiles are added through LDS.  The grid is persistent: a
+// workgroup walks tile groups blockIdx.x, blockIdx.x + gridDim.x, ...
+//
+// Loads.  Inputs below 2 GiB are read through a buffer resource: a lane whose
+// row lies past the end of the tensor or whose k lies past I gets the offset
+// 0x80000000, which the hardware range check turns into a zero without a
+// memory access, so ragged tiles need no branches.  The k loop is software
+// pipelined over two register buffers (chunk q+1 is in flight while the MFMAs
+// of chunk q issue).  Larger inputs use plain global loads.
 //
 //  * ttm_mc: L > 1 ("M-contiguous": rows l are adjacent in memory).  A tile
 //    is 64 consecutive rows m = l + L s.  MFMA f32 16x16x4: lane
@@ -38,6 +47,191 @@ namespace cpqr {
 
 static constexpr int TTM_THREADS = 256;
 static constexpr int TTM_TILE = 64;
+static constexpr uint32_t TTM_OOB = 0x80000000u;   // offset past any buffer we build
+
+// Keeps the instruction scheduler from moving the prefetch loads of the next
+// chunk down to their uses (which would serialise load and MFMA phases).
+#define TTM_PHASE() __builtin_amdgcn_sched_barrier(0)
+// Two waves per SIMD: 256 registers per lane for two chunk buffers, the
+// accumulators and the staged Q operands.
+#define TTM_KERNEL __global__ __launch_bounds__(TTM_THREADS) __attribute__((amdgpu_waves_per_eu(1, 2)))
+
+// ------------------------------------------------------------------ loads
+template <bool BUF>
+struct TtmSrc;
+
+// Buffer-resource source (tensor < 2 GiB): lane offset `lo` and wave-uniform
+// offset `uo` in elements; an invalid lane reads zero.
+template <>
+struct TtmSrc<true> {
+  __amdgpu_buffer_rsrc_t rsrc;
+  __device__ __forceinline__ TtmSrc(const float* p, int64_t n) {
+    rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(n * 4), 0x00020000);
+  }
+  __device__ __forceinline__ f32x4 ld4(int64_t lo, int64_t uo, bool ok) const {
+    const uint32_t v = ok ? (uint32_t)lo * 4u : TTM_OOB;
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, v, (int)(uo * 4), 0));
+  }
+  __device__ __forceinline__ float ld1(int64_t lo, int64_t uo, bool ok) const {
+    const uint32_t v = ok ? (uint32_t)lo * 4u : TTM_OOB;
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, v, (int)(uo * 4), 0));
+  }
+};
+
+// Global-pointer source (any size).
+template <>
+struct TtmSrc<false> {
+  const float* p;
+  __device__ __forceinline__ TtmSrc(const float* q, int64_t) : p(q) {}
+  __device__ __forceinline__ f32x4 ld4(int64_t lo, int64_t uo, bool ok) const {
+    return ok ? *reinterpret_cast<const f32x4*>(p + lo + uo) : f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  __device__ __forceinline__ float ld1(int64_t lo, int64_t uo, bool ok) const {
+    return ok ? p[lo + uo] : 0.f;
+  }
+};
+
+// Wave-uniform wave index (keeps tile bookkeeping in scalar registers).
+__device__ __forceinline__ int ttm_wave() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Per-wave split of a tile-group pass: slot (which tile of the group) and
+// part (which k range), with the k-chunk range [qb, qe).
+struct TtmSplit {
+  int tpw, slot, part, qb, qe;
+  __device__ __forceinline__ TtmSplit(int ks, int TC) {
+    const int wave = ttm_wave();
+    tpw = 4 / ks;
+    slot = wave / ks;
+    part = wave - slot * ks;
+    const int per = (TC + ks - 1) / ks;
+    qb = part * per;
+    qe = qb + per < TC ? qb + per : TC;
+  }
+};
+
+// Adds the KS partial accumulators of each tile through LDS; on return the
+// part-0 wave of each slot holds the sum.  `red` holds (KS-1) * tpw partial
+// tiles of NREG floats per lane.  Every wave of the workgroup calls it.
+template <int NREG>
+__device__ __forceinline__ void ttm_reduce_parts(f32x4 (&acc)[NREG / 4], float* red, int ks,
+                                                 const TtmSplit& sp) {
+  const int lane = threadIdx.x & 63;
+  if (sp.part > 0) {
+    f32x4* dst = reinterpret_cast<f32x4*>(red) + ((sp.slot * (ks - 1) + sp.part - 1) * (NREG / 4)) * 64;
+#pragma unroll
+    for (int j = 0; j < NREG / 4; ++j) dst[j * 64 + lane] = acc[j];
+  }
+  __syncthreads();
+  if (sp.part == 0) {
+    for (int p = 1; p < ks; ++p) {
+      const f32x4* src = reinterpret_cast<const f32x4*>(red) + ((sp.slot * (ks - 1) + p - 1) * (NREG / 4)) * 64;
+#pragma unroll
+      for (int j = 0; j < NREG / 4; ++j) acc[j] += src[j * 64 + lane];
+    }
+  }
+  __syncthreads();
+}
+
+
+// Pipelined tile loop shared by the four MFMA kernels.  The policy P supplies
+// the register buffer of one k chunk (Buf), the per-tile lane bookkeeping
+// (Tile) and tile(), load(), mma(), store() and stage().  The first chunk of
+// the first tile is requested before Q is staged, so the two overlap; when a
+// wave owns an even number of chunks per tile, the first chunk of its next
+// tile is requested while the last chunk of the current one is multiplied.
+template <class P>
+__device__ __forceinline__ void ttm_drive(const P& p, int64_t ntiles, int TC, int ks, float* red) {
+  const TtmSplit sp(ks, TC);
+  const int nq = sp.qe > sp.qb ? sp.qe - sp.qb : 0;
+  const bool even = (nq & 1) == 0;
+  int64_t grp = blockIdx.x;
+  typename P::Buf bufA, bufB;
+  typename P::Tile cur = p.tile(grp * sp.tpw + sp.slot);
+  if (nq > 0) p.load(bufA, cur, sp.qb);
+  p.stage();
+  __syncthreads();
+  for (; grp * sp.tpw < ntiles; grp += gridDim.x) {
+    const int64_t ngrp = grp + gridDim.x;
+    const bool more = ngrp * sp.tpw < ntiles;
+    const typename P::Tile nxt = p.tile(ngrp * sp.tpw + sp.slot);
+    f32x4 acc[P::NACC];
+#pragma unroll
+    for (int j = 0; j < P::NACC; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int q = 0;
+    if (even) {
+      // pairs whose follow-up loads stay in this tile, then a peeled last
+      // pair that requests the next tile's first chunk (or chunk TC, past I:
+      // every lane reads zero without a memory access)
+      for (; q + 3 < nq; q += 2) {
+        p.load(bufB, cur, sp.qb + q + 1);
+        TTM_PHASE();
+        p.mma(acc, bufA, sp.qb + q);
+        TTM_PHASE();
+        p.load(bufA, cur, sp.qb + q + 2);
+        TTM_PHASE();
+        p.mma(acc, bufB, sp.qb + q + 1);
+        TTM_PHASE();
+      }
+      if (nq > 0) {
+        p.load(bufB, cur, sp.qb + q + 1);
+        TTM_PHASE();
+        p.mma(acc, bufA, sp.qb + q);
+        TTM_PHASE();
+        p.load(bufA, nxt, more ? sp.qb : TC);
+        TTM_PHASE();
+        p.mma(acc, bufB, sp.qb + q + 1);
+        TTM_PHASE();
+      }
+    } else {
+      for (; q + 2 < nq; q += 2) {
+        p.load(bufB, cur, sp.qb + q + 1);
+        TTM_PHASE();
+        p.mma(acc, bufA, sp.qb + q);
+        TTM_PHASE();
+        p.load(bufA, cur, sp.qb + q + 2);
+        TTM_PHASE();
+        p.mma(acc, bufB, sp.qb + q + 1);
+        TTM_PHASE();
+      }
+      p.mma(acc, bufA, sp.qb + q);
+    }
+    if (ks > 1) ttm_reduce_parts<P::NACC * 4>(acc, red, ks, sp);
+    if (sp.part == 0) p.store(acc, cur);
+    cur = nxt;
+    if (!even && more) p.load(bufA, cur, sp.qb);
+  }
+}
+
+// Coalesced Q staging: visits Q as float4 runs of 4 consecutive k of one
+// column (needs I % 4 == 0 and a 16-byte aligned Q), padded to 32 TC rows and
+// 16 NB columns with zeros, and hands each run to put(k0, c, value).
+template <int NB, class Put>
+__device__ __forceinline__ void stage_q_runs(const float* __restrict__ Q, int I, int R, int TC, Put put) {
+  const int runs_per_col = 8 * TC;                 // 32 TC / 4
+  const int total = runs_per_col * 16 * NB;
+  for (int e0 = threadIdx.x; e0 < total; e0 += 8 * TTM_THREADS) {
+    f32x4 v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + j * TTM_THREADS;
+      const int c = e / runs_per_col, k0 = 4 * (e - c * runs_per_col);
+      v[j] = (e < total && c < R && k0 < I) ? *reinterpret_cast<const f32x4*>(Q + k0 + (int64_t)I * c)
+                                            : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = e0 + j * TTM_THREADS;
+      const int c = e / runs_per_col, k0 = 4 * (e - c * runs_per_col);
+      if (e < total) put(k0, c, v[j]);
+    }
+  }
+}
+
+__device__ __forceinline__ bool ttm_q_vec(const float* Q, int I) {
+  return (I % 4) == 0 && (((uintptr_t)Q) & 15) == 0;
+}
 
 // ------------------------------------------------------------------ f32 MFMA
 // LDS layout of Q for ttm_mc: for k-step t (4 k's), column block nb, lane:
@@ -45,125 +239,162 @@ static constexpr int TTM_TILE = 64;
 // float4:  sq[(((t/4) * NB + nb) * 64 + lane) * 4 + t%4].
 template <int NB>
 __device__ void stage_q_mc(float* sq, const float* __restrict__ Q, int I, int R, int T4) {
-  const int total = T4 * NB * 64 * 4;
-  for (int e = threadIdx.x; e < total; e += TTM_THREADS) {
-    const int tt = e & 3;
-    const int lane = (e >> 2) & 63;
-    const int rest = e >> 8;               // (t4 * NB + nb)
-    const int nb = rest % NB;
-    const int t4 = rest / NB;
-    const int k = (t4 * 4 + tt) * 4 + (lane >> 4);
-    const int c = nb * 16 + (lane & 15);
-    sq[e] = (k < I && c < R) ? Q[k + (int64_t)I * c] : 0.0f;
+  // T4 * NB elements per thread, gathered in batches of 16 independent loads
+  const int n = T4 * NB;
+  for (int b0 = 0; b0 < n; b0 += 16) {
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = (b0 + j) * TTM_THREADS + threadIdx.x;
+      const int tt = e & 3;
+      const int lane = (e >> 2) & 63;
+      const int rest = e >> 8;               // (t4 * NB + nb)
+      const int nb = rest % NB;
+      const int t4 = rest / NB;
+      const int k = (t4 * 4 + tt) * 4 + (lane >> 4);
+      const int c = nb * 16 + (lane & 15);
+      v[j] = (b0 + j < n && k < I && c < R) ? Q[k + (int64_t)I * c] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (b0 + j < n) sq[(b0 + j) * TTM_THREADS + threadIdx.x] = v[j];
   }
 }
 
-// One wave owns a tile of 64 rows m at a time (persistent over tiles); the
-// K loop runs over chunks of 32 k (8 MFMA k-steps) and is software pipelined
-// one chunk ahead, so 8 float4 loads per lane are in flight while the MFMAs
-// of the previous chunk issue.
+// Rows of an mc tile held by this lane: with VEC one float4 of rows
+// m0 + 4i .. m0 + 4i + 3, else rows m0 + 16 v + i (v = 0..3).
 template <bool VEC>
-__device__ __forceinline__ void mc_f32_load(f32x4 (&a)[8], const float* __restrict__ in,
-                                            const int64_t (&base)[4], const bool (&valid)[4],
-                                            int64_t L, int I, int q, int g) {
+struct McRows {
+  int64_t off[4];   // element offset of (row, k = 0)
+  bool ok[4];
+  __device__ __forceinline__ McRows(int64_t m0, int64_t M, int64_t L, int64_t LI, int li) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t m = VEC ? m0 + 4 * li : m0 + 16 * v + li;
+      ok[v] = m < M;
+      const int64_t s = m / L, l = m - s * L;
+      off[v] = l + LI * s;
+      if (VEC) break;
+    }
+  }
+};
+
+template <bool VEC, bool BUF>
+__device__ __forceinline__ void mc_f32_load(f32x4 (&a)[8], const TtmSrc<BUF>& src,
+                                            const McRows<VEC>& rows, int64_t L, int I, int q,
+                                            int g) {
 #pragma unroll
   for (int tt = 0; tt < 8; ++tt) {
-    const int k = 32 * q + 4 * tt + g;
+    const int kb = 32 * q + 4 * tt;             // uniform part of k
+    const bool kok = g < I - kb;
     if (VEC) {
-      a[tt] = (valid[0] && k < I) ? *reinterpret_cast<const f32x4*>(in + base[0] + L * (int64_t)k)
-                                  : f32x4{0.f, 0.f, 0.f, 0.f};
+      a[tt] = src.ld4(rows.off[0] + L * g, L * kb, rows.ok[0] && kok);
     } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) a[tt][v] = (valid[v] && k < I) ? in[base[v] + L * (int64_t)k] : 0.f;
+      for (int v = 0; v < 4; ++v) a[tt][v] = src.ld1(rows.off[v] + L * g, L * kb, rows.ok[v] && kok);
     }
   }
 }
 
-template <int NB, bool VEC>
-__global__ __launch_bounds__(TTM_THREADS) void ttm_mc_f32(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int64_t L, int I, int64_t S, int R) {
-  extern __shared__ float smem[];
-  const int TC = (I + 31) / 32;            // chunks of 32 k (8 MFMA k-steps)
-  stage_q_mc<NB>(smem, Q, I, R, 2 * TC);
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, g = lane >> 4;
-  const int64_t M = L * S;
-  const int64_t LI = L * (int64_t)I;
-  const int64_t ntiles = (M + TTM_TILE - 1) / TTM_TILE;
-  const f32x4* sqv = reinterpret_cast<const f32x4*>(smem);
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t m0 = tile * TTM_TILE;
-    int64_t base[4];
-    bool valid[4];
-    if (VEC) {
-      const int64_t m = m0 + 4 * li;
-      valid[0] = m < M;
-      const int64_t s = m / L, l = m - s * L;
-      base[0] = l + LI * s;
-    } else {
+template <int NB>
+__device__ __forceinline__ void mc_f32_mma(f32x4 (&acc)[4 * NB], const f32x4 (&a)[8],
+                                           const f32x4* sqv, int q, int lane) {
+  f32x4 b[2][NB];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t m = m0 + 16 * v + li;
-        valid[v] = m < M;
-        const int64_t s = m / L, l = m - s * L;
-        base[v] = l + LI * s;
-      }
-    }
-    f32x4 acc[4][NB];
+  for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) b[hh][nb] = sqv[((2 * q + hh) * NB + nb) * 64 + lane];
+#pragma unroll
+  for (int tt = 0; tt < 8; ++tt)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[v][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    f32x4 cur[8], nxt[8];
-    mc_f32_load<VEC>(cur, in, base, valid, L, I, 0, g);
-    for (int q = 0; q < TC; ++q) {
-      if (q + 1 < TC) mc_f32_load<VEC>(nxt, in, base, valid, L, I, q + 1, g);
-      f32x4 b[2][NB];
+      for (int nb = 0; nb < NB; ++nb)
+        acc[v * NB + nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[tt][v], b[tt >> 2][nb][tt & 3],
+                                                                acc[v * NB + nb], 0, 0, 0);
+}
+
+// Store of an mc tile from the MFMA accumulator layout: lane holds rows
+// rho = 4 g + jj of MFMA v, column 16 nb + li; with VEC row rho of MFMA v is
+// m = m0 + 4 rho + v (four consecutive rows per (nb, jj): one 16-byte store).
+template <int NB, bool VEC>
+__device__ __forceinline__ void mc_store(const f32x4 (&acc)[4 * NB], float* __restrict__ out,
+                                         int64_t m0, int64_t M, int64_t L, int R, int li, int g) {
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh)
+  for (int nb = 0; nb < NB; ++nb) {
+    const int c = 16 * nb + li;
+    if (c >= R) continue;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) b[hh][nb] = sqv[((2 * q + hh) * NB + nb) * 64 + lane];
+    for (int jj = 0; jj < 4; ++jj) {
+      if (VEC) {
+        const int64_t m = m0 + 16 * g + 4 * jj;
+        if (m < M) {
+          const int64_t s = m / L, l = m - s * L;
+          f32x4 val = {acc[0 * NB + nb][jj], acc[1 * NB + nb][jj], acc[2 * NB + nb][jj], acc[3 * NB + nb][jj]};
+          *reinterpret_cast<f32x4*>(out + l + L * (int64_t)c + L * (int64_t)R * s) = val;
+        }
+      } else {
 #pragma unroll
-      for (int tt = 0; tt < 8; ++tt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[tt][v], b[tt >> 2][nb][tt & 3],
-                                                              acc[v][nb], 0, 0, 0);
-#pragma unroll
-      for (int tt = 0; tt < 8; ++tt) cur[tt] = nxt[tt];
-    }
-    // lane holds rows rho = 4 g + jj of MFMA v, column 16 nb + li
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int c = 16 * nb + li;
-      if (c >= R) continue;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        if (VEC) {
-          const int64_t m = m0 + 16 * g + 4 * jj;     // rows m..m+3 (v = 0..3)
+        for (int v = 0; v < 4; ++v) {
+          const int64_t m = m0 + 16 * v + 4 * g + jj;
           if (m < M) {
             const int64_t s = m / L, l = m - s * L;
-            f32x4 val = {acc[0][nb][jj], acc[1][nb][jj], acc[2][nb][jj], acc[3][nb][jj]};
-            *reinterpret_cast<f32x4*>(out + l + L * (int64_t)c + L * (int64_t)R * s) = val;
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t m = m0 + 16 * v + 4 * g + jj;
-            if (m < M) {
-              const int64_t s = m / L, l = m - s * L;
-              out[l + L * (int64_t)c + L * (int64_t)R * s] = acc[v][nb][jj];
-            }
+            out[l + L * (int64_t)c + L * (int64_t)R * s] = acc[v * NB + nb][jj];
           }
         }
       }
     }
   }
+}
+
+template <int NB, bool VEC, bool BUF>
+struct TtmMcF32 {
+  static constexpr int NACC = 4 * NB;
+  struct Buf { f32x4 a[8]; };
+  struct Tile { McRows<VEC> rows; int64_t m0; };
+  float* smem; const float* Q; float* out; TtmSrc<BUF> src;
+  int64_t L, M, LI; int I, R, TC, lane, li, g;
+  __device__ __forceinline__ TtmMcF32(float* sm, const float* in, const float* q, float* o, int64_t L_,
+                                      int I_, int64_t S, int R_)
+      : smem(sm), Q(q), out(o), src(in, L_ * S * I_), L(L_), M(L_ * S), LI(L_ * (int64_t)I_), I(I_),
+        R(R_), TC((I_ + 31) / 32) {
+    lane = threadIdx.x & 63; li = lane & 15; g = lane >> 4;
+  }
+  __device__ __forceinline__ Tile tile(int64_t t) const {
+    const int64_t m0 = t * TTM_TILE;
+    return Tile{McRows<VEC>(m0, M, L, LI, li), m0};
+  }
+  __device__ __forceinline__ void load(Buf& b, const Tile& t, int q) const {
+    mc_f32_load<VEC, BUF>(b.a, src, t.rows, L, I, q, g);
+  }
+  __device__ __forceinline__ void mma(f32x4 (&acc)[NACC], const Buf& b, int q) const {
+    mc_f32_mma<NB>(acc, b.a, reinterpret_cast<const f32x4*>(smem), q, lane);
+  }
+  __device__ __forceinline__ void store(const f32x4 (&acc)[NACC], const Tile& t) const {
+    mc_store<NB, VEC>(acc, out, t.m0, M, L, R, li, g);
+  }
+  __device__ __forceinline__ void stage() const {
+    if (ttm_q_vec(Q, I)) {
+      // k = 16 t4 + 4 tt + g: a run k0..k0+3 shares (t4, tt) and spreads over g
+      float* sq = smem;
+      stage_q_runs<NB>(Q, I, R, TC, [sq](int k0, int c, f32x4 v) {
+        const int m = k0 >> 2, t4 = m >> 2, tt = m & 3, nb = c >> 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sq[(((t4 * NB + nb) * 64 + 16 * j + (c & 15)) << 2) + tt] = v[j];
+      });
+    } else {
+      stage_q_mc<NB>(smem, Q, I, R, 2 * TC);
+    }
+  }
+};
+
+template <int NB, bool VEC, bool BUF>
+TTM_KERNEL void ttm_mc_f32(
+    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
+    int64_t L, int I, int64_t S, int R, int ks) {
+  extern __shared__ float smem[];
+  const TtmMcF32<NB, VEC, BUF> p(smem, in, Q, out, L, I, S, R);
+  ttm_drive(p, (L * S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
 
 // LDS layout of Q for ttm_kc: k-step t covers 32 k; MFMA index v = 4h + cc
@@ -171,111 +402,152 @@ __global__ __launch_bounds__(TTM_THREADS) void ttm_mc_f32(
 // sq[((t * NB + nb) * 64 + lane) * 8 + v] = Q[k][16 nb + lane%16].
 template <int NB>
 __device__ void stage_q_kc(float* sq, const float* __restrict__ Q, int I, int R, int T) {
-  const int total = T * NB * 64 * 8;
-  for (int e = threadIdx.x; e < total; e += TTM_THREADS) {
-    const int v = e & 7;
-    const int lane = (e >> 3) & 63;
-    const int rest = e >> 9;
-    const int nb = rest % NB;
-    const int t = rest / NB;
-    const int k = 32 * t + 16 * (v >> 2) + 4 * (lane >> 4) + (v & 3);
-    const int c = nb * 16 + (lane & 15);
-    sq[e] = (k < I && c < R) ? Q[k + (int64_t)I * c] : 0.0f;
+  // 2 T NB elements per thread, gathered in batches of 16 independent loads
+  const int n = 2 * T * NB;
+  for (int b0 = 0; b0 < n; b0 += 16) {
+    float x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = (b0 + j) * TTM_THREADS + threadIdx.x;
+      const int v = e & 7;
+      const int lane = (e >> 3) & 63;
+      const int rest = e >> 9;
+      const int nb = rest % NB;
+      const int t = rest / NB;
+      const int k = 32 * t + 16 * (v >> 2) + 4 * (lane >> 4) + (v & 3);
+      const int c = nb * 16 + (lane & 15);
+      x[j] = (b0 + j < n && k < I && c < R) ? Q[k + (int64_t)I * c] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (b0 + j < n) sq[(b0 + j) * TTM_THREADS + threadIdx.x] = x[j];
   }
 }
 
-template <int NB, bool VEC>
-__device__ __forceinline__ void kc_f32_load(f32x4 (&x)[4][2], const float* __restrict__ in,
-                                            const int64_t (&base)[4], const bool (&valid)[4],
-                                            int I, int t, int g) {
+// Columns s of a kc tile held by this lane: s = s0 + 16 b + col (b = 0..3).
+struct KcCols {
+  int64_t off[4];   // element offset of (s, k = 4 g)
+  bool ok[4];
+  __device__ __forceinline__ KcCols(int64_t s0, int64_t S, int I, int col, int g) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t s = s0 + 16 * b + col;
+      ok[b] = s < S;
+      off[b] = s * (int64_t)I + 4 * g;
+    }
+  }
+};
+
+// Loads the 32 k of chunk t: x[b][h][cc] = in[s_b, 32 t + 16 h + 4 g + cc].
+template <bool VEC, bool BUF>
+__device__ __forceinline__ void kc_load(f32x4 (&x)[4][2], const TtmSrc<BUF>& src,
+                                        const KcCols& cols, int I, int t, int g) {
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int k = 32 * t + 16 * h + 4 * g;
+      const int kb = 32 * t + 16 * h;
       if (VEC) {
-        x[b][h] = (valid[b] && k < I) ? *reinterpret_cast<const f32x4*>(in + base[b] + k)
-                                      : f32x4{0.f, 0.f, 0.f, 0.f};
+        x[b][h] = src.ld4(cols.off[b], kb, cols.ok[b] && 4 * g < I - kb);
       } else {
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) x[b][h][cc] = (valid[b] && k + cc < I) ? in[base[b] + k + cc] : 0.f;
+        for (int cc = 0; cc < 4; ++cc)
+          x[b][h][cc] = src.ld1(cols.off[b] + cc, kb, cols.ok[b] && 4 * g + cc < I - kb);
       }
     }
 }
 
-template <int NB, bool VEC>
-__global__ __launch_bounds__(TTM_THREADS) void ttm_kc_f32(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int I, int64_t S, int R) {
-  extern __shared__ float smem[];
-  const int T = (I + 31) / 32;
-  stage_q_kc<NB>(smem, Q, I, R, T);
-  __syncthreads();
+template <int NB>
+__device__ __forceinline__ void kc_f32_mma(f32x4 (&acc)[4 * NB], const f32x4 (&x)[4][2],
+                                           const f32x4* sqv, int t, int lane) {
+  f32x4 qa[NB][2];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    qa[nb][0] = sqv[((t * NB + nb) * 64 + lane) * 2 + 0];
+    qa[nb][1] = sqv[((t * NB + nb) * 64 + lane) * 2 + 1];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[b * NB + nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[nb][h][cc], x[b][h][cc],
+                                                                  acc[b * NB + nb], 0, 0, 0);
+}
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, g = lane >> 4;
-  const int64_t ntiles = (S + TTM_TILE - 1) / TTM_TILE;
-  const f32x4* sqv = reinterpret_cast<const f32x4*>(smem);
+// Store of a kc tile: lane holds C[r = 16 nb + 4 g + jj][s = s0 + 16 b + col].
+template <int NB>
+__device__ __forceinline__ void kc_store(const f32x4 (&acc)[4 * NB], float* __restrict__ out,
+                                         int64_t s0, int64_t S, int R, int col, int g) {
   const bool vec_store = (R % 4) == 0 && (((uintptr_t)out) & 15) == 0;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t s0 = tile * TTM_TILE;
-    int64_t base[4];
-    bool valid[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t s = s0 + 16 * b + col;
-      valid[b] = s < S;
-      base[b] = s * (int64_t)I;
-    }
-    f32x4 acc[4][NB];
+  for (int b = 0; b < 4; ++b) {
+    const int64_t s = s0 + 16 * b + col;
+    if (s >= S) continue;
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int nb = 0; nb < NB; ++nb) {
+      const int r0 = 16 * nb + 4 * g;
+      if (r0 >= R) continue;
+      if (vec_store) {
+        *reinterpret_cast<f32x4*>(out + r0 + (int64_t)R * s) = acc[b * NB + nb];
+      } else {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[b][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    f32x4 cur[4][2], nxt[4][2];
-    kc_f32_load<NB, VEC>(cur, in, base, valid, I, 0, g);
-    for (int t = 0; t < T; ++t) {
-      if (t + 1 < T) kc_f32_load<NB, VEC>(nxt, in, base, valid, I, t + 1, g);
-      f32x4 qa[NB][2];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        qa[nb][0] = sqv[((t * NB + nb) * 64 + lane) * 2 + 0];
-        qa[nb][1] = sqv[((t * NB + nb) * 64 + lane) * 2 + 1];
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              acc[b][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[nb][h][cc], cur[b][h][cc], acc[b][nb], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        cur[b][0] = nxt[b][0];
-        cur[b][1] = nxt[b][1];
-      }
-    }
-    // lane holds C[r = 16 nb + 4 g + jj][s = s0 + 16 b + col]
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t s = s0 + 16 * b + col;
-      if (s >= S) continue;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int r0 = 16 * nb + 4 * g;
-        if (r0 >= R) continue;
-        if (vec_store) {
-          *reinterpret_cast<f32x4*>(out + r0 + (int64_t)R * s) = acc[b][nb];
-        } else {
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj)
-            if (r0 + jj < R) out[r0 + jj + (int64_t)R * s] = acc[b][nb][jj];
-        }
+        for (int jj = 0; jj < 4; ++jj)
+          if (r0 + jj < R) out[r0 + jj + (int64_t)R * s] = acc[b * NB + nb][jj];
       }
     }
   }
+}
+
+template <int NB, bool VEC, bool BUF>
+struct TtmKcF32 {
+  static constexpr int NACC = 4 * NB;
+  struct Buf { f32x4 x[4][2]; };
+  struct Tile { KcCols cols; int64_t s0; };
+  float* smem; const float* Q; float* out; TtmSrc<BUF> src;
+  int64_t S; int I, R, TC, lane, col, g;
+  __device__ __forceinline__ TtmKcF32(float* sm, const float* in, const float* q, float* o, int I_,
+                                      int64_t S_, int R_)
+      : smem(sm), Q(q), out(o), src(in, S_ * I_), S(S_), I(I_), R(R_), TC((I_ + 31) / 32) {
+    lane = threadIdx.x & 63; col = lane & 15; g = lane >> 4;
+  }
+  __device__ __forceinline__ Tile tile(int64_t t) const {
+    const int64_t s0 = t * TTM_TILE;
+    return Tile{KcCols(s0, S, I, col, g), s0};
+  }
+  __device__ __forceinline__ void load(Buf& b, const Tile& t, int q) const {
+    kc_load<VEC, BUF>(b.x, src, t.cols, I, q, g);
+  }
+  __device__ __forceinline__ void mma(f32x4 (&acc)[NACC], const Buf& b, int q) const {
+    kc_f32_mma<NB>(acc, b.x, reinterpret_cast<const f32x4*>(smem), q, lane);
+  }
+  __device__ __forceinline__ void store(const f32x4 (&acc)[NACC], const Tile& t) const {
+    kc_store<NB>(acc, out, t.s0, S, R, col, g);
+  }
+  __device__ __forceinline__ void stage() const {
+    if (ttm_q_vec(Q, I)) {
+      // k = 32 t + 16 h + 4 (lane/16) + cc: a run k0..k0+3 is one float4 slot
+      f32x4* sq4 = reinterpret_cast<f32x4*>(smem);
+      stage_q_runs<NB>(Q, I, R, TC, [sq4](int k0, int c, f32x4 v) {
+        const int m = k0 >> 2, t = m >> 3, h = (m >> 2) & 1, lg = m & 3, nb = c >> 4;
+        sq4[((t * NB + nb) * 64 + 16 * lg + (c & 15)) * 2 + h] = v;
+      });
+    } else {
+      stage_q_kc<NB>(smem, Q, I, R, TC);
+    }
+  }
+};
+
+template <int NB, bool VEC, bool BUF>
+TTM_KERNEL void ttm_kc_f32(
+    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
+    int I, int64_t S, int R, int ks) {
+  extern __shared__ float smem[];
+  const TtmKcF32<NB, VEC, BUF> p(smem, in, Q, out, I, S, R);
+  ttm_drive(p, (S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
 
 // ------------------------------------------------------------- bf16x3 MFMA
@@ -285,245 +557,212 @@ __global__ __launch_bounds__(TTM_THREADS) void ttm_kc_f32(
 // holds Q[k][r] with k = 32 t + 16 (e/4) + 4 (lane/16) + e%4.
 template <int NB, bool KC>
 __device__ void stage_q_bf16(bf16x8* sq, const float* __restrict__ Q, int I, int R, int T) {
+  // one item = 8 k of one (t, nb, lane); four items per batch
   const int total = T * NB * 64;
-  for (int e = threadIdx.x; e < total; e += TTM_THREADS) {
-    const int lane = e & 63;
-    const int rest = e >> 6;
-    const int nb = rest % NB;
-    const int t = rest / NB;
-    const int c = nb * 16 + (lane & 15);
-    bf16x8 hi, lo;
+  const bool vq = ttm_q_vec(Q, I);
+  for (int e0 = threadIdx.x; e0 < total; e0 += 4 * TTM_THREADS) {
+    float x[4][8];
 #pragma unroll
-    for (int ee = 0; ee < 8; ++ee) {
-      const int k = KC ? (32 * t + 16 * (ee >> 2) + 4 * (lane >> 4) + (ee & 3))
-                       : (32 * t + 8 * (lane >> 4) + ee);
-      const float x = (k < I && c < R) ? Q[k + (int64_t)I * c] : 0.0f;
-      __bf16 h, l;
-      split_bf16(x, h, l);
-      hi[ee] = h;
-      lo[ee] = l;
-    }
-    sq[2 * e] = hi;
-    sq[2 * e + 1] = lo;
-  }
-}
-
-template <bool VEC>
-__device__ __forceinline__ void mc_bf16_load(f32x4 (&a)[8], const float* __restrict__ in,
-                                             const int64_t (&base)[4], const bool (&valid)[4],
-                                             int64_t L, int I, int t, int g) {
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * TTM_THREADS;
+      const int lane = e & 63;
+      const int rest = e >> 6;
+      const int nb = rest % NB;
+      const int t = rest / NB;
+      const int c = nb * 16 + (lane & 15);
+      const bool ok = e < total && c < R;
+      if (vq) {
+        // two runs of 4 consecutive k: KC: 32t + 4g and 32t + 16 + 4g; else 32t + 8g and +4
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int k = 32 * t + 8 * g + e;
-    if (VEC) {
-      a[e] = (valid[0] && k < I) ? *reinterpret_cast<const f32x4*>(in + base[0] + L * (int64_t)k)
-                                 : f32x4{0.f, 0.f, 0.f, 0.f};
-    } else {
+        for (int h = 0; h < 2; ++h) {
+          const int k0 = KC ? 32 * t + 16 * h + 4 * (lane >> 4) : 32 * t + 8 * (lane >> 4) + 4 * h;
+          const f32x4 v = (ok && k0 < I) ? *reinterpret_cast<const f32x4*>(Q + k0 + (int64_t)I * c)
+                                         : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) a[e][v] = (valid[v] && k < I) ? in[base[v] + L * (int64_t)k] : 0.f;
-    }
-  }
-}
-
-template <int NB, bool VEC>
-__global__ __launch_bounds__(TTM_THREADS) void ttm_mc_bf16x3(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int64_t L, int I, int64_t S, int R) {
-  extern __shared__ float smem[];
-  const int T = (I + 31) / 32;
-  bf16x8* sq = reinterpret_cast<bf16x8*>(smem);
-  stage_q_bf16<NB, false>(sq, Q, I, R, T);
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, g = lane >> 4;
-  const int64_t M = L * S;
-  const int64_t LI = L * (int64_t)I;
-  const int64_t ntiles = (M + TTM_TILE - 1) / TTM_TILE;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t m0 = tile * TTM_TILE;
-    int64_t base[4];
-    bool valid[4];
-    if (VEC) {
-      const int64_t m = m0 + 4 * li;
-      valid[0] = m < M;
-      const int64_t s = m / L, l = m - s * L;
-      base[0] = l + LI * s;
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t m = m0 + 16 * v + li;
-        valid[v] = m < M;
-        const int64_t s = m / L, l = m - s * L;
-        base[v] = l + LI * s;
-      }
-    }
-    f32x4 acc[4][NB];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[v][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // A operand: rows (4 per lane), 8 consecutive k = 32 t + 8 g + e
-    f32x4 cur[8], nxt[8];
-    mc_bf16_load<VEC>(cur, in, base, valid, L, I, 0, g);
-    for (int t = 0; t < T; ++t) {
-      if (t + 1 < T) mc_bf16_load<VEC>(nxt, in, base, valid, L, I, t + 1, g);
-      bf16x8 qh[NB], ql[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        qh[nb] = sq[2 * ((t * NB + nb) * 64 + lane)];
-        ql[nb] = sq[2 * ((t * NB + nb) * 64 + lane) + 1];
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        bf16x8 xh, xl;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 h, l;
-          split_bf16(cur[e][v], h, l);
-          xh[e] = h;
-          xl[e] = l;
+          for (int j = 0; j < 4; ++j) x[u][4 * h + j] = v[j];
         }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, qh[nb], acc[v][nb], 0, 0, 0);
-          acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ql[nb], acc[v][nb], 0, 0, 0);
-          acc[v][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, qh[nb], acc[v][nb], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) cur[e] = nxt[e];
-    }
-    // lane holds rows rho = 4 g + jj of MFMA v, column 16 nb + li; with VEC
-    // row rho of MFMA v is m = m0 + 4 rho + v, else m = m0 + 16 v + rho
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int c = 16 * nb + li;
-      if (c >= R) continue;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        if (VEC) {
-          const int64_t m = m0 + 16 * g + 4 * jj;
-          if (m < M) {
-            const int64_t s = m / L, l = m - s * L;
-            f32x4 val = {acc[0][nb][jj], acc[1][nb][jj], acc[2][nb][jj], acc[3][nb][jj]};
-            *reinterpret_cast<f32x4*>(out + l + L * (int64_t)c + L * (int64_t)R * s) = val;
-          }
-        } else {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t m = m0 + 16 * v + 4 * g + jj;
-            if (m < M) {
-              const int64_t s = m / L, l = m - s * L;
-              out[l + L * (int64_t)c + L * (int64_t)R * s] = acc[v][nb][jj];
-            }
-          }
-        }
-      }
-    }
-  }
-}
-
-template <bool VEC>
-__device__ __forceinline__ void kc_bf16_load(f32x4 (&x)[4][2], const float* __restrict__ in,
-                                             const int64_t (&base)[4], const bool (&valid)[4],
-                                             int I, int t, int g) {
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = 32 * t + 16 * h + 4 * g;
-      if (VEC) {
-        x[b][h] = (valid[b] && k < I) ? *reinterpret_cast<const f32x4*>(in + base[b] + k)
-                                      : f32x4{0.f, 0.f, 0.f, 0.f};
       } else {
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) x[b][h][cc] = (valid[b] && k + cc < I) ? in[base[b] + k + cc] : 0.f;
-      }
-    }
-}
-
-template <int NB, bool VEC>
-__global__ __launch_bounds__(TTM_THREADS) void ttm_kc_bf16x3(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int I, int64_t S, int R) {
-  extern __shared__ float smem[];
-  const int T = (I + 31) / 32;
-  bf16x8* sq = reinterpret_cast<bf16x8*>(smem);
-  stage_q_bf16<NB, true>(sq, Q, I, R, T);
-  __syncthreads();
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane & 15, g = lane >> 4;
-  const int64_t ntiles = (S + TTM_TILE - 1) / TTM_TILE;
-  const bool vec_store = (R % 4) == 0 && (((uintptr_t)out) & 15) == 0;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t s0 = tile * TTM_TILE;
-    int64_t base[4];
-    bool valid[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t s = s0 + 16 * b + col;
-      valid[b] = s < S;
-      base[b] = s * (int64_t)I;
-    }
-    f32x4 acc[4][NB];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) acc[b][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    f32x4 cur[4][2], nxt[4][2];
-    kc_bf16_load<VEC>(cur, in, base, valid, I, 0, g);
-    for (int t = 0; t < T; ++t) {
-      if (t + 1 < T) kc_bf16_load<VEC>(nxt, in, base, valid, I, t + 1, g);
-      bf16x8 qh[NB], ql[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        qh[nb] = sq[2 * ((t * NB + nb) * 64 + lane)];
-        ql[nb] = sq[2 * ((t * NB + nb) * 64 + lane) + 1];
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        bf16x8 xh, xl;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 h, l;
-          split_bf16(cur[b][e >> 2][e & 3], h, l);
-          xh[e] = h;
-          xl[e] = l;
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          acc[b][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ql[nb], xh, acc[b][nb], 0, 0, 0);
-          acc[b][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qh[nb], xl, acc[b][nb], 0, 0, 0);
-          acc[b][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qh[nb], xh, acc[b][nb], 0, 0, 0);
+        for (int ee = 0; ee < 8; ++ee) {
+          const int k = KC ? (32 * t + 16 * (ee >> 2) + 4 * (lane >> 4) + (ee & 3))
+                           : (32 * t + 8 * (lane >> 4) + ee);
+          x[u][ee] = (ok && k < I) ? Q[k + (int64_t)I * c] : 0.0f;
         }
       }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        cur[b][0] = nxt[b][0];
-        cur[b][1] = nxt[b][1];
-      }
     }
-    // lane holds C[r = 16 nb + 4 g + jj][s = s0 + 16 b + col]
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t s = s0 + 16 * b + col;
-      if (s >= S) continue;
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * TTM_THREADS;
+      if (e >= total) continue;
+      bf16x8 hi, lo;
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int r0 = 16 * nb + 4 * g;
-        if (r0 >= R) continue;
-        if (vec_store) {
-          *reinterpret_cast<f32x4*>(out + r0 + (int64_t)R * s) = acc[b][nb];
-        } else {
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj)
-            if (r0 + jj < R) out[r0 + jj + (int64_t)R * s] = acc[b][nb][jj];
-        }
+      for (int ee = 0; ee < 8; ++ee) {
+        __bf16 h, l;
+        split_bf16(x[u][ee], h, l);
+        hi[ee] = h;
+        lo[ee] = l;
       }
+      sq[2 * e] = hi;
+      sq[2 * e + 1] = lo;
     }
   }
+}
+
+// A operand of the mc bf16 product: rows of the lane (as McRows), 8
+// consecutive k = 32 t + 8 g + e.
+template <bool VEC, bool BUF>
+__device__ __forceinline__ void mc_bf16_load(f32x4 (&a)[8], const TtmSrc<BUF>& src,
+                                             const McRows<VEC>& rows, int64_t L, int I, int t,
+                                             int g) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int kb = 32 * t + e;
+    const bool kok = 8 * g < I - kb;
+    if (VEC) {
+      a[e] = src.ld4(rows.off[0] + L * (8 * g), L * kb, rows.ok[0] && kok);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a[e][v] = src.ld1(rows.off[v] + L * (8 * g), L * kb, rows.ok[v] && kok);
+    }
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void mc_bf16_mma(f32x4 (&acc)[4 * NB], const f32x4 (&a)[8],
+                                            const bf16x8* sq, int t, int lane) {
+  bf16x8 qh[NB], ql[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    qh[nb] = sq[2 * ((t * NB + nb) * 64 + lane)];
+    ql[nb] = sq[2 * ((t * NB + nb) * 64 + lane) + 1];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    bf16x8 xh, xl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 h, l;
+      split_bf16(a[e][v], h, l);
+      xh[e] = h;
+      xl[e] = l;
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      f32x4& c = acc[v * NB + nb];
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, qh[nb], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, ql[nb], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, qh[nb], c, 0, 0, 0);
+    }
+  }
+}
+
+template <int NB, bool VEC, bool BUF>
+struct TtmMcBf16 {
+  static constexpr int NACC = 4 * NB;
+  struct Buf { f32x4 a[8]; };
+  struct Tile { McRows<VEC> rows; int64_t m0; };
+  float* smem; const float* Q; float* out; TtmSrc<BUF> src;
+  int64_t L, M, LI; int I, R, TC, lane, li, g;
+  __device__ __forceinline__ TtmMcBf16(float* sm, const float* in, const float* q, float* o, int64_t L_,
+                                       int I_, int64_t S, int R_)
+      : smem(sm), Q(q), out(o), src(in, L_ * S * I_), L(L_), M(L_ * S), LI(L_ * (int64_t)I_), I(I_),
+        R(R_), TC((I_ + 31) / 32) {
+    lane = threadIdx.x & 63; li = lane & 15; g = lane >> 4;
+  }
+  __device__ __forceinline__ Tile tile(int64_t t) const {
+    const int64_t m0 = t * TTM_TILE;
+    return Tile{McRows<VEC>(m0, M, L, LI, li), m0};
+  }
+  __device__ __forceinline__ void load(Buf& b, const Tile& t, int q) const {
+    mc_bf16_load<VEC, BUF>(b.a, src, t.rows, L, I, q, g);
+  }
+  __device__ __forceinline__ void mma(f32x4 (&acc)[NACC], const Buf& b, int q) const {
+    mc_bf16_mma<NB>(acc, b.a, reinterpret_cast<const bf16x8*>(smem), q, lane);
+  }
+  // the bf16 A operand puts rows in the same places as the f32 one
+  __device__ __forceinline__ void store(const f32x4 (&acc)[NACC], const Tile& t) const {
+    mc_store<NB, VEC>(acc, out, t.m0, M, L, R, li, g);
+  }
+  __device__ __forceinline__ void stage() const {
+    stage_q_bf16<NB, false>(reinterpret_cast<bf16x8*>(smem), Q, I, R, TC);
+  }
+};
+
+template <int NB, bool VEC, bool BUF>
+TTM_KERNEL void ttm_mc_bf16x3(
+    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
+    int64_t L, int I, int64_t S, int R, int ks) {
+  extern __shared__ float smem[];
+  const TtmMcBf16<NB, VEC, BUF> p(smem, in, Q, out, L, I, S, R);
+  ttm_drive(p, (L * S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
+}
+
+template <int NB>
+__device__ __forceinline__ void kc_bf16_mma(f32x4 (&acc)[4 * NB], const f32x4 (&x)[4][2],
+                                            const bf16x8* sq, int t, int lane) {
+  bf16x8 qh[NB], ql[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    qh[nb] = sq[2 * ((t * NB + nb) * 64 + lane)];
+    ql[nb] = sq[2 * ((t * NB + nb) * 64 + lane) + 1];
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    bf16x8 xh, xl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      __bf16 h, l;
+      split_bf16(x[b][e >> 2][e & 3], h, l);
+      xh[e] = h;
+      xl[e] = l;
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      f32x4& c = acc[b * NB + nb];
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ql[nb], xh, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qh[nb], xl, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(qh[nb], xh, c, 0, 0, 0);
+    }
+  }
+}
+
+template <int NB, bool VEC, bool BUF>
+struct TtmKcBf16 {
+  static constexpr int NACC = 4 * NB;
+  struct Buf { f32x4 x[4][2]; };
+  struct Tile { KcCols cols; int64_t s0; };
+  float* smem; const float* Q; float* out; TtmSrc<BUF> src;
+  int64_t S; int I, R, TC, lane, col, g;
+  __device__ __forceinline__ TtmKcBf16(float* sm, const float* in, const float* q, float* o, int I_,
+                                       int64_t S_, int R_)
+      : smem(sm), Q(q), out(o), src(in, S_ * I_), S(S_), I(I_), R(R_), TC((I_ + 31) / 32) {
+    lane = threadIdx.x & 63; col = lane & 15; g = lane >> 4;
+  }
+  __device__ __forceinline__ Tile tile(int64_t t) const {
+    const int64_t s0 = t * TTM_TILE;
+    return Tile{KcCols(s0, S, I, col, g), s0};
+  }
+  __device__ __forceinline__ void load(Buf& b, const Tile& t, int q) const {
+    kc_load<VEC, BUF>(b.x, src, t.cols, I, q, g);
+  }
+  __device__ __forceinline__ void mma(f32x4 (&acc)[NACC], const Buf& b, int q) const {
+    kc_bf16_mma<NB>(acc, b.x, reinterpret_cast<const bf16x8*>(smem), q, lane);
+  }
+  __device__ __forceinline__ void store(const f32x4 (&acc)[NACC], const Tile& t) const {
+    kc_store<NB>(acc, out, t.s0, S, R, col, g);
+  }
+  __device__ __forceinline__ void stage() const {
+    stage_q_bf16<NB, true>(reinterpret_cast<bf16x8*>(smem), Q, I, R, TC);
+  }
+};
+
+template <int NB, bool VEC, bool BUF>
+TTM_KERNEL void ttm_kc_bf16x3(
+    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
+    int I, int64_t S, int R, int ks) {
+  extern __shared__ float smem[];
+  const TtmKcBf16<NB, VEC, BUF> p(smem, in, Q, out, I, S, R);
+  ttm_drive(p, (S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
 
 // ------------------------------------------------------------ generic VALU
@@ -548,9 +787,8 @@ __global__ __launch_bounds__(TTM_THREADS) void ttm_generic(
 }
 
 // ---------------------------------------------------------------- launchers
-// Persistent grid: four 64-row tiles per workgroup pass (one per wave),
-// at most TTM_WG_PER_CU workgroups per compute unit.
-static constexpr int TTM_WG_PER_CU = 2;
+static constexpr int TTM_WG_PER_CU = 2;          // persistent grid: workgroups per CU
+static constexpr int64_t TTM_BUF_LIMIT = (int64_t)1 << 31;   // bytes addressable by a buffer offset
 
 static int device_cu_count() {
   static int cached[64] = {0};
@@ -565,50 +803,76 @@ static int device_cu_count() {
   return cached[dev];
 }
 
-static dim3 ttm_grid(int64_t rows) {
-  const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
-  int64_t wgs = (tiles + 3) / 4;
+static size_t ttm_q_lds(int I, int NB) { return (size_t)((I + 31) / 32) * 32 * 16 * NB * 4; }
+static size_t ttm_red_lds(int ks, int NB) {
+  return ks > 1 ? (size_t)(ks - 1) * (4 / ks) * 64 * 16 * NB * 4 : 0;
+}
+
+// K split: the smallest KS whose tiles x KS reaches one wave per SIMD, as
+// long as every part keeps at least two chunks and the LDS fits (measured on
+// the 256^3 rank-32 shapes: one wave per SIMD with the whole K range beats
+// two waves with half of it; tile-starved shapes gain from the split).
+static int ttm_pick_ks(int64_t tiles, int I, int NB) {
+  const int TC = (I + 31) / 32;
+  const int64_t want = (int64_t)device_cu_count() * 4;
+  int ks = 1;
+  while (ks < 4 && tiles * ks < want && TC >= 4 * ks &&
+         ttm_q_lds(I, NB) + ttm_red_lds(2 * ks, NB) <= 64 * 1024)
+    ks *= 2;
+  return ks;
+}
+
+static dim3 ttm_grid(int64_t tiles, int ks) {
+  const int tpw = 4 / ks;
+  int64_t wgs = (tiles + tpw - 1) / tpw;
   const int64_t cap = (int64_t)device_cu_count() * TTM_WG_PER_CU;
   if (wgs > cap) wgs = cap;
   return dim3((unsigned)(wgs > 0 ? wgs : 1));
 }
 
-template <int NB>
+template <int NB, bool BUF>
 static hipError_t launch_f32_nb(const float* in, const float* Q, float* out, int64_t L, int I,
                                 int64_t S, int R, bool bf16x3, hipStream_t st) {
-  // Q staged in LDS: I padded to 32, 16 NB columns, 4 bytes per entry
-  // (float, or a bf16 hi/lo pair)
-  const size_t lds = (size_t)((I + 31) / 32) * 32 * 16 * NB * 4;
+  const int64_t rows = L == 1 ? S : L * S;
+  const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
+  const int ks = ttm_pick_ks(tiles, I, NB);
+  const dim3 grid = ttm_grid(tiles, ks);
+  const size_t lds = ttm_q_lds(I, NB) + ttm_red_lds(ks, NB);
   if (L == 1) {
-    const dim3 grid = ttm_grid(S);
     const bool vec = (I % 4) == 0 && (((uintptr_t)in) & 15) == 0;
     if (bf16x3) {
-      if (vec) hipLaunchKernelGGL((ttm_kc_bf16x3<NB, true>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R);
-      else     hipLaunchKernelGGL((ttm_kc_bf16x3<NB, false>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R);
+      if (vec) hipLaunchKernelGGL((ttm_kc_bf16x3<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
+      else     hipLaunchKernelGGL((ttm_kc_bf16x3<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
     } else {
-      if (vec) hipLaunchKernelGGL((ttm_kc_f32<NB, true>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R);
-      else     hipLaunchKernelGGL((ttm_kc_f32<NB, false>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R);
+      if (vec) hipLaunchKernelGGL((ttm_kc_f32<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
+      else     hipLaunchKernelGGL((ttm_kc_f32<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
     }
   } else {
-    const dim3 grid = ttm_grid(L * S);
     const bool vec = (L % 4) == 0 && (((uintptr_t)in) & 15) == 0 && (((uintptr_t)out) & 15) == 0;
     if (bf16x3) {
-      if (vec) hipLaunchKernelGGL((ttm_mc_bf16x3<NB, true>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R);
-      else     hipLaunchKernelGGL((ttm_mc_bf16x3<NB, false>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R);
+      if (vec) hipLaunchKernelGGL((ttm_mc_bf16x3<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
+      else     hipLaunchKernelGGL((ttm_mc_bf16x3<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
     } else {
-      if (vec) hipLaunchKernelGGL((ttm_mc_f32<NB, true>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R);
-      else     hipLaunchKernelGGL((ttm_mc_f32<NB, false>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R);
+      if (vec) hipLaunchKernelGGL((ttm_mc_f32<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
+      else     hipLaunchKernelGGL((ttm_mc_f32<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
     }
   }
   return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_f32_src(const float* in, const float* Q, float* out, int64_t L, int I,
+                                 int64_t S, int R, bool bf16x3, hipStream_t st) {
+  const int64_t bytes = L * (int64_t)I * S * 4;
+  if (bytes < TTM_BUF_LIMIT - 64) return launch_f32_nb<NB, true>(in, Q, out, L, I, S, R, bf16x3, st);
+  return launch_f32_nb<NB, false>(in, Q, out, L, I, S, R, bf16x3, st);
 }
 
 bool ttm_mfma_supported(int I, int R) {
   if (R < 1 || R > 64 || I < 1) return false;
   const int NB = (R + 15) / 16;
   // Q staged in LDS: I (padded to 32) x 16 NB floats (or bf16 hi + lo pairs)
-  const size_t q_bytes = (size_t)((I + 31) / 32) * 32 * 16 * NB * 4;
-  return q_bytes <= 64 * 1024;
+  return ttm_q_lds(I, NB) <= 64 * 1024;
 }
 
 hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L, int I, int64_t S,
@@ -623,10 +887,10 @@ hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L
     return hipGetLastError();
   }
   switch ((R + 15) / 16) {
-    case 1: return launch_f32_nb<1>(in, Q, out, L, I, S, R, bf16x3, st);
-    case 2: return launch_f32_nb<2>(in, Q, out, L, I, S, R, bf16x3, st);
-    case 3: return launch_f32_nb<3>(in, Q, out, L, I, S, R, bf16x3, st);
-    default: return launch_f32_nb<4>(in, Q, out, L, I, S, R, bf16x3, st);
+    case 1: return launch_f32_src<1>(in, Q, out, L, I, S, R, bf16x3, st);
+    case 2: return launch_f32_src<2>(in, Q, out, L, I, S, R, bf16x3, st);
+    case 3: return launch_f32_src<3>(in, Q, out, L, I, S, R, bf16x3, st);
+    default: return launch_f32_src<4>(in, Q, out, L, I, S, R, bf16x3, st);
   }
 }
 
