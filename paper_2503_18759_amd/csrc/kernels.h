@@ -27,10 +27,40 @@ enum { FLAG_RANKDEF = 1, FLAG_NONFINITE = 2 };
 
 // --- TTM ------------------------------------------------------------------
 bool ttm_mfma_supported(int I, int R);
+// ev0/ev1 (optional): events stamped with the kernel's own start and end
+// (hipExtLaunchKernel), used to time single TTM launches.
 hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L, int I, int64_t S,
-                          int R, bool bf16x3, hipStream_t st);
+                          int R, bool bf16x3, hipStream_t st, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
 hipError_t launch_ttm_f64(const double* in, const double* Q, double* out, int64_t L, int I,
-                          int64_t S, int R, hipStream_t st);
+                          int64_t S, int R, hipStream_t st, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
+
+// Batched float32 TTM: one launch over `count` problems (grid.y = problem).
+// Every problem has the same layout class (L == 1 for all or for none) and
+// ranks in the same 16-column class; `args` lives in device memory.
+struct TtmArgs {
+  const float* in;
+  const float* Q;
+  float* out;
+  int64_t L, S;
+  int I, R;
+};
+struct TtmBatch {
+  int count;
+  bool kc;          // L == 1 for every problem
+  bool vec;         // 16-byte loads legal for every problem
+  bool bf16x3;
+  int nb;           // 16-column blocks (max rank / 16, rounded up)
+  int ks;           // K split across the waves of a workgroup
+  unsigned wgs;     // workgroups per problem (max over problems)
+  size_t lds;       // bytes of LDS (max over problems)
+  const TtmArgs* args;
+};
+// Host helpers for building a TtmBatch: K split and workgroups for one
+// problem of `rows` output rows (the launcher's own choice), and the LDS it needs.
+void ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds);
+hipError_t launch_ttm_f32_batched(const TtmBatch& b, hipStream_t st);
 
 // --- QR -------------------------------------------------------------------
 int qr_rmax(int R);
@@ -62,6 +92,41 @@ struct TsqrArgs {
   double* Q0;           // M x R output (explicit Q)
 };
 hipError_t launch_tsqr(const TsqrArgs& t, hipStream_t st);
+
+// Per-problem arguments of the TSQR kernels (one entry per problem of a
+// batch; a single problem passes its entry by value).
+struct LeafArgs {
+  int N, n, R, P;             // order, skipped mode, rank, leaves of this problem
+  const double* rf;           // N x R x R R factors or null
+  const double* src;          // explicit M x R matrix or null
+  int64_t M, ldv, ldstack;    // rows, leading dims of V and of the leaf-triangle stack
+  double *V, *T, *stack;
+  double *R0, *Qtop;          // non-null: single leaf, write R0 and the trivial Qtop
+};
+struct TopArgs {
+  int R, active;              // active == 0: nothing to do (single leaf)
+  int64_t rows;               // P * R
+  const double* stack;
+  double *R0, *Qtop;
+};
+struct FormArgs {
+  int R, leaf_rows;
+  int64_t M, ldv, ldq;
+  const double *V, *T, *Qtop;
+  double* Q0;
+};
+// Batched TSQR over `count` problems of one rank class (rmax) and one plan
+// (leaf_rpt, top_rpt, Pmax leaves, chunks = max form_q0 workgroups); the
+// argument arrays live in device memory.
+struct TsqrBatch {
+  int count, rmax, leaf_rpt, top_rpt, Pmax, any_top;
+  unsigned chunks;
+  const LeafArgs* leaf;
+  const TopArgs* top;
+  const FormArgs* form;
+};
+hipError_t launch_tsqr_batched(const TsqrBatch& b, hipStream_t st);
+void tsqr_args(const TsqrArgs& t, const TsqrPlan& pl, LeafArgs* la, TopArgs* ta, FormArgs* fa);
 hipError_t launch_factor_qr(int I, int R, const double* A, double* Rn, double* q64, float* q32,
                             hipStream_t st);
 
@@ -83,6 +148,28 @@ struct ApplyArgs {
 int apply_num_chunks(int64_t M, int I);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t st);
 
+// Device-side form of ApplyArgs (one entry per problem of a batch).
+struct ApplyDev {
+  const void* Y;
+  int64_t L, S, chunk;
+  int I, R, nchunks;
+  const double* Q0;
+  const double* Q0prev;
+  double* partial;
+  double* V;
+  const DevState* state;
+};
+ApplyDev apply_dev(const ApplyArgs& a);
+// Batched Y*Q0 over `count` problems of one rank class with the same Y type;
+// grid extents are maxima over the batch.
+struct ApplyBatch {
+  int count, rmax;
+  bool y_f64;
+  unsigned iblocks, nchunks, rblocks;
+  const ApplyDev* args;
+};
+hipError_t launch_apply_batched(const ApplyBatch& b, hipStream_t st);
+
 struct FinishArgs {
   int I, R;
   const double* V;      // 2 x I x R  [Vp | Vq]
@@ -101,6 +188,9 @@ struct FinishArgs {
   int last_in_sweep;
 };
 hipError_t launch_finish(const FinishArgs& f, hipStream_t st);
+// One workgroup per problem; every problem of the batch has rank class rmax
+// and factor rows-per-thread rpt.
+hipError_t launch_finish_batched(int count, int rmax, int rpt, const FinishArgs* args, hipStream_t st);
 
 // --- norms ----------------------------------------------------------------
 // partial sums of squares into `part` (nblocks doubles); returns nblocks

@@ -29,10 +29,18 @@ int qr_max_order(int R) { return qr_max_other_modes(qr_rmax(R)) + 1; }
 // column-major, factor n skipped).  Otherwise read rows of the M x R
 // column-major matrix `src`.
 template <int RMAX, int RPT>
-__global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(
-    int N, int n, int R, const double* __restrict__ rf, const double* __restrict__ src,
-    int64_t M, double* __restrict__ V, double* __restrict__ Tbuf, double* __restrict__ stack,
-    int64_t ldstack, double* __restrict__ R0, double* __restrict__ Qtop) {
+__global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(LeafArgs a0, const LeafArgs* __restrict__ batch) {
+  const LeafArgs args = batch ? batch[blockIdx.y] : a0;
+  if ((int)blockIdx.x >= args.P) return;
+  const int N = args.N, n = args.n, R = args.R;
+  const double* __restrict__ rf = args.rf;
+  const double* __restrict__ src = args.src;
+  const int64_t M = args.M, ldstack = args.ldstack;
+  double* __restrict__ V = args.V;
+  double* __restrict__ Tbuf = args.T;
+  double* __restrict__ stack = args.stack;
+  double* __restrict__ R0 = args.R0;
+  double* __restrict__ Qtop = args.Qtop;
   __shared__ QrSmem<RMAX> sm;
   __shared__ double srf[qr_max_other_modes(RMAX) * RMAX * RMAX];
   constexpr int B = QrCfg<RMAX>::NT * RPT;
@@ -75,7 +83,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(
   }
   block_qr<RMAX, RPT>(a, R, sm);
   // V rows (unit lower trapezoidal) for all B rows of the block
-  const int64_t ldv = (int64_t)gridDim.x * B;
+  const int64_t ldv = args.ldv;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int lr = tid + QrCfg<RMAX>::NT * q;
@@ -117,9 +125,14 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(
 // QR of the P*R x R stack.  Writes R0 (R x R column-major, diag >= 0) and
 // Qtop (P*R x R column-major) = explicit Q of the stack times the sign fix.
 template <int RMAX, int RPT>
-__global__ CPQR_QR_KERNEL(RMAX) void zqr_top(
-    int R, int64_t rows, const double* __restrict__ stack, double* __restrict__ R0,
-    double* __restrict__ Qtop) {
+__global__ CPQR_QR_KERNEL(RMAX) void zqr_top(TopArgs a0, const TopArgs* __restrict__ batch) {
+  const TopArgs args = batch ? batch[blockIdx.y] : a0;
+  if (!args.active) return;
+  const int R = args.R;
+  const int64_t rows = args.rows;
+  const double* __restrict__ stack = args.stack;
+  double* __restrict__ R0 = args.R0;
+  double* __restrict__ Qtop = args.Qtop;
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   const int tid = threadIdx.x;
@@ -148,10 +161,15 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_top(
 // ------------------------------------------------------------------ form Q0
 // One workgroup per 256-row chunk.  Chunk rows lie inside one leaf p.
 template <int RMAX>
-__global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(
-    int R, int64_t M, int leaf_rows, const double* __restrict__ V, int64_t ldv,
-    const double* __restrict__ Tbuf, const double* __restrict__ Qtop, int64_t ldq,
-    double* __restrict__ Q0) {
+__global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(FormArgs a0, const FormArgs* __restrict__ batch) {
+  const FormArgs args = batch ? batch[blockIdx.y] : a0;
+  const int R = args.R, leaf_rows = args.leaf_rows;
+  const int64_t M = args.M, ldv = args.ldv, ldq = args.ldq;
+  const double* __restrict__ V = args.V;
+  const double* __restrict__ Tbuf = args.T;
+  const double* __restrict__ Qtop = args.Qtop;
+  double* __restrict__ Q0 = args.Q0;
+  if ((int64_t)blockIdx.x * QrCfg<RMAX>::NT >= M) return;
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   __shared__ double sQt[RMAX * RMAX];
@@ -281,28 +299,55 @@ int64_t qr_leaf_rows(int R) { return (int64_t)QrCfg<32>::NT * qr_max_rpt(qr_rmax
     }                                                                                  \
   } while (0)
 
+void tsqr_args(const TsqrArgs& t, const TsqrPlan& pl, LeafArgs* la, TopArgs* ta, FormArgs* fa) {
+  const bool single = (t.P == 1);
+  *la = LeafArgs{t.N, t.n, t.R, t.P, t.rf, t.src, t.M, (int64_t)t.P * pl.leaf_rows, (int64_t)t.P * t.R,
+                 t.V, t.T, t.stack, single ? t.R0 : nullptr, single ? t.Qtop : nullptr};
+  *ta = TopArgs{t.R, single ? 0 : 1, (int64_t)t.P * t.R, t.stack, t.R0, t.Qtop};
+  *fa = FormArgs{t.R, (int)pl.leaf_rows, t.M, (int64_t)t.P * pl.leaf_rows, (int64_t)t.P * t.R,
+                 t.V, t.T, t.Qtop, t.Q0};
+}
+
 hipError_t launch_tsqr(const TsqrArgs& t, hipStream_t st) {
   const TsqrPlan pl = tsqr_plan(t.M, t.R);
   if (!pl.ok || pl.P != t.P) return hipErrorInvalidValue;
   const int rm = qr_rmax(t.R);
-  const bool single = (t.P == 1);
+  LeafArgs la;
+  TopArgs ta;
+  FormArgs fa;
+  tsqr_args(t, pl, &la, &ta, &fa);
   CPQR_QR_SWITCH(rm, pl.leaf_rpt, {
-    hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3(t.P), dim3(QrCfg<RM>::NT), 0, st, t.N, t.n, t.R, t.rf,
-                       t.src, t.M, t.V, t.T, t.stack, (int64_t)t.P * t.R,
-                       single ? t.R0 : nullptr, single ? t.Qtop : nullptr);
+    hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3(t.P), dim3(QrCfg<RM>::NT), 0, st, la, nullptr);
   });
-  if (!single) {
+  if (t.P > 1) {
     CPQR_QR_SWITCH(rm, pl.top_rpt, {
-      hipLaunchKernelGGL((zqr_top<RM, RP>), dim3(1), dim3(QrCfg<RM>::NT), 0, st, t.R,
-                         (int64_t)t.P * t.R, t.stack, t.R0, t.Qtop);
+      hipLaunchKernelGGL((zqr_top<RM, RP>), dim3(1), dim3(QrCfg<RM>::NT), 0, st, ta, nullptr);
     });
   }
   CPQR_QR_SWITCH(rm, 1, {
     (void)RP;
     const unsigned chunks = (unsigned)((t.M + QrCfg<RM>::NT - 1) / QrCfg<RM>::NT);
-    hipLaunchKernelGGL((form_q0<RM>), dim3(chunks), dim3(QrCfg<RM>::NT), 0, st, t.R, t.M,
-                       (int)pl.leaf_rows, t.V, (int64_t)t.P * pl.leaf_rows, t.T, t.Qtop,
-                       (int64_t)t.P * t.R, t.Q0);
+    hipLaunchKernelGGL((form_q0<RM>), dim3(chunks), dim3(QrCfg<RM>::NT), 0, st, fa, nullptr);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_tsqr_batched(const TsqrBatch& b, hipStream_t st) {
+  if (b.count <= 0) return hipSuccess;
+  const dim3 nb(1, (unsigned)b.count);
+  CPQR_QR_SWITCH(b.rmax, b.leaf_rpt, {
+    hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3((unsigned)b.Pmax, (unsigned)b.count), dim3(QrCfg<RM>::NT), 0,
+                       st, LeafArgs{}, b.leaf);
+  });
+  if (b.any_top) {
+    CPQR_QR_SWITCH(b.rmax, b.top_rpt, {
+      hipLaunchKernelGGL((zqr_top<RM, RP>), nb, dim3(QrCfg<RM>::NT), 0, st, TopArgs{}, b.top);
+    });
+  }
+  CPQR_QR_SWITCH(b.rmax, 1, {
+    (void)RP;
+    hipLaunchKernelGGL((form_q0<RM>), dim3(b.chunks, (unsigned)b.count), dim3(QrCfg<RM>::NT), 0, st,
+                       FormArgs{}, b.form);
   });
   return hipGetLastError();
 }

@@ -218,7 +218,8 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   return CPQR_OK;
 }
 
-hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s) {
+hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr) {
   const uint32_t full = (1u << p.N) - 1u;
   const void* in = (st.src == full) ? p.X : p.inter.at(st.src);
   void* out = p.inter.at(st.src & ~(1u << st.mode));
@@ -230,9 +231,10 @@ hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s) {
   }
   const int I = (int)p.dims[st.mode];
   if (p.f64)
-    return launch_ttm_f64((const double*)in, (const double*)p.Q[st.mode], (double*)out, L, I, S, p.R, s);
+    return launch_ttm_f64((const double*)in, (const double*)p.Q[st.mode], (double*)out, L, I, S, p.R, s,
+                          ev0, ev1);
   return launch_ttm_f32((const float*)in, (const float*)p.Q[st.mode], (float*)out, L, I, S, p.R,
-                        p.prec == CPQR_PREC_BF16X3, s);
+                        p.prec == CPQR_PREC_BF16X3, s, ev0, ev1);
 }
 
 hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
@@ -610,9 +612,8 @@ cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
             if ((e = hipEventCreate(&b)) != hipSuccess) return e;
             S->evs.push_back(a);
             S->evs.push_back(b);
-            if ((e = hipEventRecord(a, q)) != hipSuccess) return e;
-            if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
-            if ((e = hipEventRecord(b, q)) != hipSuccess) return e;
+            // events stamped by the kernel dispatch itself (start and end of the kernel)
+            if ((e = launch_ttm_step(p, st, q, a, b)) != hipSuccess) return e;
           } else {
             if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
           }

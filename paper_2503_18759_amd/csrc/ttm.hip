@@ -40,6 +40,8 @@
 //    accumulation; x is split in registers, Q is split once into LDS.
 //  * ttm_generic<T>: a plain VALU kernel (float64 chain and shapes outside
 //    the MFMA kernels' limits).
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -147,6 +149,7 @@ __device__ __forceinline__ void ttm_drive(const P& p, int64_t ntiles, int TC, in
   const int nq = sp.qe > sp.qb ? sp.qe - sp.qb : 0;
   const bool even = (nq & 1) == 0;
   int64_t grp = blockIdx.x;
+  if (grp * sp.tpw >= ntiles) return;   // whole workgroup: no tile of this problem
   typename P::Buf bufA, bufB;
   typename P::Tile cur = p.tile(grp * sp.tpw + sp.slot);
   if (nq > 0) p.load(bufA, cur, sp.qb);
@@ -389,12 +392,11 @@ struct TtmMcF32 {
 };
 
 template <int NB, bool VEC, bool BUF>
-TTM_KERNEL void ttm_mc_f32(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int64_t L, int I, int64_t S, int R, int ks) {
+TTM_KERNEL void ttm_mc_f32(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmMcF32<NB, VEC, BUF> p(smem, in, Q, out, L, I, S, R);
-  ttm_drive(p, (L * S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
+  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmMcF32<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.L, a.I, a.S, a.R);
+  ttm_drive(p, (a.L * a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
 
 // LDS layout of Q for ttm_kc: k-step t covers 32 k; MFMA index v = 4h + cc
@@ -542,12 +544,11 @@ struct TtmKcF32 {
 };
 
 template <int NB, bool VEC, bool BUF>
-TTM_KERNEL void ttm_kc_f32(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int I, int64_t S, int R, int ks) {
+TTM_KERNEL void ttm_kc_f32(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmKcF32<NB, VEC, BUF> p(smem, in, Q, out, I, S, R);
-  ttm_drive(p, (S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
+  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmKcF32<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.I, a.S, a.R);
+  ttm_drive(p, (a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
 
 // ------------------------------------------------------------- bf16x3 MFMA
@@ -689,12 +690,11 @@ struct TtmMcBf16 {
 };
 
 template <int NB, bool VEC, bool BUF>
-TTM_KERNEL void ttm_mc_bf16x3(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int64_t L, int I, int64_t S, int R, int ks) {
+TTM_KERNEL void ttm_mc_bf16x3(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmMcBf16<NB, VEC, BUF> p(smem, in, Q, out, L, I, S, R);
-  ttm_drive(p, (L * S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
+  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmMcBf16<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.L, a.I, a.S, a.R);
+  ttm_drive(p, (a.L * a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
 
 template <int NB>
@@ -757,12 +757,11 @@ struct TtmKcBf16 {
 };
 
 template <int NB, bool VEC, bool BUF>
-TTM_KERNEL void ttm_kc_bf16x3(
-    const float* __restrict__ in, const float* __restrict__ Q, float* __restrict__ out,
-    int I, int64_t S, int R, int ks) {
+TTM_KERNEL void ttm_kc_bf16x3(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmKcBf16<NB, VEC, BUF> p(smem, in, Q, out, I, S, R);
-  ttm_drive(p, (S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
+  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmKcBf16<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.I, a.S, a.R);
+  ttm_drive(p, (a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
 
 // ------------------------------------------------------------ generic VALU
@@ -830,42 +829,74 @@ static dim3 ttm_grid(int64_t tiles, int ks) {
   return dim3((unsigned)(wgs > 0 ? wgs : 1));
 }
 
+// Launches through hipExtLaunchKernel when timing events are given, so that
+// the events carry the kernel's own start and end times.
+#define TTM_LAUNCH(KERNEL, ...)                                                          \
+  do {                                                                                   \
+    if (ev0) hipExtLaunchKernelGGL(KERNEL, grid, blk, lds, st, ev0, ev1, 0, __VA_ARGS__); \
+    else hipLaunchKernelGGL(KERNEL, grid, blk, lds, st, __VA_ARGS__);                     \
+  } while (0)
+
 template <int NB, bool BUF>
-static hipError_t launch_f32_nb(const float* in, const float* Q, float* out, int64_t L, int I,
-                                int64_t S, int R, bool bf16x3, hipStream_t st) {
-  const int64_t rows = L == 1 ? S : L * S;
-  const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
-  const int ks = ttm_pick_ks(tiles, I, NB);
-  const dim3 grid = ttm_grid(tiles, ks);
-  const size_t lds = ttm_q_lds(I, NB) + ttm_red_lds(ks, NB);
-  if (L == 1) {
-    const bool vec = (I % 4) == 0 && (((uintptr_t)in) & 15) == 0;
+static void launch_f32_kernel(bool kc, bool vec, bool bf16x3, dim3 grid, size_t lds, hipStream_t st,
+                              const TtmArgs& a, const TtmArgs* batch, int ks, hipEvent_t ev0,
+                              hipEvent_t ev1) {
+  const dim3 blk(TTM_THREADS);
+  if (kc) {
     if (bf16x3) {
-      if (vec) hipLaunchKernelGGL((ttm_kc_bf16x3<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
-      else     hipLaunchKernelGGL((ttm_kc_bf16x3<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
+      if (vec) TTM_LAUNCH((ttm_kc_bf16x3<NB, true, BUF>), a, batch, ks);
+      else     TTM_LAUNCH((ttm_kc_bf16x3<NB, false, BUF>), a, batch, ks);
     } else {
-      if (vec) hipLaunchKernelGGL((ttm_kc_f32<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
-      else     hipLaunchKernelGGL((ttm_kc_f32<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, I, S, R, ks);
+      if (vec) TTM_LAUNCH((ttm_kc_f32<NB, true, BUF>), a, batch, ks);
+      else     TTM_LAUNCH((ttm_kc_f32<NB, false, BUF>), a, batch, ks);
     }
   } else {
-    const bool vec = (L % 4) == 0 && (((uintptr_t)in) & 15) == 0 && (((uintptr_t)out) & 15) == 0;
     if (bf16x3) {
-      if (vec) hipLaunchKernelGGL((ttm_mc_bf16x3<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
-      else     hipLaunchKernelGGL((ttm_mc_bf16x3<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
+      if (vec) TTM_LAUNCH((ttm_mc_bf16x3<NB, true, BUF>), a, batch, ks);
+      else     TTM_LAUNCH((ttm_mc_bf16x3<NB, false, BUF>), a, batch, ks);
     } else {
-      if (vec) hipLaunchKernelGGL((ttm_mc_f32<NB, true, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
-      else     hipLaunchKernelGGL((ttm_mc_f32<NB, false, BUF>), grid, dim3(TTM_THREADS), lds, st, in, Q, out, L, I, S, R, ks);
+      if (vec) TTM_LAUNCH((ttm_mc_f32<NB, true, BUF>), a, batch, ks);
+      else     TTM_LAUNCH((ttm_mc_f32<NB, false, BUF>), a, batch, ks);
     }
   }
+}
+
+static hipError_t launch_f32_any(int NB, bool buf, bool kc, bool vec, bool bf16x3, dim3 grid, size_t lds,
+                                 hipStream_t st, const TtmArgs& a, const TtmArgs* batch, int ks,
+                                 hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
+#define CPQR_TTM_NB(V)                                                                              \
+  case V:                                                                                          \
+    if (buf) launch_f32_kernel<V, true>(kc, vec, bf16x3, grid, lds, st, a, batch, ks, ev0, ev1);   \
+    else     launch_f32_kernel<V, false>(kc, vec, bf16x3, grid, lds, st, a, batch, ks, ev0, ev1);  \
+    break;
+  switch (NB) {
+    CPQR_TTM_NB(1)
+    CPQR_TTM_NB(2)
+    CPQR_TTM_NB(3)
+    CPQR_TTM_NB(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef CPQR_TTM_NB
   return hipGetLastError();
 }
 
-template <int NB>
-static hipError_t launch_f32_src(const float* in, const float* Q, float* out, int64_t L, int I,
-                                 int64_t S, int R, bool bf16x3, hipStream_t st) {
-  const int64_t bytes = L * (int64_t)I * S * 4;
-  if (bytes < TTM_BUF_LIMIT - 64) return launch_f32_nb<NB, true>(in, Q, out, L, I, S, R, bf16x3, st);
-  return launch_f32_nb<NB, false>(in, Q, out, L, I, S, R, bf16x3, st);
+static bool ttm_vec_ok(const TtmArgs& a) {
+  if (a.L == 1) return (a.I % 4) == 0 && (((uintptr_t)a.in) & 15) == 0;
+  return (a.L % 4) == 0 && (((uintptr_t)a.in) & 15) == 0 && (((uintptr_t)a.out) & 15) == 0;
+}
+
+void ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds) {
+  const int NB = (R + 15) / 16;
+  const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
+  *ks = ttm_pick_ks(tiles, I, NB);
+  *wgs = ttm_grid(tiles, *ks).x;
+  *lds = ttm_q_lds(I, NB) + ttm_red_lds(*ks, NB);
+}
+
+hipError_t launch_ttm_f32_batched(const TtmBatch& b, hipStream_t st) {
+  if (b.count <= 0) return hipSuccess;
+  return launch_f32_any(b.nb, true, b.kc, b.vec, b.bf16x3, dim3(b.wgs, (unsigned)b.count), b.lds, st,
+                        TtmArgs{}, b.args, b.ks);
 }
 
 bool ttm_mfma_supported(int I, int R) {
@@ -876,31 +907,37 @@ bool ttm_mfma_supported(int I, int R) {
 }
 
 hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L, int I, int64_t S,
-                          int R, bool bf16x3, hipStream_t st) {
+                          int R, bool bf16x3, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (L * S == 0) return hipSuccess;
   if (!ttm_mfma_supported(I, R)) {
     if (bf16x3) return hipErrorInvalidValue;
     const int64_t total = L * S * R;
     int64_t blocks = (total + TTM_THREADS - 1) / TTM_THREADS;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(ttm_generic<float>, dim3((unsigned)blocks), dim3(TTM_THREADS), 0, st, in, Q, out, L, I, S, R);
+    const dim3 grid((unsigned)blocks), blk(TTM_THREADS);
+    const size_t lds = 0;
+    TTM_LAUNCH(ttm_generic<float>, in, Q, out, L, I, S, R);
     return hipGetLastError();
   }
-  switch ((R + 15) / 16) {
-    case 1: return launch_f32_src<1>(in, Q, out, L, I, S, R, bf16x3, st);
-    case 2: return launch_f32_src<2>(in, Q, out, L, I, S, R, bf16x3, st);
-    case 3: return launch_f32_src<3>(in, Q, out, L, I, S, R, bf16x3, st);
-    default: return launch_f32_src<4>(in, Q, out, L, I, S, R, bf16x3, st);
-  }
+  const TtmArgs a{in, Q, out, L, S, I, R};
+  const int NB = (R + 15) / 16;
+  const int64_t rows = L == 1 ? S : L * S;
+  const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
+  const int ks = ttm_pick_ks(tiles, I, NB);
+  const bool buf = L * (int64_t)I * S * 4 < TTM_BUF_LIMIT - 64;
+  return launch_f32_any(NB, buf, L == 1, ttm_vec_ok(a), bf16x3, ttm_grid(tiles, ks),
+                        ttm_q_lds(I, NB) + ttm_red_lds(ks, NB), st, a, nullptr, ks, ev0, ev1);
 }
 
 hipError_t launch_ttm_f64(const double* in, const double* Q, double* out, int64_t L, int I, int64_t S,
-                          int R, hipStream_t st) {
+                          int R, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int64_t total = L * S * R;
   if (total == 0) return hipSuccess;
   int64_t blocks = (total + TTM_THREADS - 1) / TTM_THREADS;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(ttm_generic<double>, dim3((unsigned)blocks), dim3(TTM_THREADS), 0, st, in, Q, out, L, I, S, R);
+  const dim3 grid((unsigned)blocks), blk(TTM_THREADS);
+  const size_t lds = 0;
+  TTM_LAUNCH(ttm_generic<double>, in, Q, out, L, I, S, R);
   return hipGetLastError();
 }
 

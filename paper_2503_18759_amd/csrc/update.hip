@@ -23,10 +23,16 @@ static constexpr int AP_ROWS = 64;
 static constexpr int AP_KT = 32;
 
 template <typename TY, int RMAX>
-__global__ __launch_bounds__(AP_THREADS) void apply_partial(
-    const TY* __restrict__ Y, int64_t L, int I, int64_t S, int R, const double* __restrict__ Q0,
-    const double* __restrict__ Q0prev, double* __restrict__ partial, int64_t chunk,
-    const DevState* __restrict__ st) {
+__global__ __launch_bounds__(AP_THREADS) void apply_partial(ApplyDev a0, const ApplyDev* __restrict__ batch) {
+  const ApplyDev a = batch ? batch[blockIdx.z] : a0;
+  const TY* __restrict__ Y = static_cast<const TY*>(a.Y);
+  const int64_t L = a.L, S = a.S, chunk = a.chunk;
+  const int I = a.I, R = a.R;
+  const double* __restrict__ Q0 = a.Q0;
+  const double* __restrict__ Q0prev = a.Q0prev;
+  double* __restrict__ partial = a.partial;
+  const DevState* __restrict__ st = a.state;
+  if ((int)blockIdx.x * AP_ROWS >= I || (int)blockIdx.y >= a.nchunks) return;
   __shared__ double sY[AP_KT][AP_ROWS + 1];
   __shared__ double sQ[AP_KT][RMAX];
   __shared__ double sP[AP_KT][RMAX];
@@ -88,8 +94,12 @@ __global__ __launch_bounds__(AP_THREADS) void apply_partial(
   }
 }
 
-__global__ void apply_reduce(const double* __restrict__ partial, int nchunks, int64_t n,
-                             double* __restrict__ V) {
+__global__ void apply_reduce(ApplyDev a0, const ApplyDev* __restrict__ batch) {
+  const ApplyDev a = batch ? batch[blockIdx.y] : a0;
+  const double* __restrict__ partial = a.partial;
+  const int nchunks = a.nchunks;
+  const int64_t n = 2 * (int64_t)a.I * a.R;
+  double* __restrict__ V = a.V;
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
        o += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
@@ -110,29 +120,46 @@ int apply_num_chunks(int64_t M, int I) {
   return (int)((M + chunk - 1) / chunk);
 }
 
-hipError_t launch_apply(const ApplyArgs& a, hipStream_t st) {
+ApplyDev apply_dev(const ApplyArgs& a) {
   const int64_t M = a.L * a.S;
   int64_t chunk = (M + a.nchunks - 1) / a.nchunks;
   chunk = ((chunk + AP_KT - 1) / AP_KT) * AP_KT;
-  dim3 grid((a.I + AP_ROWS - 1) / AP_ROWS, a.nchunks);
-  const int rm = qr_rmax(a.R);
+  return ApplyDev{a.Y, a.L, a.S, chunk, a.I, a.R, a.nchunks, a.Q0, a.Q0prev, a.partial, a.V, a.state};
+}
+
+static hipError_t apply_launch(int rm, bool y_f64, dim3 grid, dim3 rgrid, const ApplyDev& a,
+                               const ApplyDev* batch, hipStream_t st) {
 #define CPQR_APPLY(RM)                                                                            \
-  if (a.y_f64)                                                                                    \
-    hipLaunchKernelGGL((apply_partial<double, RM>), grid, dim3(AP_THREADS), 0, st,                \
-                       (const double*)a.Y, a.L, a.I, a.S, a.R, a.Q0, a.Q0prev, a.partial, chunk, a.state); \
+  if (y_f64)                                                                                      \
+    hipLaunchKernelGGL((apply_partial<double, RM>), grid, dim3(AP_THREADS), 0, st, a, batch);     \
   else                                                                                            \
-    hipLaunchKernelGGL((apply_partial<float, RM>), grid, dim3(AP_THREADS), 0, st,                 \
-                       (const float*)a.Y, a.L, a.I, a.S, a.R, a.Q0, a.Q0prev, a.partial, chunk, a.state);
+    hipLaunchKernelGGL((apply_partial<float, RM>), grid, dim3(AP_THREADS), 0, st, a, batch);
   if (rm == 8) { CPQR_APPLY(8) }
   else if (rm == 16) { CPQR_APPLY(16) }
   else if (rm == 32) { CPQR_APPLY(32) }
   else return hipErrorInvalidValue;
 #undef CPQR_APPLY
-  const int64_t n = 2 * (int64_t)a.I * a.R;
+  hipLaunchKernelGGL(apply_reduce, rgrid, dim3(256), 0, st, a, batch);
+  return hipGetLastError();
+}
+
+static unsigned apply_reduce_blocks(int I, int R) {
+  const int64_t n = 2 * (int64_t)I * R;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(apply_reduce, dim3((unsigned)blocks), dim3(256), 0, st, a.partial, a.nchunks, n, a.V);
-  return hipGetLastError();
+  return (unsigned)blocks;
+}
+
+hipError_t launch_apply(const ApplyArgs& a, hipStream_t st) {
+  const ApplyDev d = apply_dev(a);
+  const dim3 grid((a.I + AP_ROWS - 1) / AP_ROWS, a.nchunks);
+  return apply_launch(qr_rmax(a.R), a.y_f64, grid, dim3(apply_reduce_blocks(a.I, a.R)), d, nullptr, st);
+}
+
+hipError_t launch_apply_batched(const ApplyBatch& b, hipStream_t st) {
+  if (b.count <= 0) return hipSuccess;
+  return apply_launch(b.rmax, b.y_f64, dim3(b.iblocks, b.nchunks, (unsigned)b.count),
+                      dim3(b.rblocks, (unsigned)b.count), ApplyDev{}, b.args, st);
 }
 
 // ------------------------------------------------------------------ finish
@@ -146,7 +173,8 @@ __device__ inline double beta_from_fit(double fit) {
 }
 
 template <int RMAX, int RPT>
-__global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f) {
+__global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishArgs* __restrict__ batch) {
+  const FinishArgs f = batch ? batch[blockIdx.x] : f0;
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   __shared__ double sR0[RMAX][RMAX + 1];
@@ -276,16 +304,26 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f) {
   }
 }
 
-hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
-  const int rm = qr_rmax(f.R), rp = factor_rpt(f.I);
-  if (f.I > CPQR_MAX_FACTOR_ROWS) return hipErrorInvalidValue;
-#define CPQR_FIN(RM, RP) hipLaunchKernelGGL((finish_update<RM, RP>), dim3(1), dim3(QrCfg<RM>::NT), 0, st, f)
+static hipError_t finish_launch(int rm, int rp, unsigned blocks, const FinishArgs& f,
+                                const FinishArgs* batch, hipStream_t st) {
+#define CPQR_FIN(RM, RP) \
+  hipLaunchKernelGGL((finish_update<RM, RP>), dim3(blocks), dim3(QrCfg<RM>::NT), 0, st, f, batch)
   if (rm == 8) { if (rp == 1) CPQR_FIN(8, 1); else CPQR_FIN(8, 2); }
   else if (rm == 16) { if (rp == 1) CPQR_FIN(16, 1); else CPQR_FIN(16, 2); }
   else if (rm == 32) { if (rp == 1) CPQR_FIN(32, 1); else CPQR_FIN(32, 2); }
   else return hipErrorInvalidValue;
 #undef CPQR_FIN
   return hipGetLastError();
+}
+
+hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
+  if (f.I > CPQR_MAX_FACTOR_ROWS) return hipErrorInvalidValue;
+  return finish_launch(qr_rmax(f.R), factor_rpt(f.I), 1, f, nullptr, st);
+}
+
+hipError_t launch_finish_batched(int count, int rmax, int rpt, const FinishArgs* args, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  return finish_launch(rmax, rpt, (unsigned)count, FinishArgs{}, args, st);
 }
 
 // ------------------------------------------------------------------- norms
