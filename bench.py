@@ -10,9 +10,10 @@ congruence 0.9, noise 1e-3 relative), inputs resident in HBM.
 Prints one JSON line.  ``value`` comes from the timed region (HIP graph
 replay, K sweeps, synchronised on both sides).  ``roofline`` describes the
 level-1 TTM (the TTM that streams X, the dominant streaming kernel): its
-average duration comes from HIP events stamped by every level-1 TTM dispatch
-itself (hipExtLaunchKernel start/stop events, on the library's stream) during
-a second pass of the same K sweeps launched kernel by kernel.  ``cpu_baseline`` times the FP64 oracle on a bounded
+average duration comes from HIP events on the library's stream during a
+second pass of the same K sweeps launched kernel by kernel, in which every
+level-1 TTM runs as a graph of 8 back-to-back launches (it is idempotent)
+between two events.  ``cpu_baseline`` times the FP64 oracle on a bounded
 sample of sweeps of the same workload on the host cores.
 """
 from __future__ import annotations
@@ -132,7 +133,7 @@ def main():
     elapsed = t1 - t0
 
     # kernel timing pass: same K sweeps launched kernel by kernel; every
-    # level-1 TTM dispatch stamps a pair of HIP events on the library's stream
+    # level-1 TTM is timed with HIP events on the library's stream
     tsess = P.Session(x, R, prob.init, W + K, dims=dims, tree=args.tree, prec=args.prec,
                       time_kernels=True)
     tsess.sweeps(W)

@@ -63,7 +63,9 @@ typedef enum { CPQR_DTYPE_F64 = 0, CPQR_DTYPE_F32 = 1 } cpqr_dtype;
 
 /* Option flags. */
 #define CPQR_FLAG_EXPLICIT_FIT 0x1u  /* also compute 1 - ||X - K|| / ||X|| explicitly at the end */
-#define CPQR_FLAG_TIME_KERNELS 0x2u  /* time every level-1 TTM (the TTM that reads X) with HIP events */
+#define CPQR_FLAG_TIME_KERNELS 0x2u  /* time every level-1 TTM (the TTM that reads X) with HIP events:
+                                        kernels launch one by one, and each level-1 TTM runs as a graph
+                                        of 8 back-to-back launches (it is idempotent) between two events */
 #define CPQR_FLAG_NO_GRAPH     0x4u  /* launch kernels one by one instead of replaying HIP graphs */
 
 typedef struct cpqr_handle cpqr_handle;
@@ -113,7 +115,7 @@ typedef struct {
   double ttm_flops;        /* TTM flops executed (2 |input| R per TTM) */
   double ttm_bytes;        /* TTM algorithmic bytes (input read once + output written once) */
   double seconds;          /* device wall time of the sweep loop */
-  double l1_ttm_seconds;   /* with CPQR_FLAG_TIME_KERNELS: summed duration of the level-1 TTMs */
+  double l1_ttm_seconds;   /* with CPQR_FLAG_TIME_KERNELS: summed per-launch duration of the level-1 TTMs */
   int l1_ttm_launches;     /* number of level-1 TTMs timed */
   double l1_ttm_bytes;     /* algorithmic bytes of one level-1 TTM per launch (averaged) */
   double l1_ttm_flops;     /* flops of one level-1 TTM per launch (averaged) */
@@ -163,6 +165,30 @@ cpqr_status cpqr_session_sweeps(cpqr_session *session, int nsweeps);
 cpqr_status cpqr_session_sync(cpqr_session *session);
 cpqr_status cpqr_session_result(cpqr_session *session, cpqr_result *result);
 cpqr_status cpqr_session_destroy(cpqr_session *session);
+
+/*
+ * cpqr_als_qr_batched -- `count` independent decompositions run together
+ * (a batching feature of this library, not part of the paper's method: each
+ * problem follows Algorithm 2 / 3 exactly as cpqr_als_qr would).  Every sweep
+ * of the whole batch is one HIP graph whose kernels each cover all problems
+ * (grid dimension = problem); the float32 TTM launches are autotuned (K split
+ * across the waves of a workgroup) on the first sweep by timing the
+ * candidates into scratch outputs.
+ * Xs[t], ranks[t], opts[t], results[t]: the arguments of cpqr_als_qr for
+ * problem t (same meaning, layout and ownership).  All problems must share
+ * order, tree, extrapolate, prec, iters, alpha, switch_delta and fixed_beta;
+ * prec must be CPQR_PREC_FP32 or CPQR_PREC_BF16X3; tol must be 0 (every
+ * problem runs exactly `iters` sweeps).  Violations: CPQR_EINVAL (mixed
+ * settings, tol != 0, count < 1) or CPQR_EUNSUPPORTED (FP64).  Each problem is
+ * validated as cpqr_check_args; the first failing problem's status is
+ * returned and nothing runs.  Runtime errors are reported per problem: the
+ * function returns the first non-OK status over t = 0..count-1 after filling
+ * every result it can.  Uses the handle's workspace; CPQR_EINVAL if the
+ * handle has a live session.
+ */
+cpqr_status cpqr_als_qr_batched(cpqr_handle *handle, int count, const cpqr_tensor *Xs,
+                                const int *ranks, const cpqr_options *opts,
+                                cpqr_result *results);
 
 /*
  * cpqr_check_args -- host-only: the argument checks that cpqr_als_qr makes

@@ -63,7 +63,7 @@ class _Result(ctypes.Structure):
 EXPORTS = ["cpqr_create", "cpqr_destroy", "cpqr_last_error", "cpqr_status_string",
            "cpqr_check_args", "cpqr_als_qr", "cpqr_session_create", "cpqr_session_sweeps",
            "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy",
-           "cpqr_schedule", "cpqr_ttm", "cpqr_qr"]
+           "cpqr_schedule", "cpqr_ttm", "cpqr_qr", "cpqr_als_qr_batched"]
 
 _lib = None
 
@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.cpqr_ttm.argtypes = [vp, i32, i32, ctypes.POINTER(i64), i32, i32, vp, vp, vp]
     L.cpqr_qr.argtypes = [vp, i64, i32, vp, vp, vp]
+    L.cpqr_als_qr_batched.argtypes = [vp, i32, ctypes.POINTER(_Tensor), ctypes.POINTER(i32),
+                                      ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
     for f in ("cpqr_create", "cpqr_destroy", "cpqr_check_args", "cpqr_als_qr", "cpqr_schedule",
               "cpqr_ttm", "cpqr_qr", "cpqr_session_create", "cpqr_session_sweeps",
               "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy"):
@@ -266,6 +268,39 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
                        ctypes.byref(res))
     h.check(st)
     return _result_dict(res, bufs)
+
+
+def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequence[np.ndarray]],
+                      iters: int = 50, *, dims: Optional[Sequence[Sequence[int]]] = None,
+                      tree: str = "restructured", extrapolate: str = "off", prec: str = "fp32",
+                      alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
+                      explicit_fit: bool = False, handle: Optional[Handle] = None) -> List[Dict]:
+    """Independent decompositions run together (cpqr_als_qr_batched): every
+    sweep of the whole batch is one HIP graph of batched kernels.  Returns one
+    result dict per problem (as :func:`cp_als_qr`)."""
+    L = load_library()
+    count = len(xs)
+    if not (len(ranks) == len(inits) == count) or count < 1:
+        raise ValueError("xs, ranks and inits must have the same non-zero length")
+    keeps, bufs = [], []
+    tens = (_Tensor * count)()
+    optv = (_Options * count)()
+    resv = (_Result * count)()
+    for t in range(count):
+        d, keep = _prepare(xs[t], ranks[t], inits[t], iters, dims[t] if dims else None, tree,
+                           extrapolate, prec, 0.0, alpha, switch_delta, fixed_beta, explicit_fit,
+                           False, True)
+        keeps.append(keep)
+        tens[t] = keep["ten"]
+        optv[t] = keep["opts"]
+        r, b = _result_buffers(d, ranks[t], iters)
+        resv[t] = r
+        bufs.append(b)
+    rk = (ctypes.c_int32 * count)(*[int(r) for r in ranks])
+    h = handle or default_handle(xs[0].device.index or 0)
+    st = L.cpqr_als_qr_batched(h._h, count, tens, rk, optv, resv)
+    h.check(st)
+    return [_result_dict(resv[t], bufs[t]) for t in range(count)]
 
 
 class Session:

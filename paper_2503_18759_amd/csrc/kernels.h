@@ -51,16 +51,20 @@ struct TtmBatch {
   bool kc;          // L == 1 for every problem
   bool vec;         // 16-byte loads legal for every problem
   bool bf16x3;
+  bool buf;         // every input below 2 GiB (buffer-resource loads)
   int nb;           // 16-column blocks (max rank / 16, rounded up)
   int ks;           // K split across the waves of a workgroup
   unsigned wgs;     // workgroups per problem (max over problems)
   size_t lds;       // bytes of LDS (max over problems)
   const TtmArgs* args;
 };
-// Host helpers for building a TtmBatch: K split and workgroups for one
-// problem of `rows` output rows (the launcher's own choice), and the LDS it needs.
-void ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds);
+// Host helper for building a TtmBatch: workgroups and LDS bytes for one
+// problem of `rows` output rows at K split `ks` (0: the launcher's own
+// choice, returned in *ks).  False if that split does not fit.
+bool ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds);
 hipError_t launch_ttm_f32_batched(const TtmBatch& b, hipStream_t st);
+bool ttm_vec_legal(const TtmArgs& a);   // 16-byte loads (and stores) legal for this problem
+bool ttm_buf_legal(const TtmArgs& a);   // input addressable through a buffer resource
 
 // --- QR -------------------------------------------------------------------
 int qr_rmax(int R);
@@ -160,6 +164,8 @@ struct ApplyDev {
   const DevState* state;
 };
 ApplyDev apply_dev(const ApplyArgs& a);
+unsigned apply_iblocks(int I);
+unsigned apply_reduce_blocks(int I, int R);
 // Batched Y*Q0 over `count` problems of one rank class with the same Y type;
 // grid extents are maxima over the batch.
 struct ApplyBatch {

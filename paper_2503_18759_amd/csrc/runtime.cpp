@@ -101,6 +101,9 @@ cpqr_status ws(cpqr_handle* h, const std::string& name, size_t bytes, void** out
     (ptr) = reinterpret_cast<decltype(ptr)>(p__);                        \
   } while (0)
 
+// Back-to-back launches per timed level-1 TTM (CPQR_FLAG_TIME_KERNELS).
+constexpr int kTimeReps = 8;
+
 int64_t ipow(int64_t b, int e) {
   int64_t r = 1;
   for (int i = 0; i < e; ++i) r *= b;
@@ -109,6 +112,7 @@ int64_t ipow(int64_t b, int e) {
 
 // Everything one decomposition needs on the device.
 struct Problem {
+  std::string prefix;     // workspace name prefix (one per problem of a batch)
   int N = 0, R = 0, prec = CPQR_PREC_FP32;
   std::vector<int64_t> dims;
   const void* X = nullptr;
@@ -174,34 +178,34 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   p.q0buf.resize(N);
   p.Imax = 0;
   for (int k = 0; k < N; ++k) {
-    WS(h, "A" + std::to_string(k), (size_t)p.dims[k] * R * 8, p.A[k]);
-    WS(h, "Q" + std::to_string(k), (size_t)p.dims[k] * R * p.elem, p.Q[k]);
+    WS(h, p.prefix + "A" + std::to_string(k), (size_t)p.dims[k] * R * 8, p.A[k]);
+    WS(h, p.prefix + "Q" + std::to_string(k), (size_t)p.dims[k] * R * p.elem, p.Q[k]);
     if (p.dims[k] > p.Imax) p.Imax = (int)p.dims[k];
   }
-  WS(h, "rf", (size_t)N * R * R * 8, p.rf);
-  WS(h, "lambda", (size_t)R * 8, p.lambda);
+  WS(h, p.prefix + "rf", (size_t)N * R * R * 8, p.rf);
+  WS(h, p.prefix + "lambda", (size_t)R * 8, p.lambda);
   p.M = ipow(R, N - 1);
   const TsqrPlan pl = tsqr_plan(p.M, R);
   if (!pl.ok) return fail(h, CPQR_EUNSUPPORTED, "no TSQR plan for %lld x %d", (long long)p.M, R);
   p.leaf_rows = pl.leaf_rows;
   p.P = pl.P;
-  for (int k = 0; k < N; ++k) WS(h, "q0_" + std::to_string(k), (size_t)2 * p.M * R * 8, p.q0buf[k]);
-  WS(h, "tsqrV", (size_t)p.P * p.leaf_rows * R * 8, p.tV);
-  WS(h, "tsqrT", (size_t)p.P * R * R * 8, p.tT);
-  WS(h, "tsqrS", (size_t)p.P * R * R * 8, p.tStack);
-  WS(h, "tsqrQ", (size_t)p.P * R * R * 8, p.tQtop);
-  WS(h, "R0", (size_t)R * R * 8, p.R0);
+  for (int k = 0; k < N; ++k) WS(h, p.prefix + "q0_" + std::to_string(k), (size_t)2 * p.M * R * 8, p.q0buf[k]);
+  WS(h, p.prefix + "tsqrV", (size_t)p.P * p.leaf_rows * R * 8, p.tV);
+  WS(h, p.prefix + "tsqrT", (size_t)p.P * R * R * 8, p.tT);
+  WS(h, p.prefix + "tsqrS", (size_t)p.P * R * R * 8, p.tStack);
+  WS(h, p.prefix + "tsqrQ", (size_t)p.P * R * R * 8, p.tQtop);
+  WS(h, p.prefix + "R0", (size_t)R * R * 8, p.R0);
   int nch = 1;
   for (int k = 0; k < N; ++k) {
     const int c = apply_num_chunks(p.M, (int)p.dims[k]);
     if (c > nch) nch = c;
   }
   p.nchunks_max = nch;
-  WS(h, "partial", (size_t)nch * 2 * p.Imax * R * 8, p.partial);
-  WS(h, "V", (size_t)2 * p.Imax * R * 8, p.Vbuf);
-  WS(h, "state", sizeof(DevState), p.state);
-  WS(h, "fit_hist", (size_t)(iters > 0 ? iters : 1) * 8, p.fit_hist);
-  WS(h, "norm_part", 4096 * 8, p.norm_part);
+  WS(h, p.prefix + "partial", (size_t)nch * 2 * p.Imax * R * 8, p.partial);
+  WS(h, p.prefix + "V", (size_t)2 * p.Imax * R * 8, p.Vbuf);
+  WS(h, p.prefix + "state", sizeof(DevState), p.state);
+  WS(h, p.prefix + "fit_hist", (size_t)(iters > 0 ? iters : 1) * 8, p.fit_hist);
+  WS(h, p.prefix + "norm_part", 4096 * 8, p.norm_part);
   // intermediates used by the schedule
   const uint32_t full = (1u << N) - 1u;
   for (const auto& sw : sched)
@@ -210,7 +214,7 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
         const uint32_t dst = st.src & ~(1u << st.mode);
         if (!p.inter.count(dst)) {
           void* ptr = nullptr;
-          WS(h, "Y" + std::to_string(dst), (size_t)inter_elems(p, dst) * p.elem, ptr);
+          WS(h, p.prefix + "Y" + std::to_string(dst), (size_t)inter_elems(p, dst) * p.elem, ptr);
           p.inter[dst] = ptr;
         }
       }
@@ -218,8 +222,9 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   return CPQR_OK;
 }
 
-hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s, hipEvent_t ev0 = nullptr,
-                           hipEvent_t ev1 = nullptr) {
+// TTM of one schedule step: input (X or a cached intermediate), output
+// intermediate and the [L, I, S] view around the contracted mode.
+TtmArgs ttm_step_args(const Problem& p, const Step& st) {
   const uint32_t full = (1u << p.N) - 1u;
   const void* in = (st.src == full) ? p.X : p.inter.at(st.src);
   void* out = p.inter.at(st.src & ~(1u << st.mode));
@@ -229,67 +234,80 @@ hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s, hipE
     if (k < st.mode) L *= d;
     if (k > st.mode) S *= d;
   }
-  const int I = (int)p.dims[st.mode];
+  return TtmArgs{(const float*)in, (const float*)p.Q[st.mode], (float*)out, L, S,
+                 (int)p.dims[st.mode], p.R};
+}
+
+hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr) {
+  const TtmArgs a = ttm_step_args(p, st);
   if (p.f64)
-    return launch_ttm_f64((const double*)in, (const double*)p.Q[st.mode], (double*)out, L, I, S, p.R, s,
+    return launch_ttm_f64((const double*)a.in, (const double*)a.Q, (double*)a.out, a.L, a.I, a.S, a.R, s,
                           ev0, ev1);
-  return launch_ttm_f32((const float*)in, (const float*)p.Q[st.mode], (float*)out, L, I, S, p.R,
-                        p.prec == CPQR_PREC_BF16X3, s, ev0, ev1);
+  return launch_ttm_f32(a.in, a.Q, a.out, a.L, a.I, a.S, a.R, p.prec == CPQR_PREC_BF16X3, s, ev0, ev1);
+}
+
+// Arguments of the mode-n update of sweep k (Z QR, Y*Q0, finish).  Q0 of
+// the sweep and of the previous sweep are the two halves of the mode's
+// ping-pong buffer.
+void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o, TsqrArgs* t,
+                 ApplyArgs* a, FinishArgs* f) {
+  const int R = p.R;
+  double* q0cur = p.q0buf[n] + (size_t)(sweep_k % 2) * p.M * R;
+  double* q0prev = (sweep_k >= 2) ? p.q0buf[n] + (size_t)((sweep_k - 1) % 2) * p.M * R : nullptr;
+  t->N = p.N;
+  t->n = n;
+  t->R = R;
+  t->rf = p.rf;
+  t->src = nullptr;
+  t->M = p.M;
+  t->P = p.P;
+  t->V = p.tV;
+  t->T = p.tT;
+  t->stack = p.tStack;
+  t->R0 = p.R0;
+  t->Qtop = p.tQtop;
+  t->Q0 = q0cur;
+  a->Y = p.inter.at(1u << n);
+  a->y_f64 = p.f64;
+  a->L = ipow(R, n);
+  a->I = (int)p.dims[n];
+  a->S = ipow(R, p.N - 1 - n);
+  a->R = R;
+  a->Q0 = q0cur;
+  a->Q0prev = (o->extrapolate == CPQR_EXTRAP_PAPER) ? q0prev : nullptr;
+  a->partial = p.partial;
+  a->V = p.Vbuf;
+  a->nchunks = apply_num_chunks(p.M, a->I);
+  a->state = p.state;
+  f->I = (int)p.dims[n];
+  f->R = R;
+  f->V = p.Vbuf;
+  f->R0 = p.R0;
+  f->A = p.A[n];
+  f->lambda = p.lambda;
+  f->Rn = p.rf + (size_t)n * R * R;
+  f->q64 = p.f64 ? (double*)p.Q[n] : nullptr;
+  f->q32 = p.f64 ? nullptr : (float*)p.Q[n];
+  f->state = p.state;
+  f->fit_hist = p.fit_hist;
+  f->alpha = o->alpha;
+  f->delta = o->switch_delta;
+  f->fixed_beta = o->fixed_beta;
+  f->extrap = o->extrapolate;
+  f->last_in_sweep = last ? 1 : 0;
 }
 
 hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
                          hipStream_t s) {
-  const int R = p.R;
-  double* q0cur = p.q0buf[n] + (size_t)(sweep_k % 2) * p.M * R;
-  double* q0prev = (sweep_k >= 2) ? p.q0buf[n] + (size_t)((sweep_k - 1) % 2) * p.M * R : nullptr;
   TsqrArgs t;
-  t.N = p.N;
-  t.n = n;
-  t.R = R;
-  t.rf = p.rf;
-  t.src = nullptr;
-  t.M = p.M;
-  t.P = p.P;
-  t.V = p.tV;
-  t.T = p.tT;
-  t.stack = p.tStack;
-  t.R0 = p.R0;
-  t.Qtop = p.tQtop;
-  t.Q0 = q0cur;
+  ApplyArgs a;
+  FinishArgs f;
+  update_args(p, n, sweep_k, last, o, &t, &a, &f);
   hipError_t e = launch_tsqr(t, s);
   if (e != hipSuccess) return e;
-  ApplyArgs a;
-  a.Y = p.inter.at(1u << n);
-  a.y_f64 = p.f64;
-  a.L = ipow(R, n);
-  a.I = (int)p.dims[n];
-  a.S = ipow(R, p.N - 1 - n);
-  a.R = R;
-  a.Q0 = q0cur;
-  a.Q0prev = (o->extrapolate == CPQR_EXTRAP_PAPER) ? q0prev : nullptr;
-  a.partial = p.partial;
-  a.V = p.Vbuf;
-  a.nchunks = apply_num_chunks(p.M, a.I);
-  a.state = p.state;
   e = launch_apply(a, s);
   if (e != hipSuccess) return e;
-  FinishArgs f;
-  f.I = (int)p.dims[n];
-  f.R = R;
-  f.V = p.Vbuf;
-  f.R0 = p.R0;
-  f.A = p.A[n];
-  f.lambda = p.lambda;
-  f.Rn = p.rf + (size_t)n * R * R;
-  f.q64 = p.f64 ? (double*)p.Q[n] : nullptr;
-  f.q32 = p.f64 ? nullptr : (float*)p.Q[n];
-  f.state = p.state;
-  f.fit_hist = p.fit_hist;
-  f.alpha = o->alpha;
-  f.delta = o->switch_delta;
-  f.fixed_beta = o->fixed_beta;
-  f.extrap = o->extrapolate;
-  f.last_in_sweep = last ? 1 : 0;
   return launch_finish(f, s);
 }
 
@@ -503,17 +521,19 @@ cpqr_status cpqr_check_args(const cpqr_tensor* X, int rank, const cpqr_options* 
   return check_args(nullptr, X, rank, o);
 }
 
-cpqr_status cpqr_session_create(cpqr_handle* h, const cpqr_tensor* X, int rank,
-                                const cpqr_options* o, cpqr_session** out) {
-  if (!h) return CPQR_EINVAL;
-  h->err.clear();
-  if (!out) return fail(h, CPQR_EINVAL, "null session pointer");
+}  // extern "C"
+
+namespace {
+
+// Creates the device state of one decomposition (workspace names prefixed by
+// `prefix`), computes ||X||^2 and the QRs of the initial factors.
+cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpqr_options* o,
+                                const std::string& prefix, cpqr_session** out) {
   *out = nullptr;
   {
     cpqr_status v = check_args(h, X, rank, o);
     if (v != CPQR_OK) return v;
   }
-  if (h->busy) return fail(h, CPQR_EINVAL, "the handle already has a live session");
   const int N = X->order;
   std::unique_ptr<cpqr_session> ss(new cpqr_session());
   cpqr_session& S = *ss;
@@ -526,6 +546,7 @@ cpqr_status cpqr_session_create(cpqr_handle* h, const cpqr_tensor* X, int rank,
   HIP_TRY(h, order_after_user(h));
   hipStream_t s = h->stream;
   Problem& p = S.p;
+  p.prefix = prefix;
   p.N = N;
   p.R = rank;
   p.prec = o->prec;
@@ -557,9 +578,24 @@ cpqr_status cpqr_session_create(cpqr_handle* h, const cpqr_tensor* X, int rank,
   S.nx2 = hs.nx2;
   HIP_TRY(h, hipEventCreate(&S.t0));
   HIP_TRY(h, hipEventCreate(&S.t1));
-  h->busy = true;
   *out = ss.release();
   return CPQR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpqr_status cpqr_session_create(cpqr_handle* h, const cpqr_tensor* X, int rank,
+                                const cpqr_options* o, cpqr_session** out) {
+  if (!h) return CPQR_EINVAL;
+  h->err.clear();
+  if (!out) return fail(h, CPQR_EINVAL, "null session pointer");
+  *out = nullptr;
+  if (h->busy) return fail(h, CPQR_EINVAL, "the handle already has a live session");
+  cpqr_status st = session_create_impl(h, X, rank, o, "", out);
+  if (st == CPQR_OK) h->busy = true;
+  return st;
 }
 
 cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
@@ -607,13 +643,33 @@ cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
         hipError_t e;
         if (st.kind == STEP_TTM) {
           if (timing && st.src == full) {
+            // The level-1 TTM is idempotent (it rewrites its output from X and
+            // Q_m), so it is timed as a graph of kTimeReps back-to-back
+            // launches between two events: the per-launch average then holds
+            // no event or launch overhead.
+            const std::string gk = "l1rep:" + std::to_string(st.src) + ":" + std::to_string(st.mode);
+            auto itr = S->graphs.find(gk);
+            if (itr == S->graphs.end()) {
+              hipGraph_t g;
+              if ((e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+              hipError_t el = hipSuccess;
+              for (int r = 0; r < kTimeReps && el == hipSuccess; ++r) el = launch_ttm_step(p, st, q);
+              if ((e = hipStreamEndCapture(q, &g)) != hipSuccess) return e;
+              if (el != hipSuccess) return el;
+              hipGraphExec_t ge;
+              e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+              (void)hipGraphDestroy(g);
+              if (e != hipSuccess) return e;
+              itr = S->graphs.emplace(gk, ge).first;
+            }
             hipEvent_t a, b;
             if ((e = hipEventCreate(&a)) != hipSuccess) return e;
             if ((e = hipEventCreate(&b)) != hipSuccess) return e;
             S->evs.push_back(a);
             S->evs.push_back(b);
-            // events stamped by the kernel dispatch itself (start and end of the kernel)
-            if ((e = launch_ttm_step(p, st, q, a, b)) != hipSuccess) return e;
+            if ((e = hipEventRecord(a, q)) != hipSuccess) return e;
+            if ((e = hipGraphLaunch(itr->second, q)) != hipSuccess) return e;
+            if ((e = hipEventRecord(b, q)) != hipSuccess) return e;
           } else {
             if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
           }
@@ -686,7 +742,7 @@ cpqr_status cpqr_session_result(cpqr_session* S, cpqr_result* res) {
   for (size_t i = 0; i + 1 < S->evs.size(); i += 2) {
     float e = 0.f;
     HIP_TRY(h, hipEventElapsedTime(&e, S->evs[i], S->evs[i + 1]));
-    l1_sec += e * 1e-3;
+    l1_sec += e * 1e-3 / kTimeReps;
   }
   DevState hs;
   HIP_TRY(h, hipMemcpy(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost));
@@ -767,6 +823,373 @@ cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cp
   cpqr_session_destroy(S);
   h->err = msg;
   return st;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+void count_ttm(cpqr_session* S, const std::vector<Step>& sw) {
+  Problem& p = S->p;
+  const uint32_t full = (1u << p.N) - 1u;
+  for (const Step& st : sw)
+    if (st.kind == STEP_TTM) {
+      const int64_t in = inter_elems(p, st.src);
+      const int64_t outn = in / p.dims[st.mode] * p.R;
+      S->ttm_flops += 2.0 * in * p.R;
+      S->ttm_bytes += (double)(in + outn) * p.elem;
+      if (st.src == full) {
+        S->l1_bytes += (double)(in + outn) * p.elem;
+        S->l1_flops += 2.0 * in * p.R;
+        ++S->l1_count;
+      }
+    }
+}
+
+// One batched launch of a sweep's step list, with the byte offsets of its
+// argument arrays inside the sweep's argument blob.
+struct BatchItem {
+  int kind = 0;                 // 0 TTM, 1 TSQR, 2 Y*Q0, 3 finish
+  std::string tune_sig;         // TTM: identifies the step for the autotuner
+  std::vector<int> members;     // problem indices
+  TtmBatch tb{};
+  TsqrBatch qb{};
+  ApplyBatch ab{};
+  int fin_rmax = 0, fin_rpt = 0;
+  size_t off[3] = {0, 0, 0};
+};
+
+struct BatchRun {
+  cpqr_handle* h = nullptr;
+  std::vector<cpqr_session*> S;
+  std::map<std::string, hipGraphExec_t> graphs;
+  std::map<std::string, int> tuned_ks;
+  ~BatchRun() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (cpqr_session* x : S) delete x;
+  }
+};
+
+template <typename T>
+size_t blob_put(std::vector<char>& blob, const std::vector<T>& v) {
+  const size_t off = (blob.size() + 63) & ~size_t(63);
+  blob.resize(off + v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+// TTM launch shape of a group at K split ks; false if some member cannot use it.
+bool ttm_group_shape(const std::vector<TtmArgs>& args, int ks, unsigned* wgs, size_t* lds) {
+  *wgs = 1;
+  *lds = 0;
+  for (const TtmArgs& a : args) {
+    int k = ks;
+    unsigned w = 0;
+    size_t l = 0;
+    if (!ttm_batch_shape(a.L == 1 ? a.S : a.L * a.S, a.I, a.R, &k, &w, &l)) return false;
+    if (w > *wgs) *wgs = w;
+    if (l > *lds) *lds = l;
+  }
+  return true;
+}
+
+// Builds the launches of sweep k for every problem (grouped by the kernels'
+// compile-time classes) and their argument blob.
+void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpqr_options* o,
+                      std::vector<BatchItem>* items, std::vector<char>* blob,
+                      std::vector<std::vector<TtmArgs>>* ttm_host) {
+  const int count = (int)B.S.size();
+  const bool bf = o->prec == CPQR_PREC_BF16X3;
+  int last_update = -1;
+  for (size_t i = 0; i < sw.size(); ++i)
+    if (sw[i].kind == STEP_UPDATE) last_update = (int)i;
+  for (size_t i = 0; i < sw.size(); ++i) {
+    const Step& st = sw[i];
+    if (st.kind == STEP_TTM) {
+      std::map<int, std::vector<int>> by_nb;
+      for (int t = 0; t < count; ++t) by_nb[(B.S[t]->p.R + 15) / 16].push_back(t);
+      for (auto& g : by_nb) {
+        BatchItem it;
+        it.kind = 0;
+        it.members = g.second;
+        std::vector<TtmArgs> args;
+        bool vec = true, buf = true;
+        for (int t : g.second) {
+          args.push_back(ttm_step_args(B.S[t]->p, st));
+          vec = vec && ttm_vec_legal(args.back());
+          buf = buf && ttm_buf_legal(args.back());
+        }
+        it.tune_sig = std::to_string(st.src) + "/" + std::to_string(st.mode) + "/" + std::to_string(g.first);
+        it.tb.count = (int)args.size();
+        it.tb.kc = args[0].L == 1;
+        it.tb.vec = vec;
+        it.tb.bf16x3 = bf;
+        it.tb.buf = buf;
+        it.tb.nb = g.first;
+        auto tk = B.tuned_ks.find(it.tune_sig);
+        it.tb.ks = tk != B.tuned_ks.end() ? tk->second : 1;
+        if (!ttm_group_shape(args, it.tb.ks, &it.tb.wgs, &it.tb.lds)) {
+          it.tb.ks = 1;
+          ttm_group_shape(args, 1, &it.tb.wgs, &it.tb.lds);
+        }
+        it.off[0] = blob_put(*blob, args);
+        ttm_host->push_back(args);
+        items->push_back(it);
+      }
+    } else {
+      const bool last = (int)i == last_update;
+      std::vector<TsqrArgs> ts(count);
+      std::vector<ApplyArgs> as(count);
+      std::vector<FinishArgs> fs(count);
+      for (int t = 0; t < count; ++t) update_args(B.S[t]->p, st.mode, k, last, o, &ts[t], &as[t], &fs[t]);
+      // TSQR groups: rank class and plan
+      std::map<std::tuple<int, int, int>, std::vector<int>> tg;
+      for (int t = 0; t < count; ++t) {
+        const TsqrPlan pl = tsqr_plan(ts[t].M, ts[t].R);
+        tg[std::make_tuple(qr_rmax(ts[t].R), pl.leaf_rpt, pl.P > 1 ? pl.top_rpt : 0)].push_back(t);
+      }
+      for (auto& g : tg) {
+        BatchItem it;
+        it.kind = 1;
+        it.members = g.second;
+        std::vector<LeafArgs> la;
+        std::vector<TopArgs> ta;
+        std::vector<FormArgs> fa;
+        int Pmax = 1;
+        unsigned chunks = 1;
+        for (int t : g.second) {
+          const TsqrPlan pl = tsqr_plan(ts[t].M, ts[t].R);
+          LeafArgs l;
+          TopArgs tp;
+          FormArgs f;
+          tsqr_args(ts[t], pl, &l, &tp, &f);
+          la.push_back(l);
+          ta.push_back(tp);
+          fa.push_back(f);
+          if (pl.P > Pmax) Pmax = pl.P;
+          const unsigned c = (unsigned)((ts[t].M + 255) / 256);
+          if (c > chunks) chunks = c;
+        }
+        it.qb = TsqrBatch{(int)g.second.size(), std::get<0>(g.first), std::get<1>(g.first),
+                          std::get<2>(g.first), Pmax, std::get<2>(g.first) > 0 ? 1 : 0, chunks,
+                          nullptr, nullptr, nullptr};
+        it.off[0] = blob_put(*blob, la);
+        it.off[1] = blob_put(*blob, ta);
+        it.off[2] = blob_put(*blob, fa);
+        items->push_back(it);
+      }
+      // Y*Q0 groups: rank class
+      std::map<int, std::vector<int>> ag;
+      for (int t = 0; t < count; ++t) ag[qr_rmax(as[t].R)].push_back(t);
+      for (auto& g : ag) {
+        BatchItem it;
+        it.kind = 2;
+        it.members = g.second;
+        std::vector<ApplyDev> ad;
+        unsigned ib = 1, nc = 1, rb = 1;
+        for (int t : g.second) {
+          ad.push_back(apply_dev(as[t]));
+          ib = std::max(ib, apply_iblocks(as[t].I));
+          nc = std::max(nc, (unsigned)as[t].nchunks);
+          rb = std::max(rb, apply_reduce_blocks(as[t].I, as[t].R));
+        }
+        it.ab = ApplyBatch{(int)g.second.size(), g.first, false, ib, nc, rb, nullptr};
+        it.off[0] = blob_put(*blob, ad);
+        items->push_back(it);
+      }
+      // finish groups: rank class and rows per thread
+      std::map<std::pair<int, int>, std::vector<int>> fg;
+      for (int t = 0; t < count; ++t) fg[{qr_rmax(fs[t].R), factor_rpt(fs[t].I)}].push_back(t);
+      for (auto& g : fg) {
+        BatchItem it;
+        it.kind = 3;
+        it.members = g.second;
+        std::vector<FinishArgs> fv;
+        for (int t : g.second) fv.push_back(fs[t]);
+        it.fin_rmax = g.first.first;
+        it.fin_rpt = g.first.second;
+        it.off[0] = blob_put(*blob, fv);
+        items->push_back(it);
+      }
+    }
+  }
+}
+
+hipError_t launch_item(const BatchItem& it, const char* base, hipStream_t s) {
+  switch (it.kind) {
+    case 0: {
+      TtmBatch b = it.tb;
+      b.args = reinterpret_cast<const TtmArgs*>(base + it.off[0]);
+      return launch_ttm_f32_batched(b, s);
+    }
+    case 1: {
+      TsqrBatch b = it.qb;
+      b.leaf = reinterpret_cast<const LeafArgs*>(base + it.off[0]);
+      b.top = reinterpret_cast<const TopArgs*>(base + it.off[1]);
+      b.form = reinterpret_cast<const FormArgs*>(base + it.off[2]);
+      return launch_tsqr_batched(b, s);
+    }
+    case 2: {
+      ApplyBatch b = it.ab;
+      b.args = reinterpret_cast<const ApplyDev*>(base + it.off[0]);
+      return launch_apply_batched(b, s);
+    }
+    default:
+      return launch_finish_batched((int)it.members.size(), it.fin_rmax, it.fin_rpt,
+                                   reinterpret_cast<const FinishArgs*>(base + it.off[0]), s);
+  }
+}
+
+// Autotuner: for every TTM group not tuned yet, times the K splits that fit
+// (1, 2, 4 waves per tile) with outputs redirected to scratch memory, so that
+// no cached intermediate is disturbed, and keeps the fastest.
+cpqr_status tune_ttm(BatchRun& B, std::vector<BatchItem>& items,
+                     const std::vector<std::vector<TtmArgs>>& ttm_host) {
+  cpqr_handle* h = B.h;
+  hipStream_t s = h->stream;
+  size_t ti = 0;
+  for (BatchItem& it : items) {
+    if (it.kind != 0) continue;
+    const std::vector<TtmArgs>& args = ttm_host[ti++];
+    if (B.tuned_ks.count(it.tune_sig)) continue;
+    std::vector<TtmArgs> scratch = args;
+    size_t total = 0;
+    for (const TtmArgs& a : args) total += (size_t)(a.L * a.S * a.R) * 4 + 256;
+    char* out = nullptr;
+    WS(h, "batch:tune_out", total, out);
+    size_t pos = 0;
+    for (TtmArgs& a : scratch) {
+      a.out = reinterpret_cast<float*>(out + pos);
+      pos += ((size_t)(a.L * a.S * a.R) * 4 + 255) & ~size_t(255);
+    }
+    TtmArgs* dargs = nullptr;
+    WS(h, "batch:tune_args", scratch.size() * sizeof(TtmArgs), dargs);
+    HIP_TRY(h, hipMemcpy(dargs, scratch.data(), scratch.size() * sizeof(TtmArgs), hipMemcpyHostToDevice));
+    hipEvent_t e0, e1;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    int best = 1;
+    float best_ms = 1e30f;
+    for (int ks : {1, 2, 4}) {
+      TtmBatch b = it.tb;
+      b.ks = ks;
+      if (!ttm_group_shape(args, ks, &b.wgs, &b.lds)) continue;
+      b.args = dargs;
+      HIP_TRY(h, launch_ttm_f32_batched(b, s));
+      HIP_TRY(h, hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) HIP_TRY(h, launch_ttm_f32_batched(b, s));
+      HIP_TRY(h, hipEventRecord(e1, s));
+      HIP_TRY(h, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = ks;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B.tuned_ks[it.tune_sig] = best;
+    it.tb.ks = best;
+    ttm_group_shape(args, best, &it.tb.wgs, &it.tb.lds);
+  }
+  return CPQR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs, const int* ranks,
+                                const cpqr_options* opts, cpqr_result* results) {
+  if (!h) return CPQR_EINVAL;
+  h->err.clear();
+  if (count < 1 || !Xs || !ranks || !opts || !results)
+    return fail(h, CPQR_EINVAL, "batched: count >= 1 and non-null arrays required");
+  if (h->busy) return fail(h, CPQR_EINVAL, "the handle already has a live session");
+  const cpqr_options& o0 = opts[0];
+  for (int t = 0; t < count; ++t) {
+    cpqr_status v = check_args(h, &Xs[t], ranks[t], &opts[t]);
+    if (v != CPQR_OK) {
+      const std::string m = h->err;
+      return fail(h, v, "batched problem %d: %s", t, m.c_str());
+    }
+    const cpqr_options& o = opts[t];
+    if (Xs[t].order != Xs[0].order || o.tree != o0.tree || o.extrapolate != o0.extrapolate ||
+        o.prec != o0.prec || o.iters != o0.iters || o.alpha != o0.alpha ||
+        o.switch_delta != o0.switch_delta || o.fixed_beta != o0.fixed_beta)
+      return fail(h, CPQR_EINVAL, "batched problem %d: order and options must match problem 0", t);
+    if (o.tol != 0.0) return fail(h, CPQR_EINVAL, "batched runs a fixed number of sweeps: tol must be 0");
+  }
+  if (o0.prec == CPQR_PREC_FP64) return fail(h, CPQR_EUNSUPPORTED, "batched: FP32 or BF16X3 TTMs only");
+  HIP_TRY(h, hipSetDevice(h->device));
+  HIP_TRY(h, order_after_user(h));
+  hipStream_t s = h->stream;
+  BatchRun B;
+  B.h = h;
+  h->busy = true;
+  struct Unbusy { cpqr_handle* h; ~Unbusy() { h->busy = false; } } unbusy{h};
+  for (int t = 0; t < count; ++t) {
+    cpqr_session* S = nullptr;
+    cpqr_status st = session_create_impl(h, &Xs[t], ranks[t], &opts[t], "b" + std::to_string(t) + ":", &S);
+    if (st != CPQR_OK) {
+      const std::string m = h->err;
+      return fail(h, st, "batched problem %d: %s", t, m.c_str());
+    }
+    B.S.push_back(S);
+  }
+  for (cpqr_session* S : B.S) {
+    HIP_TRY(h, hipEventRecord(S->t0, s));
+    S->t0_recorded = true;
+  }
+  const auto& sched = B.S[0]->sched;
+  for (int k = 1; k <= o0.iters; ++k) {
+    const auto& sw = sched[k - 1];
+    const std::string key = sweep_key(sw, k == 1 ? 2 : (k % 2), o0.extrapolate != 0);
+    auto itg = B.graphs.find(key);
+    if (itg == B.graphs.end()) {
+      std::vector<BatchItem> items;
+      std::vector<char> blob;
+      std::vector<std::vector<TtmArgs>> ttm_host;
+      build_sweep_plan(B, k, sw, &o0, &items, &blob, &ttm_host);
+      cpqr_status ts = tune_ttm(B, items, ttm_host);
+      if (ts != CPQR_OK) return ts;
+      char* dblob = nullptr;
+      WS(h, "batch:args:" + key, blob.size() + 64, dblob);
+      HIP_TRY(h, hipMemcpy(dblob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+      hipGraph_t g;
+      HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (const BatchItem& it : items)
+        if ((e = launch_item(it, dblob, s)) != hipSuccess) break;
+      hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess) return fail(h, CPQR_EHIP, "batched launch during capture failed: %s", hipGetErrorString(e));
+      if (e2 != hipSuccess) return fail(h, CPQR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+      hipGraphExec_t ge;
+      hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e3 != hipSuccess) return fail(h, CPQR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+      itg = B.graphs.emplace(key, ge).first;
+    }
+    HIP_TRY(h, hipGraphLaunch(itg->second, s));
+    for (cpqr_session* S : B.S) {
+      S->k = k;
+      count_ttm(S, sw);
+    }
+  }
+  HIP_TRY(h, hipStreamSynchronize(s));
+  cpqr_status first = CPQR_OK;
+  std::string first_msg;
+  for (int t = 0; t < count; ++t) {
+    cpqr_status st = cpqr_session_result(B.S[t], &results[t]);
+    if (st != CPQR_OK && first == CPQR_OK) {
+      first = st;
+      first_msg = "batched problem " + std::to_string(t) + ": " + h->err;
+    }
+  }
+  h->err = first_msg;
+  return first;
 }
 
 }  // extern "C"

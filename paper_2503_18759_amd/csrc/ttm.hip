@@ -885,17 +885,23 @@ static bool ttm_vec_ok(const TtmArgs& a) {
   return (a.L % 4) == 0 && (((uintptr_t)a.in) & 15) == 0 && (((uintptr_t)a.out) & 15) == 0;
 }
 
-void ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds) {
+bool ttm_vec_legal(const TtmArgs& a) { return ttm_vec_ok(a); }
+bool ttm_buf_legal(const TtmArgs& a) { return a.L * (int64_t)a.I * a.S * 4 < TTM_BUF_LIMIT - 64; }
+
+bool ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds) {
   const int NB = (R + 15) / 16;
   const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
-  *ks = ttm_pick_ks(tiles, I, NB);
-  *wgs = ttm_grid(tiles, *ks).x;
+  if (*ks <= 0) *ks = ttm_pick_ks(tiles, I, NB);
+  if (*ks != 1 && *ks != 2 && *ks != 4) return false;
   *lds = ttm_q_lds(I, NB) + ttm_red_lds(*ks, NB);
+  if (*lds > 64 * 1024 || (I + 31) / 32 < *ks) return false;
+  *wgs = ttm_grid(tiles, *ks).x;
+  return true;
 }
 
 hipError_t launch_ttm_f32_batched(const TtmBatch& b, hipStream_t st) {
   if (b.count <= 0) return hipSuccess;
-  return launch_f32_any(b.nb, true, b.kc, b.vec, b.bf16x3, dim3(b.wgs, (unsigned)b.count), b.lds, st,
+  return launch_f32_any(b.nb, b.buf, b.kc, b.vec, b.bf16x3, dim3(b.wgs, (unsigned)b.count), b.lds, st,
                         TtmArgs{}, b.args, b.ks);
 }
 
@@ -924,7 +930,7 @@ hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L
   const int64_t rows = L == 1 ? S : L * S;
   const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
   const int ks = ttm_pick_ks(tiles, I, NB);
-  const bool buf = L * (int64_t)I * S * 4 < TTM_BUF_LIMIT - 64;
+  const bool buf = ttm_buf_legal(a);
   return launch_f32_any(NB, buf, L == 1, ttm_vec_ok(a), bf16x3, ttm_grid(tiles, ks),
                         ttm_q_lds(I, NB) + ttm_red_lds(ks, NB), st, a, nullptr, ks, ev0, ev1);
 }

@@ -143,7 +143,9 @@ static hipError_t apply_launch(int rm, bool y_f64, dim3 grid, dim3 rgrid, const 
   return hipGetLastError();
 }
 
-static unsigned apply_reduce_blocks(int I, int R) {
+unsigned apply_iblocks(int I) { return (unsigned)((I + AP_ROWS - 1) / AP_ROWS); }
+
+unsigned apply_reduce_blocks(int I, int R) {
   const int64_t n = 2 * (int64_t)I * R;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 1024) blocks = 1024;

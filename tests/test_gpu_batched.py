@@ -1,0 +1,166 @@
+"""GPU parity of the batched sweep (cpqr_als_qr_batched) with the FP64 oracle
+run problem by problem on the same seeded inputs and initial factors.
+
+Tolerances are those of the single-problem float32 chain (see
+test_gpu_als.py): explicit fit within 1e-6, per-sweep fit within
+1e-6 + 5e-7 / (1 - fit), same update orders, and every factor column aligned
+with the oracle's (|cos| > 1 - 1e-3).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthgen as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2503_18759_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    P.load_library()
+    return P
+
+
+def _fit_tol(fo):
+    return 1e-6 + 5e-7 / max(1e-12, 1.0 - fo)
+
+
+def _mixed_batch():
+    """Problems in all three rank classes (8, 16, 32 columns), single-leaf and
+    two-leaf Z QRs (R = 18 and 23 give 324 and 529 Khatri-Rao rows), ragged
+    mode sizes and one problem whose leading mode is not a multiple of 4."""
+    specs = [([11, 9, 13], 3, 501), ([17, 23, 14], 6, 502), ([21, 19, 25], 9, 503),
+             ([26, 22, 30], 13, 504), ([31, 27, 24], 18, 505), ([29, 33, 26], 23, 506),
+             ([15, 12, 10], 4, 507)]
+    return [G.make_problem(d, r, seed=s, congruence=0.5, rho=0.01, dtype=np.float32)
+            for d, r, s in specs]
+
+
+def _check(g, prob, iters, extrap="off"):
+    o = O.cp_als_qr(prob.X.astype(np.float64), prob.rank, prob.init, iters,
+                    tree="restructured", extrap=extrap)
+    assert g["orders"] == o["orders"]
+    assert g["sweeps"] == iters
+    for fg, fo in zip(g["fits"], o["fits"]):
+        assert abs(fg - fo) <= _fit_tol(fo), (fg, fo)
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-6, (g["fit_explicit"], o["fitx"])
+    for a, b in zip(g["factors"], o["factors"]):
+        cos = np.abs(np.sum(a * b, axis=0))
+        assert np.all(cos > 1 - 1e-3), cos
+    return o
+
+
+def _run(P, probs, iters, **kw):
+    xs, dims = [], []
+    for p in probs:
+        x, d = P.to_device(p.X)
+        xs.append(x)
+        dims.append(d)
+    return P.cp_als_qr_batched(xs, [p.rank for p in probs], [p.init for p in probs], iters,
+                               dims=dims, explicit_fit=True, **kw)
+
+
+def test_batched_mixed_ranks_vs_oracle(P):
+    probs = _mixed_batch()
+    res = _run(P, probs, 10)
+    assert len(res) == len(probs)
+    for g, p in zip(res, probs):
+        _check(g, p, 10)
+
+
+def test_batched_paper_extrapolation_vs_oracle(P):
+    probs = [G.make_problem([20, 22, 18], 4, seed=21, congruence=0.6, rho=0.05, dtype=np.float32),
+             G.make_problem([30, 26, 34], 5, seed=22, congruence=0.7, rho=0.02, dtype=np.float32),
+             G.make_problem([24, 28, 20], 11, seed=23, congruence=0.5, rho=0.03, dtype=np.float32)]
+    res = _run(P, probs, 30, extrapolate="paper")
+    for g, p in zip(res, probs):
+        o = _check(g, p, 30, extrap="paper")
+        assert g["beta_sweep"] == o["beta_sweep"] and g["beta"] == o["beta"]
+
+
+def test_batched_bf16x3(P):
+    probs = _mixed_batch()[:4]
+    res = _run(P, probs, 8, prec="bf16x3")
+    for g, p in zip(res, probs):
+        o = O.cp_als_qr(p.X.astype(np.float64), p.rank, p.init, 8, tree="restructured")
+        assert g["orders"] == o["orders"]
+        assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-4
+
+
+def test_batched_equals_single_runs(P):
+    """The batched kernels compute what the single-problem path computes; only
+    the TTM K split (autotuned) may change the float32 summation order."""
+    probs = _mixed_batch()[:5]
+    res = _run(P, probs, 6)
+    for g, p in zip(res, probs):
+        x, d = P.to_device(p.X)
+        s = P.cp_als_qr(x, p.rank, p.init, 6, dims=d, tree="restructured", explicit_fit=True)
+        assert g["orders"] == s["orders"]
+        assert np.max(np.abs(g["fits"] - s["fits"])) <= 1e-6
+        assert abs(g["fit_explicit"] - s["fit_explicit"]) <= 1e-7
+
+
+def test_batched_full_size_64_problems(P):
+    """The 64-problem workload (dims U{32..160}^3, ranks U{4..24}, 1% noise) at
+    full size: three sweeps for the whole batch; a seeded sample of problems
+    is checked against the oracle."""
+    probs = G.batched_workload(64)
+    res = _run(P, probs, 3)
+    assert len(res) == 64
+    for g in res:
+        assert g["sweeps"] == 3 and np.all(np.isfinite(g["fits"]))
+    pick = np.random.default_rng(7).choice(64, size=4, replace=False)
+    for t in pick:
+        _check(res[t], probs[t], 3)
+
+
+@pytest.mark.parametrize("case", ["mixed_order", "tol", "fp64"])
+def test_batched_argument_errors(P, case):
+    probs = _mixed_batch()[:2]
+    xs, dims = [], []
+    for p in probs:
+        x, d = P.to_device(p.X)
+        xs.append(x)
+        dims.append(d)
+    ranks = [p.rank for p in probs]
+    inits = [p.init for p in probs]
+    kw = {}
+    if case == "mixed_order":
+        q = G.make_problem([6, 5, 7, 4], 2, seed=9, congruence=None, rho=0.01, dtype=np.float32)
+        x, d = P.to_device(q.X)
+        xs[1], dims[1], ranks[1], inits[1] = x, d, q.rank, q.init
+        expect = P.cpqr.EINVAL
+    elif case == "tol":
+        expect = P.cpqr.EINVAL
+    else:
+        xs = [P.to_device(p.X.astype(np.float64))[0] for p in probs]
+        kw["prec"] = "fp64"
+        expect = P.cpqr.EUNSUPPORTED
+    with pytest.raises(P.CpqrError) as ei:
+        if case == "tol":
+            # the binding always passes tol = 0; call the ABI with tol != 0
+            _batched_raw_tol(P, xs, dims, ranks, inits)
+        else:
+            P.cp_als_qr_batched(xs, ranks, inits, 3, dims=dims, **kw)
+    assert ei.value.status == expect
+    # the handle stays usable
+    P.cp_als_qr_batched(xs[:1] if case != "fp64" else [P.to_device(probs[0].X)[0]], ranks[:1],
+                        inits[:1], 2, dims=dims[:1])
+
+
+def _batched_raw_tol(P, xs, dims, ranks, inits):
+    import ctypes
+    C = P.cpqr
+    L = C.load_library()
+    count = len(xs)
+    keeps = [C._prepare(xs[t], ranks[t], inits[t], 3, dims[t], "restructured", "off", "fp32",
+                        1e-6, 0.1, 0.03, 0.0, False, False, True)[1] for t in range(count)]
+    tens = (C._Tensor * count)(*[k["ten"] for k in keeps])
+    opts = (C._Options * count)(*[k["opts"] for k in keeps])
+    res = (C._Result * count)()
+    rk = (ctypes.c_int32 * count)(*ranks)
+    h = C.default_handle(0)
+    h.check(L.cpqr_als_qr_batched(h._h, count, tens, rk, opts, res))
