@@ -49,8 +49,25 @@ typedef enum { CPQR_TREE_NONE = 0, CPQR_TREE_STANDARD = 1, CPQR_TREE_RESTRUCTURE
 
 /* Q0 extrapolation (Section 3.2, eq. (19), Algorithm 3).  OFF is beta = 0
  * (ALS-QR-BR); PAPER activates beta once the fit change drops below
- * switch_delta and picks it from the fit level (Section 4.3). */
-typedef enum { CPQR_EXTRAP_OFF = 0, CPQR_EXTRAP_PAPER = 1 } cpqr_extrap;
+ * switch_delta and picks it from the fit level (Section 4.3).  LEARNED (a
+ * feature of this library, not of the paper) takes beta from the MLP in
+ * cpqr_options.mlp_weights after sweep 2 and applies it from sweep 3 through
+ * the same eq. (19) update; every such sweep is accepted only if its fit
+ * exceeds the previous sweep's fit, otherwise the sweep-start state is
+ * restored, beta becomes the paper's table value for the previous fit, and
+ * the sweep is redone (the MLP is not consulted again). */
+typedef enum { CPQR_EXTRAP_OFF = 0, CPQR_EXTRAP_PAPER = 1, CPQR_EXTRAP_LEARNED = 2 } cpqr_extrap;
+
+/* Learned-extrapolation MLP: CPQR_MLP_FEATURES inputs -> CPQR_MLP_HIDDEN tanh
+ * units -> one linear output y, with beta = clamp(10^y - 1e-6, 0, 0.05).
+ * Parameters (float32, CPQR_MLP_PARAMS): W1 (HIDDEN x FEATURES, row-major),
+ * b1 (HIDDEN), w2 (HIDDEN), b2 (1).  Features after sweep 2 (fits f1, f2 of
+ * sweeps 1 and 2, order N, rank R, mode sizes I_n):
+ *   [f1, f2, 10 (f2 - f1), log10(max(1 - f2, 1e-12)) / 4, N / 5, R / 16,
+ *    log2(mean I_n) / 8, R / min I_n]. */
+#define CPQR_MLP_FEATURES 8
+#define CPQR_MLP_HIDDEN 64
+#define CPQR_MLP_PARAMS (CPQR_MLP_HIDDEN * CPQR_MLP_FEATURES + 2 * CPQR_MLP_HIDDEN + 1)
 
 /* Arithmetic of the TTM chain.  FP64 needs a float64 tensor; FP32 and
  * BF16X3 need a float32 tensor.  BF16X3 computes each TTM product as
@@ -100,6 +117,7 @@ typedef struct {
   double fixed_beta;    /* if > 0 with CPQR_EXTRAP_PAPER: use this beta from sweep 2 on instead of the rule */
   const double *const *init_factors; /* host, N pointers to I_n x R column-major float64 initial factors */
   unsigned flags;       /* CPQR_FLAG_* */
+  const float *mlp_weights; /* host, CPQR_MLP_PARAMS floats; required with CPQR_EXTRAP_LEARNED, else ignored */
 } cpqr_options;
 
 typedef struct {
@@ -119,6 +137,8 @@ typedef struct {
   int l1_ttm_launches;     /* number of level-1 TTMs timed */
   double l1_ttm_bytes;     /* algorithmic bytes of one level-1 TTM per launch (averaged) */
   double l1_ttm_flops;     /* flops of one level-1 TTM per launch (averaged) */
+  double beta_learned;     /* CPQR_EXTRAP_LEARNED: the MLP's beta (0 otherwise) */
+  int learned_fallback_sweep; /* CPQR_EXTRAP_LEARNED: sweep whose rejection switched to the paper's beta (0 if none) */
 } cpqr_result;
 
 /*
@@ -176,10 +196,11 @@ cpqr_status cpqr_session_destroy(cpqr_session *session);
  * candidates into scratch outputs.
  * Xs[t], ranks[t], opts[t], results[t]: the arguments of cpqr_als_qr for
  * problem t (same meaning, layout and ownership).  All problems must share
- * order, tree, extrapolate, prec, iters, alpha, switch_delta and fixed_beta;
- * prec must be CPQR_PREC_FP32 or CPQR_PREC_BF16X3; tol must be 0 (every
- * problem runs exactly `iters` sweeps).  Violations: CPQR_EINVAL (mixed
- * settings, tol != 0, count < 1) or CPQR_EUNSUPPORTED (FP64).  Each problem is
+ * order, tree, extrapolate, prec and iters (alpha, switch_delta and
+ * fixed_beta may differ); prec must be CPQR_PREC_FP32 or CPQR_PREC_BF16X3;
+ * tol must be 0 (every problem runs exactly `iters` sweeps); extrapolate
+ * must be OFF or PAPER.  Violations: CPQR_EINVAL (mixed settings, tol != 0,
+ * count < 1) or CPQR_EUNSUPPORTED (FP64, LEARNED).  Each problem is
  * validated as cpqr_check_args; the first failing problem's status is
  * returned and nothing runs.  Runtime errors are reported per problem: the
  * function returns the first non-OK status over t = 0..count-1 after filling
@@ -189,6 +210,25 @@ cpqr_status cpqr_session_destroy(cpqr_session *session);
 cpqr_status cpqr_als_qr_batched(cpqr_handle *handle, int count, const cpqr_tensor *Xs,
                                 const int *ranks, const cpqr_options *opts,
                                 cpqr_result *results);
+
+/*
+ * MLP of the learned extrapolation (a feature of this library, not of the
+ * paper).  Weights, inputs and outputs are host float32 arrays; the
+ * arithmetic runs on the device.  x is n x CPQR_MLP_FEATURES row-major.
+ * cpqr_mlp_forward -- y[i] = output for row i.
+ * cpqr_mlp_grad -- loss = (1/2n) sum_i (y_hat_i - y_i)^2 and its gradient with
+ *   respect to the CPQR_MLP_PARAMS weights (same layout).
+ * cpqr_mlp_train -- `epochs` passes of Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ *   step size lr) over shuffled mini-batches of `batch` rows (seeded order);
+ *   w is updated in place; loss_history (epochs entries, or NULL) receives
+ *   the mean-squared loss over all n rows after each epoch.
+ * Errors: CPQR_EINVAL for null pointers, n < 1, batch < 1, epochs < 0.
+ */
+cpqr_status cpqr_mlp_forward(cpqr_handle *handle, const float *w, const float *x, int n, float *y);
+cpqr_status cpqr_mlp_grad(cpqr_handle *handle, const float *w, const float *x, const float *y, int n,
+                          float *loss, float *grad);
+cpqr_status cpqr_mlp_train(cpqr_handle *handle, float *w, const float *x, const float *y, int n,
+                           int epochs, int batch, float lr, uint64_t seed, float *loss_history);
 
 /*
  * cpqr_check_args -- host-only: the argument checks that cpqr_als_qr makes

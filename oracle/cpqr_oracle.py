@@ -295,15 +295,21 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
               tree: str = "none", extrap: str = "off", alpha: float = 0.1,
               delta: float = 0.03, tol: float = 0.0, fix_beta: Optional[float] = None,
               explicit_every_sweep: bool = False, explicit_final: bool = True,
-              sweep_callback=None) -> Dict:
+              sweep_callback=None, mlp_weights=None) -> Dict:
     """CP-ALS-QR (Algorithm 2) / ALS-QR-BR(E) (Algorithm 3) in FP64 with
     direct multi-TTMs from X.  ``tree`` only selects the update order.
 
-    ``extrap``: "off" (beta = 0) or "paper" (eq. 19 with the activation rule).
+    ``extrap``: "off" (beta = 0), "paper" (eq. 19 with the activation rule)
+    or "learned" (a library feature, not the paper's: after sweep 2 beta is
+    the MLP output for the fits of sweeps 1-2 (``mlp_weights``, see
+    mlp_oracle); every later sweep is kept only if its fit exceeds the
+    previous one, otherwise the sweep-start state is restored, beta becomes
+    the paper's table value for the previous fit and the sweep is redone).
     ``fix_beta`` (test hook): apply this beta from sweep 2 onward instead of
     the rule.  ``sweep_callback(k, fit)`` (instrumentation hook) is called
     after each sweep; ``explicit_final=False`` skips the final explicit fit.
     """
+    import copy
     X = np.asarray(X, F64)
     N = X.ndim
     R = int(rank)
@@ -317,29 +323,50 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
     lam = np.ones(R)
     Q0prev: List[Optional[np.ndarray]] = [None] * N
     beta, active, beta_sweep = 0.0, False, 0
+    learned = extrap == "learned"
+    learned_on, fallback, fallback_sweep, beta_learned = False, False, 0, 0.0
     fits: List[float] = []
     fitxs: List[float] = []
     orders: List[List[int]] = []
     Vp = Vu = None
+
+    def sweep(order, b):
+        nonlocal lam, Vp, Vu
+        for n in order:
+            Yn = unfold(multi_ttm_except(X, Qs, n), n)
+            A[n], lam, Q0, R0, Vp, Vu = mode_update(Yn, Rfs, n, Q0prev[n], b, alpha)
+            Q0prev[n] = Q0
+            Qs[n], Rfs[n] = householder_qr(A[n])
+        return cheap_fit(nx2, Vp, Vu)
+
     for k in range(1, iters + 1):
         order = sweep_order(N, tree, k)
         orders.append(order)
         if fix_beta is not None:
             b = fix_beta if k >= 2 else 0.0
         else:
-            b = beta if (extrap == "paper" and active) else 0.0
-        for n in order:
-            Yn = unfold(multi_ttm_except(X, Qs, n), n)
-            A[n], lam, Q0, R0, Vp, Vu = mode_update(Yn, Rfs, n, Q0prev[n], b, alpha)
-            Q0prev[n] = Q0
-            Qs[n], Rfs[n] = householder_qr(A[n])
-        fit = cheap_fit(nx2, Vp, Vu)
+            b = beta if (extrap in ("paper", "learned") and active) else 0.0
+        if learned and learned_on and not fallback:
+            saved = copy.deepcopy((A, Qs, Rfs, lam, Q0prev))
+            fit = sweep(order, b)
+            if not fit > fits[-1]:
+                A, Qs, Rfs, lam, Q0prev = saved
+                beta, beta_sweep = beta_from_fit(fits[-1]), k - 1
+                fallback, fallback_sweep = True, k
+                fit = sweep(order, beta)
+        else:
+            fit = sweep(order, b)
         fits.append(fit)
         if explicit_every_sweep:
             fitxs.append(explicit_fit(X, lam, A))
         if extrap == "paper" and fix_beta is None and not active and k >= 2 \
                 and abs(fit - fits[-2]) < delta:
             beta, active, beta_sweep = beta_from_fit(fit), True, k
+        if learned and k == 2 and not learned_on:
+            from . import mlp_oracle as M
+            x = M.features(fits[0], fits[1], N, R, X.shape)
+            beta = M.beta_from_output(M.forward(mlp_weights, x)[0])
+            beta_learned, active, beta_sweep, learned_on = beta, True, 2, True
         if sweep_callback is not None:
             sweep_callback(k, fit)
         if tol > 0.0 and k >= 2 and abs(fit - fits[-2]) < tol:
@@ -350,6 +377,7 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
         "fitxs": np.array(fitxs),
         "orders": orders, "beta": beta if fix_beta is None else fix_beta,
         "beta_sweep": beta_sweep, "sweeps": len(fits), "nx2": nx2,
+        "beta_learned": beta_learned, "fallback_sweep": fallback_sweep,
     }
 
 

@@ -5,4 +5,5 @@ The compute path is libcpqr.so (hand-written HIP kernels behind a C ABI,
 ``include/cpqr.h``); :mod:`paper_2503_18759_amd.cpqr` is its ctypes binding.
 """
 from .cpqr import (CpqrError, Handle, Session, check_args, cp_als_qr,  # noqa: F401
-                   cp_als_qr_batched, default_handle, load_library, qr, schedule, to_device, ttm)
+                   cp_als_qr_batched, default_handle, load_library, mlp_forward, mlp_grad,
+                   mlp_train, qr, schedule, to_device, ttm)

@@ -23,7 +23,9 @@ LIB_PATH = os.path.join(_HERE, "libcpqr.so")
 # status codes (include/cpqr.h)
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ERANKDEF, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 TREES = {"none": 0, "standard": 1, "restructured": 2}
-EXTRAP = {"off": 0, "paper": 1}
+EXTRAP = {"off": 0, "paper": 1, "learned": 2}
+MLP_FEATURES, MLP_HIDDEN = 8, 64
+MLP_PARAMS = MLP_HIDDEN * MLP_FEATURES + 2 * MLP_HIDDEN + 1
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 FLAG_EXPLICIT_FIT, FLAG_TIME_KERNELS, FLAG_NO_GRAPH = 0x1, 0x2, 0x4
 
@@ -44,7 +46,7 @@ class _Options(ctypes.Structure):
                 ("iters", ctypes.c_int), ("tol", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("switch_delta", ctypes.c_double), ("fixed_beta", ctypes.c_double),
                 ("init_factors", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
-                ("flags", ctypes.c_uint)]
+                ("flags", ctypes.c_uint), ("mlp_weights", ctypes.POINTER(ctypes.c_float))]
 
 
 class _Result(ctypes.Structure):
@@ -57,13 +59,15 @@ class _Result(ctypes.Structure):
                 ("beta_sweep", ctypes.c_int), ("ttm_flops", ctypes.c_double),
                 ("ttm_bytes", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("l1_ttm_seconds", ctypes.c_double), ("l1_ttm_launches", ctypes.c_int),
-                ("l1_ttm_bytes", ctypes.c_double), ("l1_ttm_flops", ctypes.c_double)]
+                ("l1_ttm_bytes", ctypes.c_double), ("l1_ttm_flops", ctypes.c_double),
+                ("beta_learned", ctypes.c_double), ("learned_fallback_sweep", ctypes.c_int)]
 
 
 EXPORTS = ["cpqr_create", "cpqr_destroy", "cpqr_last_error", "cpqr_status_string",
            "cpqr_check_args", "cpqr_als_qr", "cpqr_session_create", "cpqr_session_sweeps",
            "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy",
-           "cpqr_schedule", "cpqr_ttm", "cpqr_qr", "cpqr_als_qr_batched"]
+           "cpqr_schedule", "cpqr_ttm", "cpqr_qr", "cpqr_als_qr_batched",
+           "cpqr_mlp_forward", "cpqr_mlp_grad", "cpqr_mlp_train"]
 
 _lib = None
 
@@ -99,6 +103,9 @@ def load_library(path: str = LIB_PATH):
     L.cpqr_qr.argtypes = [vp, i64, i32, vp, vp, vp]
     L.cpqr_als_qr_batched.argtypes = [vp, i32, ctypes.POINTER(_Tensor), ctypes.POINTER(i32),
                                       ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
+    L.cpqr_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
+    L.cpqr_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+    L.cpqr_mlp_train.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
     for f in ("cpqr_create", "cpqr_destroy", "cpqr_check_args", "cpqr_als_qr", "cpqr_schedule",
               "cpqr_ttm", "cpqr_qr", "cpqr_session_create", "cpqr_session_sweeps",
               "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy"):
@@ -198,7 +205,7 @@ def to_device(X: np.ndarray, dtype=None, device: int = 0):
 
 
 def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, switch_delta,
-             fixed_beta, explicit_fit, time_kernels, use_graph):
+             fixed_beta, explicit_fit, time_kernels, use_graph, mlp_weights=None):
     dims, dt, ptr = _dims_and_ptr(x, dims)
     N = len(dims)
     inits = [np.asfortranarray(np.asarray(a, dtype=np.float64)) for a in init]
@@ -213,9 +220,16 @@ def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, sw
         *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in inits])
     flags = (FLAG_EXPLICIT_FIT if explicit_fit else 0) | (FLAG_TIME_KERNELS if time_kernels else 0) \
         | (0 if use_graph else FLAG_NO_GRAPH)
+    wptr = None
+    if mlp_weights is not None:
+        w = np.ascontiguousarray(np.asarray(mlp_weights, dtype=np.float32).reshape(-1))
+        if w.size != MLP_PARAMS:
+            raise ValueError(f"mlp_weights must hold {MLP_PARAMS} floats")
+        keep["mlp_w"] = w
+        wptr = w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
     keep["opts"] = _Options(TREES[tree], EXTRAP[extrapolate], PRECS[prec], int(iters), float(tol),
                             float(alpha), float(switch_delta), float(fixed_beta),
-                            keep["init_ptrs"], flags)
+                            keep["init_ptrs"], flags, wptr)
     return dims, keep
 
 
@@ -244,6 +258,7 @@ def _result_dict(res, bufs):
         "ttm_flops": res.ttm_flops, "ttm_bytes": res.ttm_bytes,
         "l1_ttm_seconds": res.l1_ttm_seconds, "l1_ttm_launches": res.l1_ttm_launches,
         "l1_ttm_bytes": res.l1_ttm_bytes, "l1_ttm_flops": res.l1_ttm_flops,
+        "beta_learned": res.beta_learned, "learned_fallback_sweep": res.learned_fallback_sweep,
     }
 
 
@@ -252,7 +267,7 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
               extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
               alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
               explicit_fit: bool = False, time_kernels: bool = False, use_graph: bool = True,
-              handle: Optional[Handle] = None) -> Dict:
+              mlp_weights=None, handle: Optional[Handle] = None) -> Dict:
     """CP-ALS-QR / ALS-QR-BR(E) on the GPU (Algorithms 2 and 3).
 
     Returns a dict with factors (list of I_n x R float64 arrays), lam, fits
@@ -261,7 +276,8 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
     """
     L = load_library()
     dims, keep = _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha,
-                          switch_delta, fixed_beta, explicit_fit, time_kernels, use_graph)
+                          switch_delta, fixed_beta, explicit_fit, time_kernels, use_graph,
+                          mlp_weights)
     h = handle or default_handle(x.device.index or 0)
     res, bufs = _result_buffers(dims, rank, iters)
     st = L.cpqr_als_qr(h._h, ctypes.byref(keep["ten"]), int(rank), ctypes.byref(keep["opts"]),
@@ -312,14 +328,14 @@ class Session:
                  extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
                  alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
                  explicit_fit: bool = False, time_kernels: bool = False,
-                 use_graph: bool = True, handle: Optional[Handle] = None):
+                 use_graph: bool = True, mlp_weights=None, handle: Optional[Handle] = None):
         L = load_library()
         self._x = x
         self.rank = rank
         self.max_sweeps = max_sweeps
         self.dims, self._keep = _prepare(x, rank, init, max_sweeps, dims, tree, extrapolate, prec,
                                          tol, alpha, switch_delta, fixed_beta, explicit_fit,
-                                         time_kernels, use_graph)
+                                         time_kernels, use_graph, mlp_weights)
         self.h = handle or default_handle(x.device.index or 0)
         self._s = ctypes.c_void_p()
         self.h.check(L.cpqr_session_create(self.h._h, ctypes.byref(self._keep["ten"]), int(rank),
@@ -358,7 +374,7 @@ def check_args(dims: Sequence[int], rank: int, *, dtype: str = "f32", iters: int
                tree: str = "restructured", extrapolate: str = "off", prec: str = "fp32",
                tol: float = 0.0, alpha: float = 0.1, switch_delta: float = 0.03,
                fixed_beta: float = 0.0, init: Optional[Sequence[np.ndarray]] = None,
-               data_ptr: int = 1, raw: Optional[dict] = None) -> int:
+               data_ptr: int = 1, mlp_weights=None, raw: Optional[dict] = None) -> int:
     """Host-only argument checks of cpqr_als_qr (no device needed); returns
     the status code.  ``raw`` overrides fields with raw integers/None to
     exercise invalid inputs."""
@@ -376,10 +392,15 @@ def check_args(dims: Sequence[int], rank: int, *, dtype: str = "f32", iters: int
         *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in keep])
     if raw.get("null_init_k") is not None:
         ptrs[raw["null_init_k"]] = ctypes.POINTER(ctypes.c_double)()
+    wbuf = None
+    if mlp_weights is not None:
+        wbuf = np.zeros(MLP_PARAMS, dtype=np.float32) if mlp_weights is True else \
+            np.ascontiguousarray(np.asarray(mlp_weights, dtype=np.float32).reshape(-1))
     opts = _Options(raw.get("tree", TREES.get(tree, 9)), raw.get("extrapolate", EXTRAP.get(extrapolate, 9)),
                     raw.get("prec", PRECS.get(prec, 9)), int(iters), float(tol), float(alpha),
                     float(switch_delta), float(fixed_beta),
-                    None if raw.get("null_init") else ptrs, 0)
+                    None if raw.get("null_init") else ptrs, 0,
+                    None if wbuf is None else wbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     return int(L.cpqr_check_args(ctypes.byref(ten), int(rank), ctypes.byref(opts)))
 
 
@@ -445,3 +466,50 @@ def schedule(order: int, tree: str, sweeps: int) -> Tuple[List[List[int]], List[
             modes = tuple(k for k in range(order) if mask >> k & 1)
             poly[(modes, order - len(modes) + 1)] = int(c)
     return ords, stp, poly
+
+
+# ------------------------------------------------------------------ MLP
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def mlp_forward(w, x, handle: Optional[Handle] = None) -> np.ndarray:
+    """Learned-extrapolation MLP outputs for the rows of x (n x 8), on the GPU."""
+    L = load_library()
+    w = _f32(w, (MLP_PARAMS,))
+    x = _f32(x, (-1, MLP_FEATURES))
+    y = np.zeros(x.shape[0], dtype=np.float32)
+    h = handle or default_handle(0)
+    h.check(L.cpqr_mlp_forward(h._h, w.ctypes.data, x.ctypes.data, x.shape[0], y.ctypes.data))
+    return y
+
+
+def mlp_grad(w, x, y, handle: Optional[Handle] = None) -> Tuple[float, np.ndarray]:
+    """(loss, gradient) of the mean-squared error (1/2n) sum (yhat - y)^2, on the GPU."""
+    L = load_library()
+    w = _f32(w, (MLP_PARAMS,))
+    x = _f32(x, (-1, MLP_FEATURES))
+    y = _f32(y, (x.shape[0],))
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    loss = np.zeros(1, dtype=np.float32)
+    h = handle or default_handle(0)
+    h.check(L.cpqr_mlp_grad(h._h, w.ctypes.data, x.ctypes.data, y.ctypes.data, x.shape[0],
+                            loss.ctypes.data, g.ctypes.data))
+    return float(loss[0]), g
+
+
+def mlp_train(w, x, y, *, epochs: int, batch: int = 64, lr: float = 1e-3, seed: int = 0,
+              handle: Optional[Handle] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Adam training on the GPU; returns (weights, loss after each epoch)."""
+    L = load_library()
+    w = _f32(w, (MLP_PARAMS,)).copy()
+    x = _f32(x, (-1, MLP_FEATURES))
+    y = _f32(y, (x.shape[0],))
+    hist = np.zeros(max(epochs, 1), dtype=np.float32)
+    h = handle or default_handle(0)
+    h.check(L.cpqr_mlp_train(h._h, w.ctypes.data, x.ctypes.data, y.ctypes.data, x.shape[0],
+                             int(epochs), int(batch), float(lr), int(seed), hist.ctypes.data))
+    return w, hist[:epochs]

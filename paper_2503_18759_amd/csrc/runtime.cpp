@@ -9,6 +9,7 @@
 // and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -20,6 +21,7 @@
 
 #include "../../include/cpqr.h"
 #include "kernels.h"
+#include "mlp.h"
 #include "schedule.h"
 
 using namespace cpqr;
@@ -135,6 +137,10 @@ struct Problem {
   double* fit_hist = nullptr;
   double* norm_part = nullptr;
   std::map<uint32_t, void*> inter;   // intermediates by free-mode mask
+  // buffers that carry state from one sweep to the next (restored when a
+  // learned-beta sweep is rejected), with their shadow copies
+  std::vector<std::pair<void*, size_t>> carried;
+  std::vector<void*> shadow;
 };
 
 int64_t inter_elems(const Problem& p, uint32_t mask) {
@@ -160,6 +166,13 @@ struct cpqr_session {
   bool t0_recorded = false;
   std::vector<hipEvent_t> evs;
   std::map<std::string, hipGraphExec_t> graphs;
+  // learned extrapolation
+  float* mlp_w = nullptr;        // device weights
+  float* mlp_io = nullptr;       // device features (CPQR_MLP_FEATURES) + output (1)
+  bool learned_on = false;       // beta from the MLP in force
+  bool fallback = false;         // a learned sweep was rejected: paper beta from then on
+  double beta_learned = 0.0;
+  int fallback_sweep = 0;
   ~cpqr_session() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
@@ -204,6 +217,15 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   WS(h, p.prefix + "partial", (size_t)nch * 2 * p.Imax * R * 8, p.partial);
   WS(h, p.prefix + "V", (size_t)2 * p.Imax * R * 8, p.Vbuf);
   WS(h, p.prefix + "state", sizeof(DevState), p.state);
+  p.carried.clear();
+  for (int k = 0; k < N; ++k) {
+    p.carried.push_back({p.A[k], (size_t)p.dims[k] * R * 8});
+    p.carried.push_back({p.Q[k], (size_t)p.dims[k] * R * p.elem});
+    p.carried.push_back({p.q0buf[k], (size_t)2 * p.M * R * 8});
+  }
+  p.carried.push_back({p.rf, (size_t)N * R * R * 8});
+  p.carried.push_back({p.lambda, (size_t)R * 8});
+  p.carried.push_back({p.state, sizeof(DevState)});
   WS(h, p.prefix + "fit_hist", (size_t)(iters > 0 ? iters : 1) * 8, p.fit_hist);
   WS(h, p.prefix + "norm_part", 4096 * 8, p.norm_part);
   // intermediates used by the schedule
@@ -216,6 +238,7 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
           void* ptr = nullptr;
           WS(h, p.prefix + "Y" + std::to_string(dst), (size_t)inter_elems(p, dst) * p.elem, ptr);
           p.inter[dst] = ptr;
+          p.carried.push_back({ptr, (size_t)inter_elems(p, dst) * p.elem});
         }
       }
   (void)full;
@@ -275,7 +298,7 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   a->S = ipow(R, p.N - 1 - n);
   a->R = R;
   a->Q0 = q0cur;
-  a->Q0prev = (o->extrapolate == CPQR_EXTRAP_PAPER) ? q0prev : nullptr;
+  a->Q0prev = (o->extrapolate != CPQR_EXTRAP_OFF) ? q0prev : nullptr;
   a->partial = p.partial;
   a->V = p.Vbuf;
   a->nchunks = apply_num_chunks(p.M, a->I);
@@ -294,7 +317,8 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   f->alpha = o->alpha;
   f->delta = o->switch_delta;
   f->fixed_beta = o->fixed_beta;
-  f->extrap = o->extrapolate;
+  // the learned mode drives the same device-side beta state as the paper's rule
+  f->extrap = (o->extrapolate != CPQR_EXTRAP_OFF) ? 1 : 0;
   f->last_in_sweep = last ? 1 : 0;
 }
 
@@ -329,7 +353,9 @@ cpqr_status check_args(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpq
   if (o->iters < 1) return fail(h, CPQR_EINVAL, "iters must be >= 1");
   if (o->tree < 0 || o->tree > 2) return fail(h, CPQR_EINVAL, "bad tree");
   if (N == 2 && o->tree != CPQR_TREE_NONE) return fail(h, CPQR_EINVAL, "order 2 needs tree=none");
-  if (o->extrapolate < 0 || o->extrapolate > 1) return fail(h, CPQR_EINVAL, "bad extrapolation mode");
+  if (o->extrapolate < 0 || o->extrapolate > 2) return fail(h, CPQR_EINVAL, "bad extrapolation mode");
+  if (o->extrapolate == CPQR_EXTRAP_LEARNED && !o->mlp_weights)
+    return fail(h, CPQR_EINVAL, "learned extrapolation needs mlp_weights");
   if (o->prec < 0 || o->prec > 2) return fail(h, CPQR_EINVAL, "bad precision");
   if (X->dtype != CPQR_DTYPE_F32 && X->dtype != CPQR_DTYPE_F64) return fail(h, CPQR_EINVAL, "bad dtype");
   if ((o->prec == CPQR_PREC_FP64) != (X->dtype == CPQR_DTYPE_F64))
@@ -540,6 +566,7 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   S.h = h;
   S.opts = *o;
   S.opts.init_factors = nullptr;
+  S.opts.mlp_weights = nullptr;
   if (!build_schedule(N, o->tree, o->iters, S.sched) || !validate_schedule(N, S.sched))
     return fail(h, CPQR_EINVAL, "schedule construction failed");
   HIP_TRY(h, hipSetDevice(h->device));
@@ -576,6 +603,11 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
     return fail(h, CPQR_EINVAL, "||X|| = 0");
   }
   S.nx2 = hs.nx2;
+  if (o->extrapolate == CPQR_EXTRAP_LEARNED) {
+    WS(h, prefix + "mlp_w", CPQR_MLP_PARAMS * sizeof(float), S.mlp_w);
+    WS(h, prefix + "mlp_io", (CPQR_MLP_FEATURES + 1) * sizeof(float), S.mlp_io);
+    HIP_TRY(h, hipMemcpy(S.mlp_w, o->mlp_weights, CPQR_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+  }
   HIP_TRY(h, hipEventCreate(&S.t0));
   HIP_TRY(h, hipEventCreate(&S.t1));
   *out = ss.release();
@@ -598,6 +630,183 @@ cpqr_status cpqr_session_create(cpqr_handle* h, const cpqr_tensor* X, int rank,
   return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Enqueues sweep k (graph replay, or kernel by kernel) and counts its TTM work.
+cpqr_status run_sweep(cpqr_session* S, int k) {
+  cpqr_handle* h = S->h;
+  hipStream_t s = h->stream;
+  const cpqr_options* o = &S->opts;
+  Problem& p = S->p;
+  const int N = p.N;
+  const bool timing = (o->flags & CPQR_FLAG_TIME_KERNELS) != 0;
+  const bool use_graph = !timing && !(o->flags & CPQR_FLAG_NO_GRAPH);
+  const uint32_t full = (1u << N) - 1u;
+  const auto& sw = S->sched[k - 1];
+  for (const Step& st : sw)
+    if (st.kind == STEP_TTM) {
+      const int64_t in = inter_elems(p, st.src);
+      const int64_t outn = in / p.dims[st.mode] * p.R;
+      S->ttm_flops += 2.0 * in * p.R;
+      S->ttm_bytes += (double)(in + outn) * p.elem;
+      if (st.src == full) {
+        S->l1_bytes += (double)(in + outn) * p.elem;
+        S->l1_flops += 2.0 * in * p.R;
+        ++S->l1_count;
+      }
+    }
+  int last_update = -1;
+  for (size_t i = 0; i < sw.size(); ++i)
+    if (sw[i].kind == STEP_UPDATE) last_update = (int)i;
+  auto enqueue = [&](hipStream_t q) -> hipError_t {
+    for (size_t i = 0; i < sw.size(); ++i) {
+      const Step& st = sw[i];
+      hipError_t e;
+      if (st.kind == STEP_TTM) {
+        if (timing && st.src == full) {
+          // The level-1 TTM is idempotent (it rewrites its output from X and
+          // Q_m), so it is timed as a graph of kTimeReps back-to-back
+          // launches between two events: the per-launch average then holds
+          // no event or launch overhead.
+          const std::string gk = "l1rep:" + std::to_string(st.src) + ":" + std::to_string(st.mode);
+          auto itr = S->graphs.find(gk);
+          if (itr == S->graphs.end()) {
+            hipGraph_t g;
+            if ((e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+            hipError_t el = hipSuccess;
+            for (int r = 0; r < kTimeReps && el == hipSuccess; ++r) el = launch_ttm_step(p, st, q);
+            if ((e = hipStreamEndCapture(q, &g)) != hipSuccess) return e;
+            if (el != hipSuccess) return el;
+            hipGraphExec_t ge;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+            itr = S->graphs.emplace(gk, ge).first;
+          }
+          hipEvent_t a, b;
+          if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+          if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+          S->evs.push_back(a);
+          S->evs.push_back(b);
+          if ((e = hipEventRecord(a, q)) != hipSuccess) return e;
+          if ((e = hipGraphLaunch(itr->second, q)) != hipSuccess) return e;
+          if ((e = hipEventRecord(b, q)) != hipSuccess) return e;
+        } else {
+          if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
+        }
+      } else {
+        if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q)) != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  };
+  if (use_graph) {
+    // sweeps with the same step list and Q0 ping-pong parity share a graph
+    const std::string key = sweep_key(sw, k == 1 ? 2 : (k % 2), o->extrapolate != 0);
+    auto itg = S->graphs.find(key);
+    if (itg == S->graphs.end()) {
+      hipGraph_t g;
+      HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      hipError_t e = enqueue(s);
+      hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess) return fail(h, CPQR_EHIP, "kernel launch during capture failed: %s", hipGetErrorString(e));
+      if (e2 != hipSuccess) return fail(h, CPQR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+      hipGraphExec_t ge;
+      hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e3 != hipSuccess) return fail(h, CPQR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+      itg = S->graphs.emplace(key, ge).first;
+    }
+    HIP_TRY(h, hipGraphLaunch(itg->second, s));
+  } else {
+    hipError_t e = enqueue(s);
+    if (e != hipSuccess) return fail(h, CPQR_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  }
+  return CPQR_OK;
+}
+
+// Copies every buffer that carries state between sweeps into (to_shadow) or
+// back from its shadow copy.
+cpqr_status copy_carried(cpqr_session* S, bool to_shadow) {
+  cpqr_handle* h = S->h;
+  Problem& p = S->p;
+  if (p.shadow.size() != p.carried.size()) {
+    p.shadow.resize(p.carried.size());
+    for (size_t i = 0; i < p.carried.size(); ++i)
+      WS(h, p.prefix + "shadow" + std::to_string(i), p.carried[i].second, p.shadow[i]);
+  }
+  for (size_t i = 0; i < p.carried.size(); ++i) {
+    void* live = p.carried[i].first;
+    if (to_shadow)
+      HIP_TRY(h, hipMemcpyAsync(p.shadow[i], live, p.carried[i].second, hipMemcpyDeviceToDevice, h->stream));
+    else
+      HIP_TRY(h, hipMemcpyAsync(live, p.shadow[i], p.carried[i].second, hipMemcpyDeviceToDevice, h->stream));
+  }
+  return CPQR_OK;
+}
+
+// Fits of sweeps k-1 and k (1-based k >= 2).
+cpqr_status read_fits(cpqr_session* S, int k, double* f) {
+  cpqr_handle* h = S->h;
+  HIP_TRY(h, hipMemcpyAsync(f, S->p.fit_hist + (k - 2), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return CPQR_OK;
+}
+
+cpqr_status set_beta(cpqr_session* S, double beta, int beta_sweep) {
+  cpqr_handle* h = S->h;
+  DevState hs;
+  HIP_TRY(h, hipMemcpyAsync(&hs, S->p.state, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  hs.active = 1;
+  hs.beta = beta;
+  hs.beta_sweep = beta_sweep;
+  HIP_TRY(h, hipMemcpyAsync(S->p.state, &hs, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return CPQR_OK;
+}
+
+// The paper's beta table (Section 4.3), used for the fallback of a rejected
+// learned sweep.
+double paper_beta(double fit) {
+  if (fit > 0.95) return 1.0 / 20000.0;
+  if (fit > 0.90) return 1.0 / 2000.0;
+  if (fit > 0.70) return 1.0 / 500.0;
+  return 1.0 / 250.0;
+}
+
+// Learned beta after sweep 2 from the fits of sweeps 1 and 2 (features as in
+// cpqr.h), evaluated by the MLP kernel.
+cpqr_status learned_beta(cpqr_session* S, double f1, double f2, double* beta) {
+  cpqr_handle* h = S->h;
+  const Problem& p = S->p;
+  double sumI = 0.0, minI = 1e300;
+  for (int64_t d : p.dims) {
+    sumI += (double)d;
+    minI = std::min(minI, (double)d);
+  }
+  float x[CPQR_MLP_FEATURES] = {
+      (float)f1, (float)f2, (float)(10.0 * (f2 - f1)),
+      (float)(std::log10(std::max(1.0 - f2, 1e-12)) / 4.0), (float)(p.N / 5.0), (float)(p.R / 16.0),
+      (float)(std::log2(sumI / p.N) / 8.0), (float)(p.R / minI)};
+  HIP_TRY(h, hipMemcpyAsync(S->mlp_io, x, sizeof(x), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, launch_mlp_forward(S->mlp_w, S->mlp_io, 1, S->mlp_io + CPQR_MLP_FEATURES, h->stream));
+  float y = 0.f;
+  HIP_TRY(h, hipMemcpyAsync(&y, S->mlp_io + CPQR_MLP_FEATURES, sizeof(float), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  double b = std::pow(10.0, (double)y) - 1e-6;
+  if (!(b > 0.0)) b = 0.0;
+  if (b > 0.05) b = 0.05;
+  *beta = b;
+  return CPQR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
   if (!S) return CPQR_EINVAL;
   cpqr_handle* h = S->h;
@@ -611,97 +820,39 @@ cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
   hipStream_t s = h->stream;
   const cpqr_options* o = &S->opts;
   Problem& p = S->p;
-  const int N = p.N;
-  const bool timing = (o->flags & CPQR_FLAG_TIME_KERNELS) != 0;
-  const bool use_graph = !timing && !(o->flags & CPQR_FLAG_NO_GRAPH);
-  const uint32_t full = (1u << N) - 1u;
+  const bool learned = o->extrapolate == CPQR_EXTRAP_LEARNED;
   if (!S->t0_recorded) {
     HIP_TRY(h, hipEventRecord(S->t0, s));
     S->t0_recorded = true;
   }
   for (int it = 0; it < nsweeps; ++it) {
     const int k = S->k + 1;
-    const auto& sw = S->sched[k - 1];
-    for (const Step& st : sw)
-      if (st.kind == STEP_TTM) {
-        const int64_t in = inter_elems(p, st.src);
-        const int64_t outn = in / p.dims[st.mode] * p.R;
-        S->ttm_flops += 2.0 * in * p.R;
-        S->ttm_bytes += (double)(in + outn) * p.elem;
-        if (st.src == full) {
-          S->l1_bytes += (double)(in + outn) * p.elem;
-          S->l1_flops += 2.0 * in * p.R;
-          ++S->l1_count;
-        }
+    cpqr_status st;
+    if (learned && S->learned_on && !S->fallback) {
+      // acceptance test: keep the sweep only if the fit improves
+      if ((st = copy_carried(S, true)) != CPQR_OK) return st;
+      if ((st = run_sweep(S, k)) != CPQR_OK) return st;
+      double f[2];
+      if ((st = read_fits(S, k, f)) != CPQR_OK) return st;
+      if (!(f[1] > f[0])) {
+        if ((st = copy_carried(S, false)) != CPQR_OK) return st;
+        if ((st = set_beta(S, paper_beta(f[0]), k - 1)) != CPQR_OK) return st;
+        S->fallback = true;
+        S->fallback_sweep = k;
+        if ((st = run_sweep(S, k)) != CPQR_OK) return st;
       }
-    int last_update = -1;
-    for (size_t i = 0; i < sw.size(); ++i)
-      if (sw[i].kind == STEP_UPDATE) last_update = (int)i;
-    auto enqueue = [&](hipStream_t q) -> hipError_t {
-      for (size_t i = 0; i < sw.size(); ++i) {
-        const Step& st = sw[i];
-        hipError_t e;
-        if (st.kind == STEP_TTM) {
-          if (timing && st.src == full) {
-            // The level-1 TTM is idempotent (it rewrites its output from X and
-            // Q_m), so it is timed as a graph of kTimeReps back-to-back
-            // launches between two events: the per-launch average then holds
-            // no event or launch overhead.
-            const std::string gk = "l1rep:" + std::to_string(st.src) + ":" + std::to_string(st.mode);
-            auto itr = S->graphs.find(gk);
-            if (itr == S->graphs.end()) {
-              hipGraph_t g;
-              if ((e = hipStreamBeginCapture(q, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
-              hipError_t el = hipSuccess;
-              for (int r = 0; r < kTimeReps && el == hipSuccess; ++r) el = launch_ttm_step(p, st, q);
-              if ((e = hipStreamEndCapture(q, &g)) != hipSuccess) return e;
-              if (el != hipSuccess) return el;
-              hipGraphExec_t ge;
-              e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-              (void)hipGraphDestroy(g);
-              if (e != hipSuccess) return e;
-              itr = S->graphs.emplace(gk, ge).first;
-            }
-            hipEvent_t a, b;
-            if ((e = hipEventCreate(&a)) != hipSuccess) return e;
-            if ((e = hipEventCreate(&b)) != hipSuccess) return e;
-            S->evs.push_back(a);
-            S->evs.push_back(b);
-            if ((e = hipEventRecord(a, q)) != hipSuccess) return e;
-            if ((e = hipGraphLaunch(itr->second, q)) != hipSuccess) return e;
-            if ((e = hipEventRecord(b, q)) != hipSuccess) return e;
-          } else {
-            if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
-          }
-        } else {
-          if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q)) != hipSuccess) return e;
-        }
-      }
-      return hipSuccess;
-    };
-    if (use_graph) {
-      // sweeps with the same step list and Q0 ping-pong parity share a graph
-      const std::string key = sweep_key(sw, k == 1 ? 2 : (k % 2), o->extrapolate != 0);
-      auto itg = S->graphs.find(key);
-      if (itg == S->graphs.end()) {
-        hipGraph_t g;
-        HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue(s);
-        hipError_t e2 = hipStreamEndCapture(s, &g);
-        if (e != hipSuccess) return fail(h, CPQR_EHIP, "kernel launch during capture failed: %s", hipGetErrorString(e));
-        if (e2 != hipSuccess) return fail(h, CPQR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
-        hipGraphExec_t ge;
-        hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e3 != hipSuccess) return fail(h, CPQR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
-        itg = S->graphs.emplace(key, ge).first;
-      }
-      HIP_TRY(h, hipGraphLaunch(itg->second, s));
     } else {
-      hipError_t e = enqueue(s);
-      if (e != hipSuccess) return fail(h, CPQR_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+      if ((st = run_sweep(S, k)) != CPQR_OK) return st;
     }
     S->k = k;
+    if (learned && k == 2 && !S->learned_on) {
+      double f[2], b = 0.0;
+      if ((st = read_fits(S, 2, f)) != CPQR_OK) return st;
+      if ((st = learned_beta(S, f[0], f[1], &b)) != CPQR_OK) return st;
+      if ((st = set_beta(S, b, 2)) != CPQR_OK) return st;
+      S->beta_learned = b;
+      S->learned_on = true;
+    }
     if (o->tol > 0.0 && k >= 2) {
       DevState hs;
       HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -775,6 +926,8 @@ cpqr_status cpqr_session_result(cpqr_session* S, cpqr_result* res) {
   res->l1_ttm_launches = timing ? (int)(S->evs.size() / 2) : 0;
   res->l1_ttm_bytes = S->l1_count ? S->l1_bytes / S->l1_count : 0.0;
   res->l1_ttm_flops = S->l1_count ? S->l1_flops / S->l1_count : 0.0;
+  res->beta_learned = S->beta_learned;
+  res->learned_fallback_sweep = S->fallback_sweep;
   res->fit_explicit = std::nan("");
   if (S->opts.flags & CPQR_FLAG_EXPLICIT_FIT) {
     std::vector<double*> fac(p.A.begin(), p.A.end());
@@ -1117,12 +1270,13 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
     }
     const cpqr_options& o = opts[t];
     if (Xs[t].order != Xs[0].order || o.tree != o0.tree || o.extrapolate != o0.extrapolate ||
-        o.prec != o0.prec || o.iters != o0.iters || o.alpha != o0.alpha ||
-        o.switch_delta != o0.switch_delta || o.fixed_beta != o0.fixed_beta)
+        o.prec != o0.prec || o.iters != o0.iters)
       return fail(h, CPQR_EINVAL, "batched problem %d: order and options must match problem 0", t);
     if (o.tol != 0.0) return fail(h, CPQR_EINVAL, "batched runs a fixed number of sweeps: tol must be 0");
   }
   if (o0.prec == CPQR_PREC_FP64) return fail(h, CPQR_EUNSUPPORTED, "batched: FP32 or BF16X3 TTMs only");
+  if (o0.extrapolate == CPQR_EXTRAP_LEARNED)
+    return fail(h, CPQR_EUNSUPPORTED, "batched: learned extrapolation is not supported");
   HIP_TRY(h, hipSetDevice(h->device));
   HIP_TRY(h, order_after_user(h));
   hipStream_t s = h->stream;
@@ -1190,6 +1344,117 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
   }
   h->err = first_msg;
   return first;
+}
+
+// ---------------------------------------------------------------------- MLP
+cpqr_status cpqr_mlp_forward(cpqr_handle* h, const float* w, const float* x, int n, float* y) {
+  if (!h) return CPQR_EINVAL;
+  h->err.clear();
+  if (!w || !x || !y || n < 1) return fail(h, CPQR_EINVAL, "mlp_forward: null pointer or n < 1");
+  HIP_TRY(h, hipSetDevice(h->device));
+  HIP_TRY(h, order_after_user(h));
+  hipStream_t s = h->stream;
+  float *dw, *dx, *dy;
+  WS(h, "mlp:w", CPQR_MLP_PARAMS * sizeof(float), dw);
+  WS(h, "mlp:x", (size_t)n * CPQR_MLP_FEATURES * sizeof(float), dx);
+  WS(h, "mlp:y", (size_t)n * sizeof(float), dy);
+  HIP_TRY(h, hipMemcpyAsync(dw, w, CPQR_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, hipMemcpyAsync(dx, x, (size_t)n * CPQR_MLP_FEATURES * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, launch_mlp_forward(dw, dx, n, dy, s));
+  HIP_TRY(h, hipMemcpyAsync(y, dy, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  return CPQR_OK;
+}
+
+cpqr_status cpqr_mlp_grad(cpqr_handle* h, const float* w, const float* x, const float* y, int n,
+                          float* loss, float* grad) {
+  if (!h) return CPQR_EINVAL;
+  h->err.clear();
+  if (!w || !x || !y || !loss || !grad || n < 1) return fail(h, CPQR_EINVAL, "mlp_grad: null pointer or n < 1");
+  HIP_TRY(h, hipSetDevice(h->device));
+  HIP_TRY(h, order_after_user(h));
+  hipStream_t s = h->stream;
+  const int chunks = mlp_grad_chunks(n, MLP_GRAD_PER_WAVE);
+  float *dw, *dx, *dy, *part, *lpart, *dg, *dl;
+  WS(h, "mlp:w", CPQR_MLP_PARAMS * sizeof(float), dw);
+  WS(h, "mlp:x", (size_t)n * CPQR_MLP_FEATURES * sizeof(float), dx);
+  WS(h, "mlp:y", (size_t)n * sizeof(float), dy);
+  WS(h, "mlp:part", (size_t)chunks * CPQR_MLP_PARAMS * sizeof(float), part);
+  WS(h, "mlp:lpart", (size_t)chunks * sizeof(float), lpart);
+  WS(h, "mlp:g", (CPQR_MLP_PARAMS + 1) * sizeof(float), dg);
+  dl = dg + CPQR_MLP_PARAMS;
+  HIP_TRY(h, hipMemcpyAsync(dw, w, CPQR_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, hipMemcpyAsync(dx, x, (size_t)n * CPQR_MLP_FEATURES * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, hipMemcpyAsync(dy, y, (size_t)n * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, launch_mlp_grad(dw, dx, dy, nullptr, n, part, lpart, dg, dl, s));
+  HIP_TRY(h, hipMemcpyAsync(grad, dg, CPQR_MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipMemcpyAsync(loss, dl, sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  return CPQR_OK;
+}
+
+cpqr_status cpqr_mlp_train(cpqr_handle* h, float* w, const float* x, const float* y, int n, int epochs,
+                           int batch, float lr, uint64_t seed, float* loss_history) {
+  if (!h) return CPQR_EINVAL;
+  h->err.clear();
+  if (!w || !x || !y || n < 1 || batch < 1 || epochs < 0)
+    return fail(h, CPQR_EINVAL, "mlp_train: null pointer, n < 1, batch < 1 or epochs < 0");
+  HIP_TRY(h, hipSetDevice(h->device));
+  HIP_TRY(h, order_after_user(h));
+  hipStream_t s = h->stream;
+  const int bmax = std::min(batch, n);
+  const int chunks = std::max(mlp_grad_chunks(bmax, MLP_GRAD_PER_WAVE), mlp_grad_chunks(n, MLP_GRAD_PER_WAVE));
+  float *dw, *dx, *dy, *part, *lpart, *dg, *dm, *dv;
+  int* didx;
+  WS(h, "mlp:w", CPQR_MLP_PARAMS * sizeof(float), dw);
+  WS(h, "mlp:x", (size_t)n * CPQR_MLP_FEATURES * sizeof(float), dx);
+  WS(h, "mlp:y", (size_t)n * sizeof(float), dy);
+  WS(h, "mlp:part", (size_t)chunks * CPQR_MLP_PARAMS * sizeof(float), part);
+  WS(h, "mlp:lpart", (size_t)chunks * sizeof(float), lpart);
+  WS(h, "mlp:g", (CPQR_MLP_PARAMS + 1) * sizeof(float), dg);
+  WS(h, "mlp:m", CPQR_MLP_PARAMS * sizeof(float), dm);
+  WS(h, "mlp:v", CPQR_MLP_PARAMS * sizeof(float), dv);
+  WS(h, "mlp:idx", (size_t)n * epochs * sizeof(int) + sizeof(int), didx);
+  // seeded shuffles for every epoch (splitmix64 stream driving Fisher-Yates)
+  std::vector<int> order((size_t)n * epochs);
+  uint64_t st = seed;
+  auto next = [&]() {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  for (int e = 0; e < epochs; ++e) {
+    int* o = order.data() + (size_t)e * n;
+    for (int i = 0; i < n; ++i) o[i] = i;
+    for (int i = n - 1; i > 0; --i) std::swap(o[i], o[next() % (uint64_t)(i + 1)]);
+  }
+  HIP_TRY(h, hipMemcpyAsync(dw, w, CPQR_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, hipMemcpyAsync(dx, x, (size_t)n * CPQR_MLP_FEATURES * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, hipMemcpyAsync(dy, y, (size_t)n * sizeof(float), hipMemcpyHostToDevice, s));
+  if (epochs > 0)
+    HIP_TRY(h, hipMemcpyAsync(didx, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(h, hipMemsetAsync(dm, 0, CPQR_MLP_PARAMS * sizeof(float), s));
+  HIP_TRY(h, hipMemsetAsync(dv, 0, CPQR_MLP_PARAMS * sizeof(float), s));
+  std::vector<float> losses(epochs > 0 ? epochs : 1);
+  int t = 0;
+  for (int e = 0; e < epochs; ++e) {
+    for (int b0 = 0; b0 < n; b0 += bmax) {
+      const int nb = std::min(bmax, n - b0);
+      HIP_TRY(h, launch_mlp_grad(dw, dx, dy, didx + (size_t)e * n + b0, nb, part, lpart, dg,
+                                 dg + CPQR_MLP_PARAMS, s));
+      HIP_TRY(h, launch_mlp_adam(dw, dg, dm, dv, ++t, lr, 0.9f, 0.999f, 1e-8f, s));
+    }
+    // loss over all rows after the epoch
+    HIP_TRY(h, launch_mlp_grad(dw, dx, dy, nullptr, n, part, lpart, dg, dg + CPQR_MLP_PARAMS, s));
+    HIP_TRY(h, hipMemcpyAsync(&losses[e], dg + CPQR_MLP_PARAMS, sizeof(float), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(h, hipMemcpyAsync(w, dw, CPQR_MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  if (loss_history)
+    for (int e = 0; e < epochs; ++e) loss_history[e] = losses[e];
+  return CPQR_OK;
 }
 
 }  // extern "C"

@@ -95,6 +95,8 @@ def test_schedule_rejects_bad_arguments():
     (dict(dims=[40, 40, 40], rank=5, raw={"tree": 5}), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, raw={"prec": 3}), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, raw={"extrapolate": 4}), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, extrapolate="learned"), C.EINVAL),   # learned needs mlp_weights
+    (dict(dims=[40, 40, 40], rank=5, extrapolate="learned", mlp_weights=True), C.OK),
     (dict(dims=[40, 40, 40], rank=5, raw={"null_init": True}), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, raw={"null_init_k": 1}), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, raw={"null_dims": True}), C.EINVAL),
