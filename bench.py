@@ -85,6 +85,61 @@ def cpu_baseline(prob, budget_s: float):
                       f"multi-TTM from X, float64 numpy), {sec:.1f} s"}
 
 
+def time_to_fit_study(max_sweeps: int = 200):
+    """Wall time on the GPU until the explicit fit reaches f* - 1e-6 on the
+    40^5 rank-16 workload, for plain ALS-QR-BR, the paper's ALS-QR-BRE and the
+    learned extrapolation with its fallback.  f* is the explicit fit of the
+    float64 oracle's plain BR after 200 sweeps (tests/golden, written by a
+    script that calls only the oracle).  Only the sweeps are timed (host clock
+    around sweeps + synchronisation); the explicit fit checked after each
+    sweep is not."""
+    import numpy as np
+    import torch
+
+    import paper_2503_18759_amd as P
+    from paper_2503_18759_amd import learned_beta as LB
+    import synthgen as G
+
+    with open(os.path.join(ROOT, "tests", "golden", "fstar_40pow5_r16.json")) as f:
+        fstar = float(json.load(f)["fstar"])
+    target = fstar - 1e-6
+    prob = G.workload("fp32_40pow5_r16")
+    x, dims = P.to_device(prob.X)
+    weights = LB.load_weights()
+    variants = {"plain_br": dict(extrapolate="off"), "paper_bre": dict(extrapolate="paper"),
+                "learned_fallback": dict(extrapolate="learned", mlp_weights=weights)}
+    out = {}
+    for name, kw in variants.items():
+        sess = P.Session(x, prob.rank, prob.init, max_sweeps, dims=dims, tree="restructured",
+                         explicit_fit=True, **kw)
+        sess.sweeps(1)          # first sweep: graph capture and warm-up, not timed
+        sess.sync()
+        torch.cuda.synchronize()
+        sec, k, fitx, reached = 0.0, 1, float("nan"), False
+        while k < max_sweeps:
+            t0 = time.perf_counter()
+            sess.sweeps(1)
+            sess.sync()
+            sec += time.perf_counter() - t0
+            k += 1
+            fitx = sess.result()["fit_explicit"]
+            if fitx >= target:
+                reached = True
+                break
+        r = sess.result()
+        sess.close()
+        out[name] = {"seconds": sec, "sweeps": k, "reached": reached, "fit_explicit": fitx,
+                     "beta": r["beta"], "beta_sweep": r["beta_sweep"],
+                     "beta_learned": r["beta_learned"],
+                     "learned_fallback_sweep": r["learned_fallback_sweep"]}
+        print(json.dumps({"variant": name, **out[name]}), file=sys.stderr, flush=True)
+    return {"study": "time_to_fit", "workload": "order-5 dense 40^5 float32, rank 16, planted "
+            "congruence 0.85, noise 1e-3; restructured tree", "fstar": fstar,
+            "target": target, "max_sweeps": max_sweeps,
+            "timing": "sweeps 2..k, host clock around each sweep and its synchronisation",
+            "variants": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +149,8 @@ def main():
     ap.add_argument("--tree", default="restructured", choices=["none", "standard", "restructured"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--study", choices=["time-to-fit"], default=None,
+                    help="run a study instead of the benchmark (prints its own JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-MiB device buffer once (a plain copy "
                          "kernel of known size, used to scale hardware byte counters)")
@@ -113,6 +170,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     P.load_library()
+    if args.study == "time-to-fit":
+        print(json.dumps(time_to_fit_study()), flush=True)
+        return
     prob = G.workload(WORKLOAD)
     x, dims = P.to_device(prob.X)
     R, K, W = prob.rank, args.steps, args.warmup

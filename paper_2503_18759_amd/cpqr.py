@@ -73,13 +73,18 @@ _lib = None
 
 
 def load_library(path: str = LIB_PATH):
-    """Load libcpqr.so; raises if it has not been built."""
+    """Load libcpqr.so; raises if it has not been built.
+
+    torch is imported first: it brings its own HIP runtime (libamdhip64), and
+    loading it before libcpqr makes the library bind to that same runtime, so
+    device memory, streams and events are shared with torch."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libcpqr.so not found at {path}: build it with "
                            "`python -m paper_2503_18759_amd.build` (no CPU fallback exists)")
+    import torch  # noqa: F401  (see above)
     L = ctypes.CDLL(path)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
     L.cpqr_create.argtypes = [ctypes.POINTER(vp), i32, vp]
@@ -289,11 +294,12 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
 def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequence[np.ndarray]],
                       iters: int = 50, *, dims: Optional[Sequence[Sequence[int]]] = None,
                       tree: str = "restructured", extrapolate: str = "off", prec: str = "fp32",
-                      alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
+                      alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta=0.0,
                       explicit_fit: bool = False, handle: Optional[Handle] = None) -> List[Dict]:
     """Independent decompositions run together (cpqr_als_qr_batched): every
     sweep of the whole batch is one HIP graph of batched kernels.  Returns one
-    result dict per problem (as :func:`cp_als_qr`)."""
+    result dict per problem (as :func:`cp_als_qr`).  ``fixed_beta`` may be one
+    value or one per problem."""
     L = load_library()
     count = len(xs)
     if not (len(ranks) == len(inits) == count) or count < 1:
@@ -303,8 +309,9 @@ def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequen
     optv = (_Options * count)()
     resv = (_Result * count)()
     for t in range(count):
+        fb = fixed_beta[t] if isinstance(fixed_beta, (list, tuple, np.ndarray)) else fixed_beta
         d, keep = _prepare(xs[t], ranks[t], inits[t], iters, dims[t] if dims else None, tree,
-                           extrapolate, prec, 0.0, alpha, switch_delta, fixed_beta, explicit_fit,
+                           extrapolate, prec, 0.0, alpha, switch_delta, fb, explicit_fit,
                            False, True)
         keeps.append(keep)
         tens[t] = keep["ten"]
