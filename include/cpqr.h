@@ -118,6 +118,10 @@ typedef struct {
   const double *const *init_factors; /* host, N pointers to I_n x R column-major float64 initial factors */
   unsigned flags;       /* CPQR_FLAG_* */
   const float *mlp_weights; /* host, CPQR_MLP_PARAMS floats; required with CPQR_EXTRAP_LEARNED, else ignored */
+  const double *beta_schedule; /* host, `iters` values or NULL.  With CPQR_EXTRAP_PAPER: sweep k+1 uses
+                                  beta = beta_schedule[k] (k >= 1; entry 0 is unused since sweep 1 has
+                                  no previous Q0), overriding the rule and fixed_beta.  Used to label the
+                                  training data of the learned extrapolation. */
 } cpqr_options;
 
 typedef struct {

@@ -295,7 +295,7 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
               tree: str = "none", extrap: str = "off", alpha: float = 0.1,
               delta: float = 0.03, tol: float = 0.0, fix_beta: Optional[float] = None,
               explicit_every_sweep: bool = False, explicit_final: bool = True,
-              sweep_callback=None, mlp_weights=None) -> Dict:
+              sweep_callback=None, mlp_weights=None, beta_schedule=None) -> Dict:
     """CP-ALS-QR (Algorithm 2) / ALS-QR-BR(E) (Algorithm 3) in FP64 with
     direct multi-TTMs from X.  ``tree`` only selects the update order.
 
@@ -306,7 +306,9 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
     previous one, otherwise the sweep-start state is restored, beta becomes
     the paper's table value for the previous fit and the sweep is redone).
     ``fix_beta`` (test hook): apply this beta from sweep 2 onward instead of
-    the rule.  ``sweep_callback(k, fit)`` (instrumentation hook) is called
+    the rule.  ``beta_schedule`` (with "paper"): sweep k >= 2 uses
+    beta_schedule[k - 1] instead of the rule.  ``sweep_callback(k, fit)``
+    (instrumentation hook) is called
     after each sweep; ``explicit_final=False`` skips the final explicit fit.
     """
     import copy
@@ -342,7 +344,9 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
     for k in range(1, iters + 1):
         order = sweep_order(N, tree, k)
         orders.append(order)
-        if fix_beta is not None:
+        if beta_schedule is not None and extrap == "paper":
+            b = float(beta_schedule[k - 1]) if k >= 2 else 0.0
+        elif fix_beta is not None:
             b = fix_beta if k >= 2 else 0.0
         else:
             b = beta if (extrap in ("paper", "learned") and active) else 0.0
@@ -359,8 +363,8 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
         fits.append(fit)
         if explicit_every_sweep:
             fitxs.append(explicit_fit(X, lam, A))
-        if extrap == "paper" and fix_beta is None and not active and k >= 2 \
-                and abs(fit - fits[-2]) < delta:
+        if extrap == "paper" and fix_beta is None and beta_schedule is None and not active \
+                and k >= 2 and abs(fit - fits[-2]) < delta:
             beta, active, beta_sweep = beta_from_fit(fit), True, k
         if learned and k == 2 and not learned_on:
             from . import mlp_oracle as M

@@ -46,7 +46,8 @@ class _Options(ctypes.Structure):
                 ("iters", ctypes.c_int), ("tol", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("switch_delta", ctypes.c_double), ("fixed_beta", ctypes.c_double),
                 ("init_factors", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
-                ("flags", ctypes.c_uint), ("mlp_weights", ctypes.POINTER(ctypes.c_float))]
+                ("flags", ctypes.c_uint), ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
+                ("beta_schedule", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Result(ctypes.Structure):
@@ -210,7 +211,8 @@ def to_device(X: np.ndarray, dtype=None, device: int = 0):
 
 
 def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, switch_delta,
-             fixed_beta, explicit_fit, time_kernels, use_graph, mlp_weights=None):
+             fixed_beta, explicit_fit, time_kernels, use_graph, mlp_weights=None,
+             beta_schedule=None):
     dims, dt, ptr = _dims_and_ptr(x, dims)
     N = len(dims)
     inits = [np.asfortranarray(np.asarray(a, dtype=np.float64)) for a in init]
@@ -232,9 +234,16 @@ def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, sw
             raise ValueError(f"mlp_weights must hold {MLP_PARAMS} floats")
         keep["mlp_w"] = w
         wptr = w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    sptr = None
+    if beta_schedule is not None:
+        sch = np.ascontiguousarray(np.asarray(beta_schedule, dtype=np.float64).reshape(-1))
+        if sch.size != iters:
+            raise ValueError("beta_schedule must hold one value per sweep")
+        keep["sched"] = sch
+        sptr = sch.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     keep["opts"] = _Options(TREES[tree], EXTRAP[extrapolate], PRECS[prec], int(iters), float(tol),
                             float(alpha), float(switch_delta), float(fixed_beta),
-                            keep["init_ptrs"], flags, wptr)
+                            keep["init_ptrs"], flags, wptr, sptr)
     return dims, keep
 
 
@@ -272,7 +281,7 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
               extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
               alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
               explicit_fit: bool = False, time_kernels: bool = False, use_graph: bool = True,
-              mlp_weights=None, handle: Optional[Handle] = None) -> Dict:
+              mlp_weights=None, beta_schedule=None, handle: Optional[Handle] = None) -> Dict:
     """CP-ALS-QR / ALS-QR-BR(E) on the GPU (Algorithms 2 and 3).
 
     Returns a dict with factors (list of I_n x R float64 arrays), lam, fits
@@ -282,7 +291,7 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
     L = load_library()
     dims, keep = _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha,
                           switch_delta, fixed_beta, explicit_fit, time_kernels, use_graph,
-                          mlp_weights)
+                          mlp_weights, beta_schedule)
     h = handle or default_handle(x.device.index or 0)
     res, bufs = _result_buffers(dims, rank, iters)
     st = L.cpqr_als_qr(h._h, ctypes.byref(keep["ten"]), int(rank), ctypes.byref(keep["opts"]),
@@ -295,7 +304,8 @@ def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequen
                       iters: int = 50, *, dims: Optional[Sequence[Sequence[int]]] = None,
                       tree: str = "restructured", extrapolate: str = "off", prec: str = "fp32",
                       alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta=0.0,
-                      explicit_fit: bool = False, handle: Optional[Handle] = None) -> List[Dict]:
+                      explicit_fit: bool = False, beta_schedules=None,
+                      handle: Optional[Handle] = None) -> List[Dict]:
     """Independent decompositions run together (cpqr_als_qr_batched): every
     sweep of the whole batch is one HIP graph of batched kernels.  Returns one
     result dict per problem (as :func:`cp_als_qr`).  ``fixed_beta`` may be one
@@ -312,7 +322,8 @@ def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequen
         fb = fixed_beta[t] if isinstance(fixed_beta, (list, tuple, np.ndarray)) else fixed_beta
         d, keep = _prepare(xs[t], ranks[t], inits[t], iters, dims[t] if dims else None, tree,
                            extrapolate, prec, 0.0, alpha, switch_delta, fb, explicit_fit,
-                           False, True)
+                           False, True, None,
+                           beta_schedules[t] if beta_schedules is not None else None)
         keeps.append(keep)
         tens[t] = keep["ten"]
         optv[t] = keep["opts"]

@@ -192,6 +192,8 @@ struct FinishArgs {
   double fixed_beta;    // > 0: use from sweep 2 on
   int extrap;           // 0 off, 1 paper
   int last_in_sweep;
+  const double* beta_sched;  // device, sched_len values or null: beta of sweep k+1 = beta_sched[k]
+  int sched_len;
 };
 hipError_t launch_finish(const FinishArgs& f, hipStream_t st);
 // One workgroup per problem; every problem of the batch has rank class rmax

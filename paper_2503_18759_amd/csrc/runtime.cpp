@@ -141,6 +141,8 @@ struct Problem {
   // learned-beta sweep is rejected), with their shadow copies
   std::vector<std::pair<void*, size_t>> carried;
   std::vector<void*> shadow;
+  double* beta_sched = nullptr;   // device copy of cpqr_options.beta_schedule (iters values) or null
+  int sched_len = 0;
 };
 
 int64_t inter_elems(const Problem& p, uint32_t mask) {
@@ -320,6 +322,8 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   // the learned mode drives the same device-side beta state as the paper's rule
   f->extrap = (o->extrapolate != CPQR_EXTRAP_OFF) ? 1 : 0;
   f->last_in_sweep = last ? 1 : 0;
+  f->beta_sched = p.beta_sched;
+  f->sched_len = p.sched_len;
 }
 
 hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
@@ -567,6 +571,7 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   S.opts = *o;
   S.opts.init_factors = nullptr;
   S.opts.mlp_weights = nullptr;
+  S.opts.beta_schedule = nullptr;
   if (!build_schedule(N, o->tree, o->iters, S.sched) || !validate_schedule(N, S.sched))
     return fail(h, CPQR_EINVAL, "schedule construction failed");
   HIP_TRY(h, hipSetDevice(h->device));
@@ -603,6 +608,12 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
     return fail(h, CPQR_EINVAL, "||X|| = 0");
   }
   S.nx2 = hs.nx2;
+  if (o->beta_schedule && o->extrapolate == CPQR_EXTRAP_PAPER) {
+    WS(h, prefix + "beta_sched", (size_t)o->iters * sizeof(double), p.beta_sched);
+    HIP_TRY(h, hipMemcpy(p.beta_sched, o->beta_schedule, (size_t)o->iters * sizeof(double),
+                         hipMemcpyHostToDevice));
+    p.sched_len = o->iters;
+  }
   if (o->extrapolate == CPQR_EXTRAP_LEARNED) {
     WS(h, prefix + "mlp_w", CPQR_MLP_PARAMS * sizeof(float), S.mlp_w);
     WS(h, prefix + "mlp_io", (CPQR_MLP_FEATURES + 1) * sizeof(float), S.mlp_io);

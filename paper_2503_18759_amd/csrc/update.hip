@@ -287,7 +287,14 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
       const int k0 = st->sweep;
       f.fit_hist[k0] = fit;
       if (!isfinite(fit)) atomicOr(&st->flags, FLAG_NONFINITE);
-      if (f.extrap != 0 && !st->active) {
+      if (f.extrap != 0 && f.beta_sched != nullptr) {
+        // scheduled beta for the next sweep (k0 + 1 is its 0-based index)
+        if (k0 + 1 < f.sched_len) {
+          st->active = 1;
+          st->beta = f.beta_sched[k0 + 1];
+          st->beta_sweep = k0 + 1;
+        }
+      } else if (f.extrap != 0 && !st->active) {
         if (f.fixed_beta > 0.0) {
           if (k0 == 0) {
             st->active = 1;

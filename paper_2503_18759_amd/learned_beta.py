@@ -5,10 +5,14 @@ Section 4.3).
 Training set: 2,000 seeded problems (seeds 10000..11999), order 3 for even
 and 4 for odd indices, mode sizes U{24..64}, rank U{4..16}, planted
 congruence U[0, 0.9], noise 10^U[-4, -1.5] (relative).  For every problem
-the GPU runs HORIZON float32 sweeps of ALS-QR-BRE with beta fixed from sweep 2
-for each beta of GRID (one batched launch sequence per group of problems; the
-smallest grid value stands for beta = 0), and the label is the beta whose
-explicit fit after HORIZON sweeps is highest.  The features are those of the
+the GPU runs HORIZON float32 sweeps of ALS-QR-BRE for each beta of GRID with
+the schedule: beta = 0 in sweeps 1-2, the candidate beta in sweeps 3 to
+HORIZON-2, and beta = 0 in the last two sweeps (one batched launch sequence
+per group of problems).  The final plain sweeps matter: at a fixed point eq.
+(19) scales the update by 1 + (1 - alpha) beta, which the weights lambda
+carry, so a fit read while beta is still on mixes the acceleration with that
+offset; two plain sweeps remove it.  The label is the beta whose explicit fit
+after HORIZON sweeps is highest (ties: the smallest beta).  The features are those of the
 learned mode (include/cpqr.h), computed from the fits of sweeps 1 and 2 of
 the beta = 0 run.  The MLP (8 -> 64 tanh -> 1) regresses log10(beta + 1e-6)
 and is trained with the library's Adam kernels.
@@ -30,7 +34,7 @@ import numpy as np
 
 from . import cpqr as C
 
-GRID = [1e-12, 5e-5, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 1e-2, 2e-2]
+GRID = [0.0, 5e-5, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 1e-2, 2e-2, 3.5e-2, 5e-2]
 HORIZON = 30
 BASE_SEED = 10000
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "learned_beta_mlp.json")
@@ -41,6 +45,11 @@ def features(f1: float, f2: float, N: int, R: int, dims: Sequence[int]) -> np.nd
     d = [float(v) for v in dims]
     return np.array([f1, f2, 10.0 * (f2 - f1), math.log10(max(1.0 - f2, 1e-12)) / 4.0, N / 5.0,
                      R / 16.0, math.log2(sum(d) / len(d)) / 8.0, R / min(d)], dtype=np.float32)
+
+
+def schedule(beta: float) -> List[float]:
+    """Per-sweep beta (entry k is the beta of sweep k + 1)."""
+    return [0.0, 0.0] + [beta] * (HORIZON - 4) + [0.0, 0.0]
 
 
 def problem(t: int):
@@ -58,7 +67,7 @@ def problem(t: int):
 
 def label_group(probs) -> List[tuple]:
     """(features, best beta, explicit fits per grid value) for problems of one order."""
-    xs, dims, ranks, inits, betas = [], [], [], [], []
+    xs, dims, ranks, inits, scheds = [], [], [], [], []
     for p in probs:
         x, d = C.to_device(p.X)
         for b in GRID:
@@ -66,22 +75,22 @@ def label_group(probs) -> List[tuple]:
             dims.append(d)
             ranks.append(p.rank)
             inits.append(p.init)
-            betas.append(b)
+            scheds.append(schedule(b))
     res = C.cp_als_qr_batched(xs, ranks, inits, HORIZON, dims=dims, extrapolate="paper",
-                              fixed_beta=betas, explicit_fit=True)
+                              beta_schedules=scheds, explicit_fit=True)
     out = []
     G = len(GRID)
     for i, p in enumerate(probs):
         rs = res[i * G:(i + 1) * G]
         fx = np.array([r["fit_explicit"] for r in rs])
         best = int(np.argmax(fx))
-        beta = 0.0 if best == 0 else GRID[best]
+        beta = GRID[best]
         f = features(rs[0]["fits"][0], rs[0]["fits"][1], p.X.ndim, p.rank, p.X.shape)
         out.append((f, beta, fx))
     return out
 
 
-def build_dataset(count: int, group: int = 7, log=print):
+def build_dataset(count: int, group: int = 5, log=print):
     X, y, fits = [], [], []
     t0 = time.time()
     for order_parity in (0, 1):
@@ -121,8 +130,7 @@ def main():
     w, hist, val_loss, const_loss = train(X, y, epochs=args.epochs)
     print(f"train loss {hist[0]:.4f} -> {hist[-1]:.4f}; validation {val_loss:.4f} "
           f"(constant predictor {const_loss:.4f})", flush=True)
-    labels = {f"{b:g}": int(np.sum(np.isclose(y, math.log10((0.0 if i == 0 else b) + 1e-6))))
-              for i, b in enumerate(GRID)}
+    labels = {f"{b:g}": int(np.sum(np.isclose(y, math.log10(b + 1e-6)))) for b in GRID}
     doc = {
         "what": "weights of the learned extrapolation MLP (8 -> 64 tanh -> 1, output log10(beta + 1e-6))",
         "layout": "W1 (64 x 8 row-major), b1 (64), w2 (64), b2 (1)",

@@ -105,6 +105,21 @@ def test_fp32_trees(P, name, tree):
     _check_fp32(g, o)
 
 
+def test_fp64_beta_schedule(P):
+    """A per-sweep beta schedule (the labelling tool of the learned mode),
+    including zero entries, against the oracle with the same schedule."""
+    prob = G.workload("small_o4", dtype=np.float64)
+    sched = [0.0, 0.0, 3e-3, 3e-3, 0.0, 1e-2, 2e-4, 0.0, 5e-3, 5e-3, 0.0, 0.0]
+    x, dims = P.to_device(prob.X)
+    g = P.cp_als_qr(x, prob.rank, prob.init, len(sched), dims=dims, tree="restructured",
+                    extrapolate="paper", prec="fp64", beta_schedule=sched)
+    o = O.cp_als_qr(prob.X, prob.rank, prob.init, len(sched), tree="restructured", extrap="paper",
+                    beta_schedule=sched)
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+
+
 def test_fp32_paper_extrapolation(P):
     prob = G.make_problem([30, 26, 34], 5, seed=22, congruence=0.7, rho=0.02, dtype=np.float32)
     g, o = _run(P, prob, 40, prec="fp32", tree="restructured", extrap="paper")

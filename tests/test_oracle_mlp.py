@@ -95,3 +95,28 @@ def test_learned_rejection_falls_back_to_paper_beta():
     k = r["fallback_sweep"]
     assert r["beta"] == O.beta_from_fit(r["fits"][k - 2])
     assert np.all(np.diff(r["fits"][k - 2:]) > -1e-12)
+
+
+def test_zero_schedule_equals_plain_br():
+    """beta_schedule of zeros is exactly ALS-QR-BR (eq. 19 with beta = 0)."""
+    prob = G.make_problem([9, 8, 10], 3, seed=43, congruence=0.5, rho=0.05, dtype=np.float64)
+    a = O.cp_als_qr(prob.X, 3, prob.init, 7, tree="restructured", extrap="off")
+    b = O.cp_als_qr(prob.X, 3, prob.init, 7, tree="restructured", extrap="paper",
+                    beta_schedule=[0.0] * 7)
+    assert np.array_equal(a["fits"], b["fits"])
+
+
+def test_committed_weights_load_and_give_a_beta():
+    """The trained weights shipped with the package have the documented
+    layout and map a 40^5 rank-16 start to a beta inside the clamp."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2503_18759_amd", "data", "learned_beta_mlp.json")
+    with open(path) as f:
+        doc = json.load(f)
+    w = np.asarray(doc["weights"], dtype=np.float64)
+    assert w.size == M.PARAMS and np.all(np.isfinite(w))
+    x = M.features(0.8553, 0.8961, 5, 16, [40] * 5)
+    b = M.beta_from_output(M.forward(w, x)[0])
+    assert 0.0 <= b <= M.BETA_MAX
