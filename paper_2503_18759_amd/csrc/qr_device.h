@@ -9,8 +9,10 @@
 // the rows below the pivot, the RMAX values  sum_i x_i a_i[s]  (s = j gives
 // the squared tail norm, s > j the dot products with the trailing columns,
 // s < j the dot products with the earlier reflectors, which build T).  Per
-// column: one wave-level transpose reduction, an LDS exchange, the reflector
-// scalars computed once by wave 0, and two barriers.
+// column: one wave-level transpose reduction, one LDS exchange of the wave
+// partials behind a single barrier, and the reflector scalars computed by
+// every wave redundantly (so no second barrier is needed); the dot products
+// of column j+1 are formed while column j's update is applied.
 //
 // Reflector convention: x = column j from row j down; if the part below the
 // pivot is exactly zero the reflector is the identity (tau = 0); otherwise
@@ -75,7 +77,7 @@ template <int RMAX>
 struct QrSmem {
   double piv[2][RMAX];
   double red[2][QR_MAX_WAVES][RMAX];
-  double w[2][RMAX + 4];       // w_c (zero for c <= j), then tau, beta, scale
+  double w[QR_MAX_WAVES][RMAX];   // per-wave copy of w_c (zero for c <= j)
   double U[RMAX][RMAX + 1];    // U[m][j] = (V^T v_j)_m for m < j
   double T[RMAX][RMAX + 1];
   double tau[RMAX];
@@ -93,85 +95,135 @@ struct QrWySmem {
   double M[RMAX][RMAX + 1];    // T V1^T B
 };
 
+// Reflector scalars from q = x0^2 + st (st = squared norm below the pivot):
+// nrm = sqrt(q), beta = -sign(x0) nrm, tau = (|x0| + nrm) / nrm and
+// scale = 1 / (x0 - beta) = sign(x0) / (|x0| + nrm).  The hardware reciprocal
+// square root and reciprocal are refined by two Newton steps each (full
+// double precision from their ~2^-22 start); outside a safe exponent range
+// the exact library square root and divisions are used instead.
+__device__ __forceinline__ void qr_reflector_scalars(double x0, double st, double* tau, double* beta,
+                                                     double* scale) {
+  if (st == 0.0) {
+    *tau = 0.0;
+    *beta = x0;
+    *scale = 0.0;
+    return;
+  }
+  const double q = fma(x0, x0, st);
+  const double ax = fabs(x0);
+  double nrm, rn, rd;
+  if (q > 1e-280 && q < 1e280) {
+    double y = __builtin_amdgcn_rsq(q);
+    const double hq = 0.5 * q;
+    y = y * fma(-hq * y, y, 1.5);
+    y = y * fma(-hq * y, y, 1.5);
+    nrm = q * y;
+    rn = y;
+    const double den = ax + nrm;
+    double r = __builtin_amdgcn_rcp(den);
+    r = r * fma(-den, r, 2.0);
+    r = r * fma(-den, r, 2.0);
+    rd = r;
+  } else {
+    nrm = sqrt(q);
+    rn = 1.0 / nrm;
+    rd = 1.0 / (ax + nrm);
+  }
+  const bool neg = x0 < 0.0;
+  *beta = neg ? nrm : -nrm;
+  *tau = (ax + nrm) * rn;
+  *scale = neg ? -rd : rd;
+}
+
 // Factor the block (R <= RMAX columns); see the storage note above.
 template <int RMAX, int RPT>
 __device__ __forceinline__ void block_qr(QrRow<RMAX> (&a)[RPT], int R, QrSmem<RMAX>& sm) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NT = QrCfg<RMAX>::NT;
+  constexpr int G = 64 / RMAX;
+  // column 0: pivot row, x and the dot products
+  if (tid == 0) {
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) sm.piv[0][c] = a[0].get(c);
+  }
+  double x[RPT];
+  double part[RMAX];
+#pragma unroll
+  for (int p = 0; p < RPT; ++p) x[p] = (tid + NT * p > 0) ? a[p].get(0) : 0.0;
+#pragma unroll
+  for (int s = 0; s < RMAX; ++s) {
+    double acc = 0.0;
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) acc = fma(x[p], a[p].get(s), acc);
+    part[s] = acc;
+  }
   for (int j = 0; j < R; ++j) {
     const int buf = j & 1;
-    if (tid == j) {
+    wave_transpose_reduce<RMAX>(part);
+    if ((lane % G) == 0) sm.red[buf][wave][lane / G] = part[0];
+    __syncthreads();
+    // every wave: lane c < RMAX gets tot_c = sum_{i>j} x_i a_i[c]
+    double tot = 0.0;
+    if (lane < RMAX) {
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) sm.piv[buf][c] = a[0].get(c);
+      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
     }
-    // x = column j below the pivot (indexed register read)
-    double x[RPT];
+    const double st = __shfl(tot, j, 64);
+    const double x0 = sm.piv[buf][j];
+    double tau, beta, scale;
+    qr_reflector_scalars(x0, st, &tau, &beta, &scale);
+    if (lane < RMAX) {
+      // c > j: w_c = a_j[c] + scale * sum_{i>j} x_i a_i[c]  (v^T a_c with v_j = 1)
+      // m < j: u_m = (V^T v_j)_m = scale_m (x_m[j] + scale * sum_{i>j} x_i x_m[i])
+      const double pc = sm.piv[buf][lane];
+      const double wu = fma(scale, tot, pc);
+      sm.w[wave][lane] = (lane > j) ? wu : 0.0;
+      if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * sm.scale[lane] : 0.0;
+    }
+    if (wave == 0 && lane == 0) {
+      sm.tau[j] = tau;
+      sm.beta[j] = beta;
+      sm.scale[j] = scale;
+    }
+    // the wave reads back its own copy of w (same wave: ordering only)
+    __builtin_amdgcn_wave_barrier();
+    double wv[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) wv[c] = sm.w[wave][c];
+    // rows below the pivot: a -= tau v w^T with v = x scale; the pivot row:
+    // a -= tau w^T (v_j = 1); w vanishes for c <= j.  Column j+1 is updated
+    // first, then the remaining columns together with the dot products of
+    // column j+1.
+    const int jn = j + 1;
+    double coef[RPT], xn[RPT];
 #pragma unroll
     for (int p = 0; p < RPT; ++p) {
-      const double v = a[p].get(j);
-      x[p] = (tid + NT * p > j) ? v : 0.0;
+      const int row = tid + NT * p;
+      coef[p] = (row > j) ? tau * x[p] * scale : ((row == j) ? tau : 0.0);
     }
-    double part[RMAX];
+    const double wn = (jn < RMAX) ? sm.w[wave][jn < RMAX ? jn : 0] : 0.0;
+#pragma unroll
+    for (int p = 0; p < RPT; ++p) {
+      const int row = tid + NT * p;
+      const double an = (jn < RMAX) ? fma(-coef[p], wn, a[p].get(jn < RMAX ? jn : 0)) : 0.0;
+      xn[p] = (row > jn) ? an : 0.0;
+    }
 #pragma unroll
     for (int s = 0; s < RMAX; ++s) {
       double acc = 0.0;
 #pragma unroll
-      for (int p = 0; p < RPT; ++p) acc = fma(x[p], a[p].get(s), acc);
+      for (int p = 0; p < RPT; ++p) {
+        const double v = fma(-coef[p], wv[s], a[p].get(s));
+        a[p].set(s, v);
+        acc = fma(xn[p], v, acc);
+      }
       part[s] = acc;
     }
-    wave_transpose_reduce<RMAX>(part);
-    constexpr int G = 64 / RMAX;
-    if ((lane % G) == 0) sm.red[buf][wave][lane / G] = part[0];
-    __syncthreads();
-    if (wave == 0) {
-      // lane c < RMAX: tot = sum_i x_i a_i[c] over the rows below the pivot
-      double tot = 0.0;
-      if (lane < RMAX) {
 #pragma unroll
-        for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
-      }
-      const double st = __shfl(tot, j, 64);
-      const double x0 = sm.piv[buf][j];
-      double tau, beta, scale;
-      if (st == 0.0) {
-        tau = 0.0;
-        beta = x0;
-        scale = 0.0;
-      } else {
-        const double nrm = sqrt(fma(x0, x0, st));
-        beta = (x0 >= 0.0) ? -nrm : nrm;
-        const double d = x0 - beta;   // nonzero: |d| >= nrm
-        tau = -d / beta;
-        scale = 1.0 / d;
-      }
-      if (lane < RMAX) {
-        // c > j: w_c = a_j[c] + scale * sum_{i>j} x_i a_i[c]  (v^T a_c with v_j = 1)
-        // m < j: u_m = (V^T v_j)_m = scale_m (x_m[j] + scale * sum_{i>j} x_i x_m[i])
-        const double pc = sm.piv[buf][lane];
-        const double wu = fma(scale, tot, pc);
-        sm.w[buf][lane] = (lane > j) ? wu : 0.0;
-        sm.U[lane][j] = (lane < j) ? wu * sm.scale[lane] : 0.0;
-      }
-      if (lane == 0) {
-        sm.w[buf][RMAX] = tau;
-        sm.w[buf][RMAX + 1] = beta;
-        sm.w[buf][RMAX + 2] = scale;
-        sm.tau[j] = tau;
-        sm.beta[j] = beta;
-        sm.scale[j] = scale;
-      }
-    }
-    __syncthreads();
-    const double tau = sm.w[buf][RMAX];
-    const double scale = sm.w[buf][RMAX + 2];
+    for (int p = 0; p < RPT; ++p) x[p] = xn[p];
+    if (tid == jn && jn < R) {
 #pragma unroll
-    for (int p = 0; p < RPT; ++p) {
-      // rows below the pivot: a -= tau v w^T with v = x scale; the pivot
-      // row: a -= tau w^T (v_j = 1); w vanishes for c <= j
-      const int row = tid + NT * p;
-      const double coef = (row > j) ? tau * x[p] * scale : ((row == j) ? tau : 0.0);
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) a[p].set(c, fma(-coef, sm.w[buf][c], a[p].get(c)));
+      for (int c = 0; c < RMAX; ++c) sm.piv[buf ^ 1][c] = a[0].get(c);
     }
   }
   __syncthreads();
