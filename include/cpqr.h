@@ -84,6 +84,9 @@ typedef enum { CPQR_DTYPE_F64 = 0, CPQR_DTYPE_F32 = 1 } cpqr_dtype;
                                         kernels launch one by one, and each level-1 TTM runs as a graph
                                         of 8 back-to-back launches (it is idempotent) between two events */
 #define CPQR_FLAG_NO_GRAPH     0x4u  /* launch kernels one by one instead of replaying HIP graphs */
+#define CPQR_FLAG_DENSE_ZQR    0x8u  /* factor Z_n by the dense two-level TSQR even where the
+                                        one-workgroup staircase QR applies (Z_n of at most 256
+                                        rows, or order 3 at ranks 17..32); for comparison */
 
 typedef struct cpqr_handle cpqr_handle;
 

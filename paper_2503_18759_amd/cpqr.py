@@ -27,7 +27,8 @@ EXTRAP = {"off": 0, "paper": 1, "learned": 2}
 MLP_FEATURES, MLP_HIDDEN = 8, 64
 MLP_PARAMS = MLP_HIDDEN * MLP_FEATURES + 2 * MLP_HIDDEN + 1
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
-FLAG_EXPLICIT_FIT, FLAG_TIME_KERNELS, FLAG_NO_GRAPH = 0x1, 0x2, 0x4
+FLAG_EXPLICIT_FIT, FLAG_TIME_KERNELS, FLAG_NO_GRAPH, FLAG_DENSE_ZQR = 0x1, 0x2, 0x4, 0x8
+ZQR = ("stair", "dense")
 
 
 class CpqrError(RuntimeError):
@@ -212,7 +213,9 @@ def to_device(X: np.ndarray, dtype=None, device: int = 0):
 
 def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, switch_delta,
              fixed_beta, explicit_fit, time_kernels, use_graph, mlp_weights=None,
-             beta_schedule=None):
+             beta_schedule=None, zqr="stair"):
+    if zqr not in ZQR:
+        raise ValueError(f"zqr must be one of {ZQR}")
     dims, dt, ptr = _dims_and_ptr(x, dims)
     N = len(dims)
     inits = [np.asfortranarray(np.asarray(a, dtype=np.float64)) for a in init]
@@ -226,7 +229,7 @@ def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, sw
     keep["init_ptrs"] = (ctypes.POINTER(ctypes.c_double) * N)(
         *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in inits])
     flags = (FLAG_EXPLICIT_FIT if explicit_fit else 0) | (FLAG_TIME_KERNELS if time_kernels else 0) \
-        | (0 if use_graph else FLAG_NO_GRAPH)
+        | (0 if use_graph else FLAG_NO_GRAPH) | (FLAG_DENSE_ZQR if zqr == "dense" else 0)
     wptr = None
     if mlp_weights is not None:
         w = np.ascontiguousarray(np.asarray(mlp_weights, dtype=np.float32).reshape(-1))
@@ -281,8 +284,12 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
               extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
               alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
               explicit_fit: bool = False, time_kernels: bool = False, use_graph: bool = True,
-              mlp_weights=None, beta_schedule=None, handle: Optional[Handle] = None) -> Dict:
+              mlp_weights=None, beta_schedule=None, zqr: str = "stair",
+              handle: Optional[Handle] = None) -> Dict:
     """CP-ALS-QR / ALS-QR-BR(E) on the GPU (Algorithms 2 and 3).
+
+    ``zqr="dense"`` factors Z_n by the two-level TSQR even where the
+    one-workgroup staircase QR applies (for comparison).
 
     Returns a dict with factors (list of I_n x R float64 arrays), lam, fits
     (per-sweep fit history), fit, fit_explicit, orders, beta, beta_sweep,
@@ -291,7 +298,7 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
     L = load_library()
     dims, keep = _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha,
                           switch_delta, fixed_beta, explicit_fit, time_kernels, use_graph,
-                          mlp_weights, beta_schedule)
+                          mlp_weights, beta_schedule, zqr)
     h = handle or default_handle(x.device.index or 0)
     res, bufs = _result_buffers(dims, rank, iters)
     st = L.cpqr_als_qr(h._h, ctypes.byref(keep["ten"]), int(rank), ctypes.byref(keep["opts"]),
@@ -304,7 +311,7 @@ def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequen
                       iters: int = 50, *, dims: Optional[Sequence[Sequence[int]]] = None,
                       tree: str = "restructured", extrapolate: str = "off", prec: str = "fp32",
                       alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta=0.0,
-                      explicit_fit: bool = False, beta_schedules=None,
+                      explicit_fit: bool = False, beta_schedules=None, zqr: str = "stair",
                       handle: Optional[Handle] = None) -> List[Dict]:
     """Independent decompositions run together (cpqr_als_qr_batched): every
     sweep of the whole batch is one HIP graph of batched kernels.  Returns one
@@ -323,7 +330,7 @@ def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequen
         d, keep = _prepare(xs[t], ranks[t], inits[t], iters, dims[t] if dims else None, tree,
                            extrapolate, prec, 0.0, alpha, switch_delta, fb, explicit_fit,
                            False, True, None,
-                           beta_schedules[t] if beta_schedules is not None else None)
+                           beta_schedules[t] if beta_schedules is not None else None, zqr)
         keeps.append(keep)
         tens[t] = keep["ten"]
         optv[t] = keep["opts"]
@@ -346,14 +353,15 @@ class Session:
                  extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
                  alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
                  explicit_fit: bool = False, time_kernels: bool = False,
-                 use_graph: bool = True, mlp_weights=None, handle: Optional[Handle] = None):
+                 use_graph: bool = True, mlp_weights=None, zqr: str = "stair",
+                 handle: Optional[Handle] = None):
         L = load_library()
         self._x = x
         self.rank = rank
         self.max_sweeps = max_sweeps
         self.dims, self._keep = _prepare(x, rank, init, max_sweeps, dims, tree, extrapolate, prec,
                                          tol, alpha, switch_delta, fixed_beta, explicit_fit,
-                                         time_kernels, use_graph, mlp_weights)
+                                         time_kernels, use_graph, mlp_weights, None, zqr)
         self.h = handle or default_handle(x.device.index or 0)
         self._s = ctypes.c_void_p()
         self.h.check(L.cpqr_session_create(self.h._h, ctypes.byref(self._keep["ten"]), int(rank),

@@ -131,6 +131,25 @@ struct TsqrBatch {
 };
 hipError_t launch_tsqr_batched(const TsqrBatch& b, hipStream_t st);
 void tsqr_args(const TsqrArgs& t, const TsqrPlan& pl, LeafArgs* la, TopArgs* ta, FormArgs* fa);
+// Khatri-Rao QR of Z_n in one workgroup, rows in staircase order (largest
+// digit first).  Used when Z_n has at most 256 rows, or when its rows beyond
+// the first 256 fit the narrow slices of an instantiated shape.
+struct StairPlan {
+  bool ok;
+  int rmax;       // columns of slice 0
+  int ns;         // narrow slices (0: all rows in slice 0)
+};
+StairPlan stair_plan(int N, int R);
+struct StairArgs {
+  int N, n, R;          // order, skipped mode, rank
+  int64_t M;            // R^(N-1) rows of Z_n
+  const double* rf;     // N x R x R column-major R factors
+  double* R0;           // R x R output (column-major, diag >= 0)
+  double* Q0;           // M x R output (column-major, Kolda row order)
+  int active;           // 0: nothing to do (batched entries of other plans)
+};
+hipError_t launch_zqr_stair(const StairPlan& pl, const StairArgs& a, hipStream_t st);
+hipError_t launch_zqr_stair_batched(const StairPlan& pl, int count, const StairArgs* args, hipStream_t st);
 hipError_t launch_factor_qr(int I, int R, const double* A, double* Rn, double* q64, float* q32,
                             hipStream_t st);
 

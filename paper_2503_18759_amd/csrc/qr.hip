@@ -91,7 +91,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(LeafArgs a0, const LeafArgs* __res
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
       if (c < R) {
-        const double v = block_qr_v<RMAX, RPT>(a, q, lr, c, sm);
+        const double v = block_qr_v<RMAX>(a[q], lr, c, sm);
         V[row + ldv * c] = v;
       }
     }
@@ -144,7 +144,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_top(TopArgs a0, const TopArgs* __restri
     for (int c = 0; c < RMAX; ++c) a[q].set(c, (row < rows && c < R) ? stack[row + rows * c] : 0.0);
   }
   block_qr<RMAX, RPT>(a, R, sm);
-  block_qr_publish<RMAX, RPT>(a, R, sm, wy, true);
+  block_qr_publish<RMAX>(a[0], R, sm, wy, true);
   block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
   for (int e = tid; e < R * R; e += QrCfg<RMAX>::NT) {
     const int i = e % R, c = e / R;
@@ -154,7 +154,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_top(TopArgs a0, const TopArgs* __restri
   for (int q = 0; q < RPT; ++q) {
     const int64_t row = tid + QrCfg<RMAX>::NT * q;
     if (row < rows)
-      block_qr_q_row<RMAX, RPT>(a, q, R, sm, wy, [&](int c, double val) { Qtop[row + rows * c] = val; });
+      block_qr_q_row<RMAX>(a[q], (int)row, R, sm, wy, [&](int c, double val) { Qtop[row + rows * c] = val; });
   }
 }
 
@@ -206,6 +206,160 @@ __global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(FormArgs a0, const Fo
     if (c < R) Q0[row + M * c] = q[c];
 }
 
+// --------------------------------------------------------------- staircase
+// Digits (d_0 .. d_{K-1}; d_0 indexes the first remaining mode) of staircase
+// position s.  Shell m (largest digit m) holds positions [m^K, (m+1)^K);
+// inside a shell the tuples come by the highest index h with d_h = m, from
+// h = K-1 down to 0, then by the digits below h (base m+1, lowest fastest)
+// and above h (base m).  Positions below (c+1)^K are exactly the tuples with
+// every digit <= c, the profile of column c of Z_n.
+__device__ __forceinline__ int64_t ipow_d(int64_t b, int e) {
+  int64_t p = 1;
+  for (int k = 0; k < e; ++k) p *= b;
+  return p;
+}
+
+template <int KMAX>
+__device__ __forceinline__ void stair_digits(int64_t s, int K, int (&d)[KMAX]) {
+  int m = (int)floor(pow((double)s, 1.0 / (double)K));
+  while (ipow_d(m + 1, K) <= s) ++m;
+  while (m > 0 && ipow_d(m, K) > s) --m;
+  int64_t o = s - ipow_d(m, K);
+  int h = K - 1;
+  int64_t lo = 1;
+  for (; h >= 0; --h) {
+    lo = ipow_d(m + 1, h);
+    const int64_t cnt = lo * ipow_d(m, K - 1 - h);
+    if (o < cnt) break;
+    o -= cnt;
+  }
+  int64_t l = o % lo, u = o / lo;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    int dk = 0;
+    if (k < h) {
+      dk = (int)(l % (m + 1));
+      l /= (m + 1);
+    } else if (k == h) {
+      dk = m;
+    } else if (k < K) {
+      dk = (int)(u % m);
+      u /= m;
+    }
+    d[k] = dk;
+  }
+}
+
+// One workgroup per problem: build Z_n in staircase order from the R
+// factors, factor it (block_qr_stair) and write R0 (diag >= 0) and the
+// explicit Q0 (sign-fixed, rows scattered back to the Kolda order).
+template <int RMAX, int NS, int RT, int CS>
+__global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __restrict__ batch) {
+  const StairArgs args = batch ? batch[blockIdx.x] : a0;
+  if (!args.active) return;
+  constexpr int NT = QrCfg<RMAX>::NT;
+  constexpr int KMAX = qr_max_other_modes(RMAX);
+  constexpr int NSA = NS > 0 ? NS : 1;
+  const int N = args.N, n = args.n, R = args.R, K = N - 1;
+  const int64_t M = args.M;
+  __shared__ QrSmem<RMAX> sm;
+  // the R factors are needed only to build Z_n; their LDS is reused for the
+  // compact WY product afterwards
+  __shared__ union StairLds {
+    double srf[KMAX * RMAX * RMAX];
+    QrWySmem<RMAX> wy;
+  } u;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < K * RMAX * RMAX; e += NT) {
+    const int q = e / (RMAX * RMAX), rem = e % (RMAX * RMAX);
+    const int i = rem % RMAX, c = rem / RMAX;
+    const int mode = (q < n) ? q : q + 1;
+    u.srf[e] = (i < R && c < R) ? args.rf[(int64_t)mode * R * R + i + (int64_t)R * c] : 0.0;
+  }
+  __syncthreads();
+  QrStair<RMAX, NS, RT, CS> z;
+  int64_t krow[NS + 1];   // Kolda row of each held row (-1: beyond M)
+  {
+    int d[KMAX];
+    const int64_t s0 = tid;
+    if (s0 < M) {
+      stair_digits<KMAX>(s0, K, d);
+      int64_t kr = 0, w = 1;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < K) {
+          kr += d[k] * w;
+          w *= R;
+        }
+      krow[0] = kr;
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) {
+        double v = 1.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < K) v *= u.srf[k * RMAX * RMAX + d[k] + RMAX * c];
+        z.a0.set(c, v);
+      }
+    } else {
+      krow[0] = -1;
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) z.a0.set(c, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      const int64_t sq = (int64_t)NT * (q + 1) + tid;
+      if (sq < M) {
+        stair_digits<KMAX>(sq, K, d);
+        int64_t kr = 0, w = 1;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < K) {
+            kr += d[k] * w;
+            w *= R;
+          }
+        krow[q + 1] = kr;
+#pragma unroll
+        for (int c = 0; c < RT; ++c) {
+          double v = 1.0;
+#pragma unroll
+          for (int k = 0; k < KMAX; ++k)
+            if (k < K) v *= u.srf[k * RMAX * RMAX + d[k] + RMAX * (CS + c)];
+          z.at[q].set(c, v);
+        }
+      } else {
+        krow[q + 1] = -1;
+#pragma unroll
+        for (int c = 0; c < RT; ++c) z.at[q].set(c, 0.0);
+      }
+    }
+  }
+  (void)NSA;
+  block_qr_stair<RMAX, NS, RT, CS>(z, R, K, M, sm);
+  // R0 = D R with D = sign(diag R)
+  if (tid < R) {
+    const double sg = (sm.beta[tid] < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c)
+      if (c < R) args.R0[tid + R * c] = sg * block_qr_r<RMAX>(z.a0, tid, c, sm);
+  }
+  __syncthreads();   // the R factors in LDS are dead from here on
+  block_qr_publish<RMAX>(z.a0, R, sm, u.wy, true);
+  block_qr_wy_product<RMAX>(sm, u.wy, R, nullptr, 0);
+  double* __restrict__ Q0 = args.Q0;
+  if (krow[0] >= 0)
+    block_qr_q_row<RMAX>(z.a0, tid, R, sm, u.wy, [&](int c, double val) { Q0[krow[0] + M * c] = val; });
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    if (krow[q + 1] < 0) continue;
+    double v[RT];
+#pragma unroll
+    for (int m = 0; m < RT; ++m) v[m] = (CS + m < R) ? z.at[q].get(m) * sm.scale[CS + m] : 0.0;
+    const int64_t kr = krow[q + 1];
+    wy_q_row<RMAX, RT, CS>(v, (int64_t)NT * (q + 1) + tid, R, sm, u.wy,
+                           [&](int c, double val) { Q0[kr + M * c] = val; });
+  }
+}
+
 // ------------------------------------------------------------- factor QR
 // QR of the I x R float64 factor `A` (column-major) by one workgroup.
 // Writes Rn (R x R col-major, diag >= 0) and the explicit Q in the requested
@@ -225,7 +379,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void factor_qr(
     for (int c = 0; c < RMAX; ++c) a[q].set(c, (row < I && c < R) ? A[row + (int64_t)I * c] : 0.0);
   }
   block_qr<RMAX, RPT>(a, R, sm);
-  block_qr_publish<RMAX, RPT>(a, R, sm, wy, true);
+  block_qr_publish<RMAX>(a[0], R, sm, wy, true);
   block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
   for (int e = tid; e < R * R; e += QrCfg<RMAX>::NT) {
     const int i = e % R, c = e / R;
@@ -235,7 +389,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void factor_qr(
   for (int q = 0; q < RPT; ++q) {
     const int row = tid + QrCfg<RMAX>::NT * q;
     if (row < I)
-      block_qr_q_row<RMAX, RPT>(a, q, R, sm, wy, [&](int c, double val) {
+      block_qr_q_row<RMAX>(a[q], row, R, sm, wy, [&](int c, double val) {
         if (q64) q64[row + (int64_t)I * c] = val;
         if (q32) q32[row + (int64_t)I * c] = (float)val;
       });
@@ -350,6 +504,57 @@ hipError_t launch_tsqr_batched(const TsqrBatch& b, hipStream_t st) {
                        FormArgs{}, b.form);
   });
   return hipGetLastError();
+}
+
+// Shapes of zqr_stair: all rows in slice 0 (Z_n of at most 256 rows), and
+// order 3 at ranks 17..32 (rows 289..1024; the first 16 columns vanish
+// beyond row 256, the narrow slices hold columns 16..31 of rows 256..1023).
+StairPlan stair_plan(int N, int R) {
+  StairPlan pl{};
+  const int rm = qr_rmax(R);
+  if (rm == 0 || N < 2 || N - 1 > qr_max_other_modes(rm)) return pl;
+  int64_t M = 1;
+  for (int k = 0; k < N - 1; ++k) M *= R;
+  if (M <= QrCfg<32>::NT) {
+    pl.ok = true;
+    pl.rmax = rm;
+    pl.ns = 0;
+  } else if (N == 3 && rm == 32 && M <= 4 * QrCfg<32>::NT) {
+    pl.ok = true;
+    pl.rmax = 32;
+    pl.ns = 3;
+  }
+  return pl;
+}
+
+static hipError_t stair_launch(const StairPlan& pl, unsigned blocks, const StairArgs& a,
+                               const StairArgs* batch, hipStream_t st) {
+  if (!pl.ok) return hipErrorInvalidValue;
+  if (pl.ns == 0) {
+    if (pl.rmax == 8)
+      hipLaunchKernelGGL((zqr_stair<8, 0, 4, 4>), dim3(blocks), dim3(QrCfg<8>::NT), 0, st, a, batch);
+    else if (pl.rmax == 16)
+      hipLaunchKernelGGL((zqr_stair<16, 0, 8, 8>), dim3(blocks), dim3(QrCfg<16>::NT), 0, st, a, batch);
+    else if (pl.rmax == 32)
+      hipLaunchKernelGGL((zqr_stair<32, 0, 16, 16>), dim3(blocks), dim3(QrCfg<32>::NT), 0, st, a, batch);
+    else
+      return hipErrorInvalidValue;
+  } else if (pl.rmax == 32 && pl.ns == 3) {
+    hipLaunchKernelGGL((zqr_stair<32, 3, 16, 16>), dim3(blocks), dim3(QrCfg<32>::NT), 0, st, a, batch);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zqr_stair(const StairPlan& pl, const StairArgs& a, hipStream_t st) {
+  if (!pl.ok || a.M > (int64_t)QrCfg<32>::NT * (pl.ns + 1) || a.R > pl.rmax) return hipErrorInvalidValue;
+  return stair_launch(pl, 1, a, nullptr, st);
+}
+
+hipError_t launch_zqr_stair_batched(const StairPlan& pl, int count, const StairArgs* args, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  return stair_launch(pl, (unsigned)count, StairArgs{}, args, st);
 }
 
 int factor_rpt(int I) { return I <= QrCfg<32>::NT ? 1 : 2; }

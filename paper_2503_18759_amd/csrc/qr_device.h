@@ -135,6 +135,26 @@ __device__ __forceinline__ void qr_reflector_scalars(double x0, double st, doubl
   *scale = neg ? -rd : rd;
 }
 
+// T (upper triangular) of the compact WY form, row by row from the U
+// entries collected during the factorisation: T[k][k] = tau_k and
+// T[k][j] = -tau_j sum_{m=k}^{j-1} T[k][m] U[m][j] for j > k.
+template <int RMAX>
+__device__ __forceinline__ void block_qr_build_t(int R, QrSmem<RMAX>& sm) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < RMAX * (RMAX + 1); e += QrCfg<RMAX>::NT) (&sm.T[0][0])[e] = 0.0;
+  __syncthreads();
+  if (tid < R) {
+    const int k = tid;
+    sm.T[k][k] = sm.tau[k];
+    for (int j = k + 1; j < R; ++j) {
+      double acc = 0.0;
+      for (int m = k; m < j; ++m) acc = fma(sm.T[k][m], sm.U[m][j], acc);
+      sm.T[k][j] = -sm.tau[j] * acc;
+    }
+  }
+  __syncthreads();
+}
+
 // Factor the block (R <= RMAX columns); see the storage note above.
 template <int RMAX, int RPT>
 __device__ __forceinline__ void block_qr(QrRow<RMAX> (&a)[RPT], int R, QrSmem<RMAX>& sm) {
@@ -227,28 +247,151 @@ __device__ __forceinline__ void block_qr(QrRow<RMAX> (&a)[RPT], int R, QrSmem<RM
     }
   }
   __syncthreads();
-  // T (upper triangular), row by row: T[k][k] = tau_k,
-  // T[k][j] = -tau_j sum_{m=k}^{j-1} T[k][m] U[m][j]  (j > k)
-  for (int e = tid; e < RMAX * (RMAX + 1); e += NT) (&sm.T[0][0])[e] = 0.0;
-  __syncthreads();
-  if (tid < R) {
-    const int k = tid;
-    sm.T[k][k] = sm.tau[k];
-    for (int j = k + 1; j < R; ++j) {
-      double acc = 0.0;
-      for (int m = k; m < j; ++m) acc = fma(sm.T[k][m], sm.U[m][j], acc);
-      sm.T[k][j] = -sm.tau[j] * acc;
+  block_qr_build_t<RMAX>(R, sm);
+}
+
+// ------------------------------------------------------------ staircase QR
+// Householder QR of Z_n with its rows in staircase order.  Section 3.2 notes
+// the triangular structure of Q0 and Section 5 names exploiting it as a way
+// to cut the cost of Q0, its main bottleneck.  Column c of Z_n is the product,
+// row by row, of the columns c of the upper triangular R factors of the other
+// modes, so it vanishes at every row one of whose K digits (indices into the
+// other modes) exceeds c.  With the rows ordered by their largest digit, the
+// nonzeros of column c are the first (c+1)^K rows (its profile), and the
+// Householder reflectors keep that profile.
+//
+// Layout: slice 0 (row tid) holds all RMAX columns; the narrow slices
+// q = 0..NS-1 hold rows NT (q+1) + tid and only the RT columns [CS, CS+RT),
+// because the first CS columns vanish beyond row CS^K <= NT.  A narrow slice
+// takes part in a column step only once its first row lies in the column's
+// profile, so early columns run on slice 0 alone.  Requires R <= CS + RT
+// and R <= NT; otherwise the storage and reflector conventions of block_qr
+// hold (a narrow row keeps x of reflector c in its column c - CS).
+template <int RMAX, int NS, int RT, int CS>
+struct QrStair {
+  QrRow<RMAX> a0;
+  QrRow<RT> at[NS > 0 ? NS : 1];
+};
+
+// Rows in the profile of column c: min(M, (c+1)^K).
+__device__ __forceinline__ int64_t stair_profile(int c, int K, int64_t M) {
+  int64_t p = 1;
+  for (int k = 0; k < K; ++k) p *= (int64_t)(c + 1);
+  return p < M ? p : M;
+}
+
+template <int RMAX, int NS, int RT, int CS>
+__device__ __forceinline__ void block_qr_stair(QrStair<RMAX, NS, RT, CS>& z, int R, int K, int64_t M,
+                                               QrSmem<RMAX>& sm) {
+  static_assert(CS >= 1 && CS + RT <= RMAX, "narrow columns must lie inside the block");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NT = QrCfg<RMAX>::NT;
+  constexpr int G = 64 / RMAX;
+  constexpr int NSA = NS > 0 ? NS : 1;
+  if (tid == 0) {
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) sm.piv[0][c] = z.a0.get(c);
+  }
+  // x of the current column below the pivot: slice 0 and the narrow slices
+  // (which vanish in column 0 < CS)
+  double xs0 = (tid > 0) ? z.a0.get(0) : 0.0;
+  double xt[NSA];
+#pragma unroll
+  for (int q = 0; q < NSA; ++q) xt[q] = 0.0;
+  double part[RMAX];
+#pragma unroll
+  for (int s = 0; s < RMAX; ++s) part[s] = xs0 * z.a0.get(s);
+  for (int j = 0; j < R; ++j) {
+    const int buf = j & 1;
+    wave_transpose_reduce<RMAX>(part);
+    if ((lane % G) == 0) sm.red[buf][wave][lane / G] = part[0];
+    __syncthreads();
+    double tot = 0.0;
+    if (lane < RMAX) {
+#pragma unroll
+      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
+    }
+    const double st = __shfl(tot, j, 64);
+    const double xp = sm.piv[buf][j];
+    double tau, beta, scale;
+    qr_reflector_scalars(xp, st, &tau, &beta, &scale);
+    if (lane < RMAX) {
+      const double pc = sm.piv[buf][lane];
+      const double wu = fma(scale, tot, pc);
+      sm.w[wave][lane] = (lane > j) ? wu : 0.0;
+      if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * sm.scale[lane] : 0.0;
+    }
+    if (wave == 0 && lane == 0) {
+      sm.tau[j] = tau;
+      sm.beta[j] = beta;
+      sm.scale[j] = scale;
+    }
+    // the wave reads w back from its own LDS copy as the columns are updated
+    // (keeping all of w in registers as well would not fit beside the rows)
+    __builtin_amdgcn_wave_barrier();
+    const int jn = j + 1;
+    // narrow slices inside the profile of column min(jn, R-1); the profile
+    // of column j is contained in it, so every slice the reflector changes
+    // is among them
+    const int64_t prof = stair_profile(jn < R ? jn : R - 1, K, M);
+    int na = 0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) na += ((int64_t)NT * (q + 1) < prof) ? 1 : 0;
+    const double coef0 = (tid > j) ? tau * xs0 * scale : ((tid == j) ? tau : 0.0);
+    double coef[NSA];
+#pragma unroll
+    for (int q = 0; q < NSA; ++q) coef[q] = tau * xt[q] * scale;
+    const double wn = (jn < RMAX) ? sm.w[wave][jn < RMAX ? jn : 0] : 0.0;
+    const double an0 = (jn < RMAX) ? fma(-coef0, wn, z.a0.get(jn < RMAX ? jn : 0)) : 0.0;
+    const double xn0 = (tid > jn) ? an0 : 0.0;
+    const int jt = (jn - CS < 0) ? 0 : ((jn - CS >= RT) ? RT - 1 : jn - CS);
+    const bool jin = (jn >= CS) && (jn - CS < RT);
+    // one branch-free body per count of active narrow slices
+    static_for<0, NS + 1>([&](auto nac) {
+      constexpr int NA = decltype(nac)::value;
+      if (na != NA) return;
+      double xnt[NA > 0 ? NA : 1];
+      static_for<0, NA>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        xnt[q] = jin ? fma(-coef[q], wn, z.at[q].get(jt)) : 0.0;
+      });
+      static_for<0, RMAX>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        const double ws = sm.w[wave][s];
+        const double v = fma(-coef0, ws, z.a0.get(s));
+        z.a0.set(s, v);
+        double acc = xn0 * v;
+        if constexpr (s >= CS && s - CS < RT) {
+          static_for<0, NA>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            const double vt = fma(-coef[q], ws, z.at[q].get(s - CS));
+            z.at[q].set(s - CS, vt);
+            acc = fma(xnt[q], vt, acc);
+          });
+        }
+        part[s] = acc;
+      });
+      static_for<0, NSA>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        if constexpr (q < NA) xt[q] = xnt[q];
+        else xt[q] = 0.0;
+      });
+    });
+    xs0 = xn0;
+    if (tid == jn && jn < R) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c) sm.piv[buf ^ 1][c] = z.a0.get(c);
     }
   }
   __syncthreads();
+  block_qr_build_t<RMAX>(R, sm);
 }
 
 // Element (row, c) of the reflector matrix V (unit lower trapezoidal) for a
-// row held by this thread as a[p].
-template <int RMAX, int RPT>
-__device__ __forceinline__ double block_qr_v(const QrRow<RMAX> (&a)[RPT], int p, int row, int c,
-                                             const QrSmem<RMAX>& sm) {
-  return (row > c) ? a[p].get(c) * sm.scale[c] : ((row == c) ? 1.0 : 0.0);
+// row held by this thread in `r` (c is a column index of r).
+template <int RMAX>
+__device__ __forceinline__ double block_qr_v(const QrRow<RMAX>& r, int row, int c, const QrSmem<RMAX>& sm) {
+  return (row > c) ? r.get(c) * sm.scale[c] : ((row == c) ? 1.0 : 0.0);
 }
 
 // Element (j, c) of the R factor (before the sign fix), from the thread that
@@ -259,17 +402,18 @@ __device__ __forceinline__ double block_qr_r(const QrRow<RMAX>& row0, int j, int
   return (c > j) ? row0.get(c) : ((c == j) ? sm.beta[j] : 0.0);
 }
 
-// After block_qr: publish the first R rows of V and the R factor to LDS,
+// After the factorisation: publish the first R rows of V and the R factor to
+// LDS (row0 is the thread's row of slice 0, which holds rows 0..R-1),
 // optionally fixing signs so that diag(R) >= 0 (sm.sgn holds the signs).
-template <int RMAX, int RPT>
-__device__ __forceinline__ void block_qr_publish(const QrRow<RMAX> (&a)[RPT], int R, QrSmem<RMAX>& sm,
+template <int RMAX>
+__device__ __forceinline__ void block_qr_publish(const QrRow<RMAX>& row0, int R, QrSmem<RMAX>& sm,
                                                  QrWySmem<RMAX>& wy, bool fix_sign) {
   const int tid = threadIdx.x;
   if (tid < RMAX) {
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
       const bool in = (tid < R) && (c < R);
-      wy.V1[tid][c] = in ? block_qr_v<RMAX, RPT>(a, 0, tid, c, sm) : 0.0;
+      wy.V1[tid][c] = in ? block_qr_v<RMAX>(row0, tid, c, sm) : 0.0;
     }
     double sg = 1.0;
     if (fix_sign && tid < R && sm.beta[tid] < 0.0) sg = -1.0;
@@ -277,7 +421,7 @@ __device__ __forceinline__ void block_qr_publish(const QrRow<RMAX> (&a)[RPT], in
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) {
       const bool in = (tid < R) && (c < R);
-      wy.Rm[tid][c] = in ? sg * block_qr_r<RMAX>(a[0], tid, c, sm) : 0.0;
+      wy.Rm[tid][c] = in ? sg * block_qr_r<RMAX>(row0, tid, c, sm) : 0.0;
     }
   }
   __syncthreads();
@@ -311,22 +455,28 @@ __device__ __forceinline__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWy
   __syncthreads();
 }
 
-// Row `row` (block-local) of the explicit Q = (E - V M) * diag(sgn) with
-// M = T V1^T: store(c, value) for c < R; run-time loop over c.
-template <int RMAX, int RPT, typename Store>
-__device__ __forceinline__ void block_qr_q_row(const QrRow<RMAX> (&a)[RPT], int p, int R,
-                                               const QrSmem<RMAX>& sm, const QrWySmem<RMAX>& wy,
-                                               Store&& store) {
-  const int row = threadIdx.x + QrCfg<RMAX>::NT * p;
-  double v[RMAX];
-#pragma unroll
-  for (int m = 0; m < RMAX; ++m) v[m] = (m < R) ? block_qr_v<RMAX, RPT>(a, p, row, m, sm) : 0.0;
+// Row `row` of the explicit Q = (E - V M) * diag(sgn) with M = T V1^T, from
+// the row's reflector entries v[m] = V[row][OFF + m] (zero outside
+// [OFF, OFF + W)): store(c, value) for c < R; run-time loop over c.
+template <int RMAX, int W, int OFF, typename Store>
+__device__ __forceinline__ void wy_q_row(const double (&v)[W], int64_t row, int R, const QrSmem<RMAX>& sm,
+                                         const QrWySmem<RMAX>& wy, Store&& store) {
   for (int c = 0; c < R; ++c) {
     double acc = (row == c) ? 1.0 : 0.0;
 #pragma unroll
-    for (int m = 0; m < RMAX; ++m) acc = fma(-v[m], wy.M[m][c], acc);
+    for (int m = 0; m < W; ++m) acc = fma(-v[m], wy.M[OFF + m][c], acc);
     store(c, acc * sm.sgn[c]);
   }
+}
+
+// Row `row` (block-local) of the explicit Q for a row held in `r`.
+template <int RMAX, typename Store>
+__device__ __forceinline__ void block_qr_q_row(const QrRow<RMAX>& r, int row, int R, const QrSmem<RMAX>& sm,
+                                               const QrWySmem<RMAX>& wy, Store&& store) {
+  double v[RMAX];
+#pragma unroll
+  for (int m = 0; m < RMAX; ++m) v[m] = (m < R) ? block_qr_v<RMAX>(r, row, m, sm) : 0.0;
+  wy_q_row<RMAX, RMAX, 0>(v, row, R, sm, wy, store);
 }
 
 // Sum V doubles over the whole workgroup; every thread receives the totals.

@@ -123,6 +123,7 @@ struct Problem {
   int64_t M = 0;          // R^(N-1) rows of Z_n
   int P = 0;              // TSQR leaves
   int64_t leaf_rows = 0;
+  StairPlan stair{};      // staircase Z_n QR (ok == false: dense TSQR)
   int nchunks_max = 0;
   int Imax = 0;
   // device pointers
@@ -326,13 +327,17 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   f->sched_len = p.sched_len;
 }
 
+StairArgs stair_args(const TsqrArgs& t) {
+  return StairArgs{t.N, t.n, t.R, t.M, t.rf, t.R0, t.Q0, 1};
+}
+
 hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
                          hipStream_t s) {
   TsqrArgs t;
   ApplyArgs a;
   FinishArgs f;
   update_args(p, n, sweep_k, last, o, &t, &a, &f);
-  hipError_t e = launch_tsqr(t, s);
+  hipError_t e = p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
   if (e != hipSuccess) return e;
   e = launch_apply(a, s);
   if (e != hipSuccess) return e;
@@ -586,6 +591,7 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   p.X = X->data;
   p.f64 = (o->prec == CPQR_PREC_FP64);
   p.elem = p.f64 ? 8 : 4;
+  if (!(o->flags & CPQR_FLAG_DENSE_ZQR)) p.stair = stair_plan(N, rank);
   cpqr_status stt = setup(h, p, o->iters, S.sched);
   if (stt != CPQR_OK) return stt;
   S.nelem = 1;
@@ -1014,13 +1020,14 @@ void count_ttm(cpqr_session* S, const std::vector<Step>& sw) {
 // One batched launch of a sweep's step list, with the byte offsets of its
 // argument arrays inside the sweep's argument blob.
 struct BatchItem {
-  int kind = 0;                 // 0 TTM, 1 TSQR, 2 Y*Q0, 3 finish
+  int kind = 0;                 // 0 TTM, 1 TSQR, 2 Y*Q0, 3 finish, 4 staircase Z QR
   std::string tune_sig;         // TTM: identifies the step for the autotuner
   std::vector<int> members;     // problem indices
   TtmBatch tb{};
   TsqrBatch qb{};
   ApplyBatch ab{};
   int fin_rmax = 0, fin_rpt = 0;
+  StairPlan sp{};
   size_t off[3] = {0, 0, 0};
 };
 
@@ -1107,11 +1114,27 @@ void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpq
       std::vector<ApplyArgs> as(count);
       std::vector<FinishArgs> fs(count);
       for (int t = 0; t < count; ++t) update_args(B.S[t]->p, st.mode, k, last, o, &ts[t], &as[t], &fs[t]);
-      // TSQR groups: rank class and plan
+      // staircase Z QR groups: kernel shape; TSQR groups: rank class and plan
+      std::map<std::pair<int, int>, std::vector<int>> sg;
       std::map<std::tuple<int, int, int>, std::vector<int>> tg;
       for (int t = 0; t < count; ++t) {
+        const StairPlan& sp = B.S[t]->p.stair;
+        if (sp.ok) {
+          sg[{sp.rmax, sp.ns}].push_back(t);
+          continue;
+        }
         const TsqrPlan pl = tsqr_plan(ts[t].M, ts[t].R);
         tg[std::make_tuple(qr_rmax(ts[t].R), pl.leaf_rpt, pl.P > 1 ? pl.top_rpt : 0)].push_back(t);
+      }
+      for (auto& g : sg) {
+        BatchItem it;
+        it.kind = 4;
+        it.members = g.second;
+        it.sp = B.S[g.second[0]]->p.stair;
+        std::vector<StairArgs> sa;
+        for (int t : g.second) sa.push_back(stair_args(ts[t]));
+        it.off[0] = blob_put(*blob, sa);
+        items->push_back(it);
       }
       for (auto& g : tg) {
         BatchItem it;
@@ -1199,6 +1222,9 @@ hipError_t launch_item(const BatchItem& it, const char* base, hipStream_t s) {
       b.args = reinterpret_cast<const ApplyDev*>(base + it.off[0]);
       return launch_apply_batched(b, s);
     }
+    case 4:
+      return launch_zqr_stair_batched(it.sp, (int)it.members.size(),
+                                      reinterpret_cast<const StairArgs*>(base + it.off[0]), s);
     default:
       return launch_finish_batched((int)it.members.size(), it.fin_rmax, it.fin_rpt,
                                    reinterpret_cast<const FinishArgs*>(base + it.off[0]), s);

@@ -228,38 +228,56 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
     });
   }
   block_allreduce<2, NW>(sc, sred2);
-  // lambda = column norms of Ahat
-  double cn[RMAX];
+  // lambda = column norms of Ahat.  The wave partials of the squared norms
+  // go to LDS; lane c of every wave then owns column c (its total, norm and
+  // reciprocal), and each row takes the reciprocals with lane reads.
+  {
+    // two halves of at most 16 columns keep the reduction's registers low
+    constexpr int H = RMAX > 16 ? 16 : RMAX;
+    constexpr int G = 64 / H;
+    const int lane = tid & 63, wave = tid >> 6;
+    static_for<0, RMAX / H>([&](auto hc) {
+      constexpr int h0 = decltype(hc)::value * H;
+      double cn[H];
 #pragma unroll
-  for (int c = 0; c < RMAX; ++c) {
-    double s = 0.0;
+      for (int c = 0; c < H; ++c) {
+        double s = 0.0;
 #pragma unroll
-    for (int p = 0; p < RPT; ++p) s = fma(a[p].get(c), a[p].get(c), s);
-    cn[c] = s;
+        for (int p = 0; p < RPT; ++p) s = fma(a[p].get(h0 + c), a[p].get(h0 + c), s);
+        cn[c] = s;
+      }
+      wave_transpose_reduce<H>(cn);
+      if ((lane % G) == 0) sredR[wave][h0 + lane / G] = cn[0];
+    });
   }
-  block_allreduce<RMAX, NW>(cn, sredR);
-  double inv[RMAX];
+  __syncthreads();
+  const int lane = tid & 63;
+  double inv_l = 0.0;
+  {
+    double tot = 0.0;
+    if (lane < RMAX) {
 #pragma unroll
-  for (int c = 0; c < RMAX; ++c) {
-    const double lam = sqrt(cn[c]);
-    if (c < R) {
-      if (lam == 0.0) bad |= FLAG_RANKDEF;
-      if (!isfinite(lam)) bad |= FLAG_NONFINITE;
+      for (int w = 0; w < NW; ++w) tot += sredR[w][lane];
     }
-    inv[c] = (c < R && lam != 0.0) ? 1.0 / lam : 0.0;
-    if (tid == 0 && c < R) f.lambda[c] = lam;
+    const bool col = lane < R;
+    const double lam = sqrt(tot);
+    if (__any(col && lam == 0.0)) bad |= FLAG_RANKDEF;
+    if (__any(col && !isfinite(lam))) bad |= FLAG_NONFINITE;
+    inv_l = (col && lam != 0.0) ? 1.0 / lam : 0.0;
+    if (tid < R) f.lambda[tid] = lam;
   }
 #pragma unroll
-  for (int p = 0; p < RPT; ++p) {
-    const int row = tid + NT * p;
+  for (int c = 0; c < RMAX; ++c) {
+    const double ic = lane_read(inv_l, c);
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) {
-      a[p].set(c, a[p].get(c) * inv[c]);
+    for (int p = 0; p < RPT; ++p) {
+      const int row = tid + NT * p;
+      a[p].set(c, a[p].get(c) * ic);
       if (row < I && c < R) f.A[row + (int64_t)I * c] = a[p].get(c);
     }
   }
   block_qr<RMAX, RPT>(a, R, sm);
-  block_qr_publish<RMAX, RPT>(a, R, sm, wy, true);
+  block_qr_publish<RMAX>(a[0], R, sm, wy, true);
   block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
   for (int e = tid; e < R * R; e += NT) {
     const int i = e % R, c = e / R;
@@ -269,7 +287,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   for (int p = 0; p < RPT; ++p) {
     const int row = tid + NT * p;
     if (row < I)
-      block_qr_q_row<RMAX, RPT>(a, p, R, sm, wy, [&](int c, double val) {
+      block_qr_q_row<RMAX>(a[p], row, R, sm, wy, [&](int c, double val) {
         if (f.q64) f.q64[row + (int64_t)I * c] = val;
         if (f.q32) f.q32[row + (int64_t)I * c] = (float)val;
       });

@@ -68,15 +68,37 @@ def test_fp64_standard_40cube_rank5_full_workload(P):
     assert np.max(np.abs(g["lam"] - o["lam"]) / o["lam"]) <= 1e-9
 
 
+@pytest.mark.parametrize("zqr", ["stair", "dense"])
 @pytest.mark.parametrize("name", ["small_o3", "small_o4", "small_o5"])
 @pytest.mark.parametrize("tree", ["none", "standard", "restructured"])
-def test_fp64_trees(P, name, tree):
+def test_fp64_trees(P, name, tree, zqr):
     prob = G.workload(name, dtype=np.float64)
-    g, o = _run(P, prob, 12, prec="fp64", tree=tree)
+    g, o = _run(P, prob, 12, prec="fp64", tree=tree, zqr=zqr)
     assert g["orders"] == o["orders"]
     assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
     for a, b in zip(g["factors"], o["factors"]):
         assert np.max(np.abs(a - b)) <= 1e-8
+
+
+@pytest.mark.parametrize("dims,R,seed", [([36, 40, 34], 17, 61), ([30, 28, 33], 23, 62),
+                                         ([33, 35, 32], 32, 63)])
+def test_fp64_staircase_zqr_order3(P, dims, R, seed):
+    """Order 3 at ranks 17..32: Z_n (R^2 = 289..1024 rows) is factored in one
+    workgroup in staircase row order (rows past 256 hold only columns
+    16..31).  float64 parity with the oracle, whose Householder QR runs on
+    Z_n in the Kolda row order, and with the dense two-level TSQR."""
+    prob = G.make_problem(dims, R, seed=seed, congruence=0.5, rho=0.01, dtype=np.float64)
+    g, o = _run(P, prob, 6, prec="fp64", tree="restructured")
+    assert g["orders"] == o["orders"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+    assert np.max(np.abs(g["lam"] - o["lam"]) / o["lam"]) <= 1e-9
+    x, d = P.to_device(prob.X)
+    dz = P.cp_als_qr(x, R, prob.init, 6, dims=d, tree="restructured", prec="fp64", zqr="dense")
+    assert np.max(np.abs(g["fits"] - dz["fits"])) <= 1e-12
+    for a, b in zip(g["factors"], dz["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-10
 
 
 def test_fp64_fixed_beta_extrapolation(P):
