@@ -67,6 +67,31 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Device global memory (address space 1).  Accesses through these types
+// compile to global rather than flat loads and stores; flat accesses also
+// count against the LDS wait counter, so an LDS wait would stall on
+// outstanding global stores.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) f32x4 gf32x4;
+typedef __attribute__((address_space(1))) double gdouble;
+
+// Kernel arguments that come either by value or from a per-problem device
+// array (batched launches): the array entry is read by every lane and then
+// passed through readfirstlane word by word, so that the compiler keeps every
+// field in scalar registers (uniform pointers for buffer resources and
+// scalar loop bounds) instead of treating the struct as per-lane data.
+template <typename T>
+__device__ __forceinline__ T kernel_args(const T& by_value, const T* batch, unsigned index) {
+  static_assert(sizeof(T) % 4 == 0, "argument structs are made of 32-bit words");
+  T v = batch ? batch[index] : by_value;
+  int w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(T) / 4; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  __builtin_memcpy(&v, w, sizeof(T));
+  return v;
+}
+
 // Value of `v` in lane `l` (wave-uniform), read into scalar registers.
 __device__ __forceinline__ double lane_read(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);

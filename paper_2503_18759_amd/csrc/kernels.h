@@ -28,10 +28,14 @@ enum { FLAG_RANKDEF = 1, FLAG_NONFINITE = 2 };
 // --- TTM ------------------------------------------------------------------
 bool ttm_mfma_supported(int I, int R);
 // ev0/ev1 (optional): events stamped with the kernel's own start and end
-// (hipExtLaunchKernel), used to time single TTM launches.
+// (hipExtLaunchKernel), used to time single TTM launches.  ks: waves per
+// output tile (K split 1, 2 or 4); 0, or a split this shape cannot use,
+// takes the launcher's own choice.
 hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L, int I, int64_t S,
                           int R, bool bf16x3, hipStream_t st, hipEvent_t ev0 = nullptr,
-                          hipEvent_t ev1 = nullptr);
+                          hipEvent_t ev1 = nullptr, int ks = 0);
+// K splits a float32 MFMA TTM of this shape can use (bit k set: split 1 << k).
+unsigned ttm_ks_options(int64_t L, int I, int64_t S, int R);
 hipError_t launch_ttm_f64(const double* in, const double* Q, double* out, int64_t L, int I,
                           int64_t S, int R, hipStream_t st, hipEvent_t ev0 = nullptr,
                           hipEvent_t ev1 = nullptr);

@@ -30,17 +30,17 @@ int qr_max_order(int R) { return qr_max_other_modes(qr_rmax(R)) + 1; }
 // column-major matrix `src`.
 template <int RMAX, int RPT>
 __global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(LeafArgs a0, const LeafArgs* __restrict__ batch) {
-  const LeafArgs args = batch ? batch[blockIdx.y] : a0;
+  const LeafArgs args = kernel_args(a0, batch, blockIdx.y);
   if ((int)blockIdx.x >= args.P) return;
   const int N = args.N, n = args.n, R = args.R;
-  const double* __restrict__ rf = args.rf;
-  const double* __restrict__ src = args.src;
+  const gdouble* __restrict__ rf = (const gdouble*)args.rf;
+  const gdouble* __restrict__ src = (const gdouble*)args.src;
   const int64_t M = args.M, ldstack = args.ldstack;
-  double* __restrict__ V = args.V;
-  double* __restrict__ Tbuf = args.T;
-  double* __restrict__ stack = args.stack;
-  double* __restrict__ R0 = args.R0;
-  double* __restrict__ Qtop = args.Qtop;
+  gdouble* __restrict__ V = (gdouble*)args.V;
+  gdouble* __restrict__ Tbuf = (gdouble*)args.T;
+  gdouble* __restrict__ stack = (gdouble*)args.stack;
+  gdouble* __restrict__ R0 = (gdouble*)args.R0;
+  gdouble* __restrict__ Qtop = (gdouble*)args.Qtop;
   __shared__ QrSmem<RMAX> sm;
   __shared__ double srf[qr_max_other_modes(RMAX) * RMAX * RMAX];
   constexpr int B = QrCfg<RMAX>::NT * RPT;
@@ -126,13 +126,13 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(LeafArgs a0, const LeafArgs* __res
 // Qtop (P*R x R column-major) = explicit Q of the stack times the sign fix.
 template <int RMAX, int RPT>
 __global__ CPQR_QR_KERNEL(RMAX) void zqr_top(TopArgs a0, const TopArgs* __restrict__ batch) {
-  const TopArgs args = batch ? batch[blockIdx.y] : a0;
+  const TopArgs args = kernel_args(a0, batch, blockIdx.y);
   if (!args.active) return;
   const int R = args.R;
   const int64_t rows = args.rows;
-  const double* __restrict__ stack = args.stack;
-  double* __restrict__ R0 = args.R0;
-  double* __restrict__ Qtop = args.Qtop;
+  const gdouble* __restrict__ stack = (const gdouble*)args.stack;
+  gdouble* __restrict__ R0 = (gdouble*)args.R0;
+  gdouble* __restrict__ Qtop = (gdouble*)args.Qtop;
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   const int tid = threadIdx.x;
@@ -162,13 +162,13 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_top(TopArgs a0, const TopArgs* __restri
 // One workgroup per 256-row chunk.  Chunk rows lie inside one leaf p.
 template <int RMAX>
 __global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(FormArgs a0, const FormArgs* __restrict__ batch) {
-  const FormArgs args = batch ? batch[blockIdx.y] : a0;
+  const FormArgs args = kernel_args(a0, batch, blockIdx.y);
   const int R = args.R, leaf_rows = args.leaf_rows;
   const int64_t M = args.M, ldv = args.ldv, ldq = args.ldq;
-  const double* __restrict__ V = args.V;
-  const double* __restrict__ Tbuf = args.T;
-  const double* __restrict__ Qtop = args.Qtop;
-  double* __restrict__ Q0 = args.Q0;
+  const gdouble* __restrict__ V = (const gdouble*)args.V;
+  const gdouble* __restrict__ Tbuf = (const gdouble*)args.T;
+  const gdouble* __restrict__ Qtop = (const gdouble*)args.Qtop;
+  gdouble* __restrict__ Q0 = (gdouble*)args.Q0;
   if ((int64_t)blockIdx.x * QrCfg<RMAX>::NT >= M) return;
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
@@ -255,6 +255,8 @@ __device__ __forceinline__ void stair_digits(int64_t s, int K, int (&d)[KMAX]) {
 // explicit Q0 (sign-fixed, rows scattered back to the Kolda order).
 template <int RMAX, int NS, int RT, int CS>
 __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __restrict__ batch) {
+  // arguments read directly: passing them through readfirstlane makes the
+  // compiler spill this kernel's rows to the accumulation registers
   const StairArgs args = batch ? batch[blockIdx.x] : a0;
   if (!args.active) return;
   constexpr int NT = QrCfg<RMAX>::NT;
@@ -274,7 +276,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
     const int q = e / (RMAX * RMAX), rem = e % (RMAX * RMAX);
     const int i = rem % RMAX, c = rem / RMAX;
     const int mode = (q < n) ? q : q + 1;
-    u.srf[e] = (i < R && c < R) ? args.rf[(int64_t)mode * R * R + i + (int64_t)R * c] : 0.0;
+    u.srf[e] = (i < R && c < R) ? ((const gdouble*)args.rf)[(int64_t)mode * R * R + i + (int64_t)R * c] : 0.0;
   }
   __syncthreads();
   QrStair<RMAX, NS, RT, CS> z;
@@ -340,12 +342,12 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
     const double sg = (sm.beta[tid] < 0.0) ? -1.0 : 1.0;
 #pragma unroll
     for (int c = 0; c < RMAX; ++c)
-      if (c < R) args.R0[tid + R * c] = sg * block_qr_r<RMAX>(z.a0, tid, c, sm);
+      if (c < R) ((gdouble*)args.R0)[tid + R * c] = sg * block_qr_r<RMAX>(z.a0, tid, c, sm);
   }
   __syncthreads();   // the R factors in LDS are dead from here on
   block_qr_publish<RMAX>(z.a0, R, sm, u.wy, true);
   block_qr_wy_product<RMAX>(sm, u.wy, R, nullptr, 0);
-  double* __restrict__ Q0 = args.Q0;
+  gdouble* __restrict__ Q0 = (gdouble*)args.Q0;
   if (krow[0] >= 0)
     block_qr_q_row<RMAX>(z.a0, tid, R, sm, u.wy, [&](int c, double val) { Q0[krow[0] + M * c] = val; });
 #pragma unroll

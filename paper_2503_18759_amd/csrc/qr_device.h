@@ -188,7 +188,7 @@ __device__ __forceinline__ void block_qr(QrRow<RMAX> (&a)[RPT], int R, QrSmem<RM
 #pragma unroll
       for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
     }
-    const double st = __shfl(tot, j, 64);
+    const double st = lane_read(tot, j);
     const double x0 = sm.piv[buf][j];
     double tau, beta, scale;
     qr_reflector_scalars(x0, st, &tau, &beta, &scale);
@@ -311,7 +311,7 @@ __device__ __forceinline__ void block_qr_stair(QrStair<RMAX, NS, RT, CS>& z, int
 #pragma unroll
       for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
     }
-    const double st = __shfl(tot, j, 64);
+    const double st = lane_read(tot, j);
     const double xp = sm.piv[buf][j];
     double tau, beta, scale;
     qr_reflector_scalars(xp, st, &tau, &beta, &scale);

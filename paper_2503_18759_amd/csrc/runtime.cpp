@@ -17,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/cpqr.h"
@@ -44,6 +45,8 @@ struct cpqr_handle {
   std::string err;
   std::map<std::string, DevBuf> bufs;
   bool busy = false;                  // a session is using the workspace
+  // tuned K split of float32 TTMs by shape (L, I, S, R, precision)
+  std::map<std::tuple<int64_t, int, int64_t, int, int>, int> ttm_ks;
 };
 
 namespace {
@@ -124,6 +127,7 @@ struct Problem {
   int P = 0;              // TSQR leaves
   int64_t leaf_rows = 0;
   StairPlan stair{};      // staircase Z_n QR (ok == false: dense TSQR)
+  std::map<uint32_t, int> ttm_ks;    // TTM step (src | mode << 16) -> K split (0: default)
   int nchunks_max = 0;
   int Imax = 0;
   // device pointers
@@ -270,7 +274,66 @@ hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s, hipE
   if (p.f64)
     return launch_ttm_f64((const double*)a.in, (const double*)a.Q, (double*)a.out, a.L, a.I, a.S, a.R, s,
                           ev0, ev1);
-  return launch_ttm_f32(a.in, a.Q, a.out, a.L, a.I, a.S, a.R, p.prec == CPQR_PREC_BF16X3, s, ev0, ev1);
+  const auto k = p.ttm_ks.find(st.src | ((uint32_t)st.mode << 16));
+  return launch_ttm_f32(a.in, a.Q, a.out, a.L, a.I, a.S, a.R, p.prec == CPQR_PREC_BF16X3, s, ev0, ev1,
+                        k == p.ttm_ks.end() ? 0 : k->second);
+}
+
+// K split (waves per output tile) of every float32 TTM step of the schedule:
+// each shape is timed once per handle (one warm-up and three launches per
+// candidate, output redirected to scratch so that no cached intermediate is
+// touched) and the fastest split is kept.  The best split depends on the
+// shape and on the memory system, so it is measured rather than assumed.
+cpqr_status tune_ttm_steps(cpqr_handle* h, Problem& p, const std::vector<std::vector<Step>>& sched) {
+  if (p.f64) return CPQR_OK;
+  hipStream_t s = h->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  for (const auto& sw : sched)
+    for (const Step& st : sw) {
+      if (st.kind != STEP_TTM) continue;
+      const uint32_t key = st.src | ((uint32_t)st.mode << 16);
+      if (p.ttm_ks.count(key)) continue;
+      const TtmArgs a = ttm_step_args(p, st);
+      const auto shape = std::make_tuple(a.L, a.I, a.S, a.R, p.prec);
+      const auto known = h->ttm_ks.find(shape);
+      if (known != h->ttm_ks.end()) {
+        p.ttm_ks[key] = known->second;
+        continue;
+      }
+      const unsigned opts = ttm_ks_options(a.L, a.I, a.S, a.R);
+      int best = 0;
+      if (opts & (opts - 1)) {   // more than one candidate
+        float* out = nullptr;
+        WS(h, "tune:ttm_out", (size_t)(a.L * a.S * a.R) * 4 + 256, out);
+        if (!e0) {
+          HIP_TRY(h, hipEventCreate(&e0));
+          HIP_TRY(h, hipEventCreate(&e1));
+        }
+        float best_ms = 1e30f;
+        for (int b = 0; b < 3; ++b) {
+          if (!(opts & (1u << b))) continue;
+          const int ks = 1 << b;
+          const bool bf = p.prec == CPQR_PREC_BF16X3;
+          HIP_TRY(h, launch_ttm_f32(a.in, a.Q, out, a.L, a.I, a.S, a.R, bf, s, nullptr, nullptr, ks));
+          HIP_TRY(h, hipEventRecord(e0, s));
+          for (int r = 0; r < 3; ++r)
+            HIP_TRY(h, launch_ttm_f32(a.in, a.Q, out, a.L, a.I, a.S, a.R, bf, s, nullptr, nullptr, ks));
+          HIP_TRY(h, hipEventRecord(e1, s));
+          HIP_TRY(h, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = ks;
+          }
+        }
+      }
+      h->ttm_ks[shape] = best;
+      p.ttm_ks[key] = best;
+    }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return CPQR_OK;
 }
 
 // Arguments of the mode-n update of sweep k (Z QR, Y*Q0, finish).  Q0 of
@@ -614,6 +677,8 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
     return fail(h, CPQR_EINVAL, "||X|| = 0");
   }
   S.nx2 = hs.nx2;
+  stt = tune_ttm_steps(h, p, S.sched);
+  if (stt != CPQR_OK) return stt;
   if (o->beta_schedule && o->extrapolate == CPQR_EXTRAP_PAPER) {
     WS(h, prefix + "beta_sched", (size_t)o->iters * sizeof(double), p.beta_sched);
     HIP_TRY(h, hipMemcpy(p.beta_sched, o->beta_schedule, (size_t)o->iters * sizeof(double),

@@ -220,7 +220,7 @@ __device__ __forceinline__ void stage_q_runs(const float* __restrict__ Q, int I,
     for (int j = 0; j < 8; ++j) {
       const int e = e0 + j * TTM_THREADS;
       const int c = e / runs_per_col, k0 = 4 * (e - c * runs_per_col);
-      v[j] = (e < total && c < R && k0 < I) ? *reinterpret_cast<const f32x4*>(Q + k0 + (int64_t)I * c)
+      v[j] = (e < total && c < R && k0 < I) ? *reinterpret_cast<const gf32x4*>((const gfloat*)Q + k0 + (int64_t)I * c)
                                             : f32x4{0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
@@ -256,7 +256,7 @@ __device__ void stage_q_mc(float* sq, const float* __restrict__ Q, int I, int R,
       const int t4 = rest / NB;
       const int k = (t4 * 4 + tt) * 4 + (lane >> 4);
       const int c = nb * 16 + (lane & 15);
-      v[j] = (b0 + j < n && k < I && c < R) ? Q[k + (int64_t)I * c] : 0.0f;
+      v[j] = (b0 + j < n && k < I && c < R) ? ((const gfloat*)Q)[k + (int64_t)I * c] : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j)
@@ -323,6 +323,7 @@ __device__ __forceinline__ void mc_f32_mma(f32x4 (&acc)[4 * NB], const f32x4 (&a
 template <int NB, bool VEC>
 __device__ __forceinline__ void mc_store(const f32x4 (&acc)[4 * NB], float* __restrict__ out,
                                          int64_t m0, int64_t M, int64_t L, int R, int li, int g) {
+  gfloat* __restrict__ gout = (gfloat*)out;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int c = 16 * nb + li;
@@ -334,7 +335,7 @@ __device__ __forceinline__ void mc_store(const f32x4 (&acc)[4 * NB], float* __re
         if (m < M) {
           const int64_t s = m / L, l = m - s * L;
           f32x4 val = {acc[0 * NB + nb][jj], acc[1 * NB + nb][jj], acc[2 * NB + nb][jj], acc[3 * NB + nb][jj]};
-          *reinterpret_cast<f32x4*>(out + l + L * (int64_t)c + L * (int64_t)R * s) = val;
+          *reinterpret_cast<gf32x4*>(gout + l + L * (int64_t)c + L * (int64_t)R * s) = val;
         }
       } else {
 #pragma unroll
@@ -342,7 +343,7 @@ __device__ __forceinline__ void mc_store(const f32x4 (&acc)[4 * NB], float* __re
           const int64_t m = m0 + 16 * v + 4 * g + jj;
           if (m < M) {
             const int64_t s = m / L, l = m - s * L;
-            out[l + L * (int64_t)c + L * (int64_t)R * s] = acc[v * NB + nb][jj];
+            gout[l + L * (int64_t)c + L * (int64_t)R * s] = acc[v * NB + nb][jj];
           }
         }
       }
@@ -394,7 +395,7 @@ struct TtmMcF32 {
 template <int NB, bool VEC, bool BUF>
 TTM_KERNEL void ttm_mc_f32(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmArgs a = kernel_args(a0, batch, blockIdx.y);
   const TtmMcF32<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.L, a.I, a.S, a.R);
   ttm_drive(p, (a.L * a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
@@ -418,7 +419,7 @@ __device__ void stage_q_kc(float* sq, const float* __restrict__ Q, int I, int R,
       const int t = rest / NB;
       const int k = 32 * t + 16 * (v >> 2) + 4 * (lane >> 4) + (v & 3);
       const int c = nb * 16 + (lane & 15);
-      x[j] = (b0 + j < n && k < I && c < R) ? Q[k + (int64_t)I * c] : 0.0f;
+      x[j] = (b0 + j < n && k < I && c < R) ? ((const gfloat*)Q)[k + (int64_t)I * c] : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j)
@@ -484,6 +485,7 @@ __device__ __forceinline__ void kc_f32_mma(f32x4 (&acc)[4 * NB], const f32x4 (&x
 template <int NB>
 __device__ __forceinline__ void kc_store(const f32x4 (&acc)[4 * NB], float* __restrict__ out,
                                          int64_t s0, int64_t S, int R, int col, int g) {
+  gfloat* __restrict__ gout = (gfloat*)out;
   const bool vec_store = (R % 4) == 0 && (((uintptr_t)out) & 15) == 0;
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
@@ -494,11 +496,11 @@ __device__ __forceinline__ void kc_store(const f32x4 (&acc)[4 * NB], float* __re
       const int r0 = 16 * nb + 4 * g;
       if (r0 >= R) continue;
       if (vec_store) {
-        *reinterpret_cast<f32x4*>(out + r0 + (int64_t)R * s) = acc[b * NB + nb];
+        *reinterpret_cast<gf32x4*>(gout + r0 + (int64_t)R * s) = acc[b * NB + nb];
       } else {
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
-          if (r0 + jj < R) out[r0 + jj + (int64_t)R * s] = acc[b * NB + nb][jj];
+          if (r0 + jj < R) gout[r0 + jj + (int64_t)R * s] = acc[b * NB + nb][jj];
       }
     }
   }
@@ -546,7 +548,7 @@ struct TtmKcF32 {
 template <int NB, bool VEC, bool BUF>
 TTM_KERNEL void ttm_kc_f32(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmArgs a = kernel_args(a0, batch, blockIdx.y);
   const TtmKcF32<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.I, a.S, a.R);
   ttm_drive(p, (a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
@@ -577,7 +579,7 @@ __device__ void stage_q_bf16(bf16x8* sq, const float* __restrict__ Q, int I, int
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int k0 = KC ? 32 * t + 16 * h + 4 * (lane >> 4) : 32 * t + 8 * (lane >> 4) + 4 * h;
-          const f32x4 v = (ok && k0 < I) ? *reinterpret_cast<const f32x4*>(Q + k0 + (int64_t)I * c)
+          const f32x4 v = (ok && k0 < I) ? *reinterpret_cast<const gf32x4*>((const gfloat*)Q + k0 + (int64_t)I * c)
                                          : f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int j = 0; j < 4; ++j) x[u][4 * h + j] = v[j];
@@ -587,7 +589,7 @@ __device__ void stage_q_bf16(bf16x8* sq, const float* __restrict__ Q, int I, int
         for (int ee = 0; ee < 8; ++ee) {
           const int k = KC ? (32 * t + 16 * (ee >> 2) + 4 * (lane >> 4) + (ee & 3))
                            : (32 * t + 8 * (lane >> 4) + ee);
-          x[u][ee] = (ok && k < I) ? Q[k + (int64_t)I * c] : 0.0f;
+          x[u][ee] = (ok && k < I) ? ((const gfloat*)Q)[k + (int64_t)I * c] : 0.0f;
         }
       }
     }
@@ -692,7 +694,7 @@ struct TtmMcBf16 {
 template <int NB, bool VEC, bool BUF>
 TTM_KERNEL void ttm_mc_bf16x3(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmArgs a = kernel_args(a0, batch, blockIdx.y);
   const TtmMcBf16<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.L, a.I, a.S, a.R);
   ttm_drive(p, (a.L * a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
@@ -759,7 +761,7 @@ struct TtmKcBf16 {
 template <int NB, bool VEC, bool BUF>
 TTM_KERNEL void ttm_kc_bf16x3(TtmArgs a0, const TtmArgs* __restrict__ batch, int ks) {
   extern __shared__ float smem[];
-  const TtmArgs a = batch ? batch[blockIdx.y] : a0;
+  const TtmArgs a = kernel_args(a0, batch, blockIdx.y);
   const TtmKcBf16<NB, VEC, BUF> p(smem, a.in, a.Q, a.out, a.I, a.S, a.R);
   ttm_drive(p, (a.S + TTM_TILE - 1) / TTM_TILE, p.TC, ks, smem + (size_t)p.TC * 32 * 16 * NB);
 }
@@ -912,8 +914,22 @@ bool ttm_mfma_supported(int I, int R) {
   return ttm_q_lds(I, NB) <= 64 * 1024;
 }
 
+unsigned ttm_ks_options(int64_t L, int I, int64_t S, int R) {
+  if (!ttm_mfma_supported(I, R) || L * S == 0) return 0;
+  const int64_t rows = L == 1 ? S : L * S;
+  unsigned m = 0;
+  for (int b = 0; b < 3; ++b) {
+    int ks = 1 << b;
+    unsigned wgs;
+    size_t lds;
+    // every part of a split K range keeps at least two chunks of 32
+    if ((I + 31) / 32 >= 2 * ks && ttm_batch_shape(rows, I, R, &ks, &wgs, &lds)) m |= 1u << b;
+  }
+  return m;
+}
+
 hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L, int I, int64_t S,
-                          int R, bool bf16x3, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                          int R, bool bf16x3, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int ks_req) {
   if (L * S == 0) return hipSuccess;
   if (!ttm_mfma_supported(I, R)) {
     if (bf16x3) return hipErrorInvalidValue;
@@ -929,7 +945,13 @@ hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L
   const int NB = (R + 15) / 16;
   const int64_t rows = L == 1 ? S : L * S;
   const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
-  const int ks = ttm_pick_ks(tiles, I, NB);
+  int ks = ttm_pick_ks(tiles, I, NB);
+  if (ks_req == 1 || ks_req == 2 || ks_req == 4) {
+    int k = ks_req;
+    unsigned wgs;
+    size_t lds;
+    if (ttm_batch_shape(rows, I, R, &k, &wgs, &lds)) ks = ks_req;
+  }
   const bool buf = ttm_buf_legal(a);
   return launch_f32_any(NB, buf, L == 1, ttm_vec_ok(a), bf16x3, ttm_grid(tiles, ks),
                         ttm_q_lds(I, NB) + ttm_red_lds(ks, NB), st, a, nullptr, ks, ev0, ev1);

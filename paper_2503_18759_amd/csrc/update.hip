@@ -24,13 +24,14 @@ static constexpr int AP_KT = 32;
 
 template <typename TY, int RMAX>
 __global__ __launch_bounds__(AP_THREADS) void apply_partial(ApplyDev a0, const ApplyDev* __restrict__ batch) {
-  const ApplyDev a = batch ? batch[blockIdx.z] : a0;
-  const TY* __restrict__ Y = static_cast<const TY*>(a.Y);
+  const ApplyDev a = kernel_args(a0, batch, blockIdx.z);
+  typedef __attribute__((address_space(1))) TY gTY;
+  const gTY* __restrict__ Y = static_cast<const gTY*>((const gTY*)a.Y);
   const int64_t L = a.L, S = a.S, chunk = a.chunk;
   const int I = a.I, R = a.R;
-  const double* __restrict__ Q0 = a.Q0;
-  const double* __restrict__ Q0prev = a.Q0prev;
-  double* __restrict__ partial = a.partial;
+  const gdouble* __restrict__ Q0 = (const gdouble*)a.Q0;
+  const gdouble* __restrict__ Q0prev = (const gdouble*)a.Q0prev;
+  gdouble* __restrict__ partial = (gdouble*)a.partial;
   const DevState* __restrict__ st = a.state;
   if ((int)blockIdx.x * AP_ROWS >= I || (int)blockIdx.y >= a.nchunks) return;
   __shared__ double sY[AP_KT][AP_ROWS + 1];
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(AP_THREADS) void apply_partial(ApplyDev a0, const A
     __syncthreads();
   }
   if (i0 + i < I) {
-    double* out = partial + (int64_t)blockIdx.y * 2 * I * R;
+    gdouble* out = partial + (int64_t)blockIdx.y * 2 * I * R;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = rg + 4 * u;
@@ -95,11 +96,11 @@ __global__ __launch_bounds__(AP_THREADS) void apply_partial(ApplyDev a0, const A
 }
 
 __global__ void apply_reduce(ApplyDev a0, const ApplyDev* __restrict__ batch) {
-  const ApplyDev a = batch ? batch[blockIdx.y] : a0;
-  const double* __restrict__ partial = a.partial;
+  const ApplyDev a = kernel_args(a0, batch, blockIdx.y);
+  const gdouble* __restrict__ partial = (const gdouble*)a.partial;
   const int nchunks = a.nchunks;
   const int64_t n = 2 * (int64_t)a.I * a.R;
-  double* __restrict__ V = a.V;
+  gdouble* __restrict__ V = (gdouble*)a.V;
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
        o += (int64_t)gridDim.x * blockDim.x) {
     double s = 0.0;
@@ -176,7 +177,7 @@ __device__ inline double beta_from_fit(double fit) {
 
 template <int RMAX, int RPT>
 __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishArgs* __restrict__ batch) {
-  const FinishArgs f = batch ? batch[blockIdx.x] : f0;
+  const FinishArgs f = kernel_args(f0, batch, blockIdx.x);
   __shared__ QrSmem<RMAX> sm;
   __shared__ QrWySmem<RMAX> wy;
   __shared__ double sR0[RMAX][RMAX + 1];
@@ -186,9 +187,13 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   const int tid = threadIdx.x;
   const int I = f.I, R = f.R;
   DevState* st = f.state;
+  const gdouble* __restrict__ gV = (const gdouble*)f.V;
+  gdouble* __restrict__ gA = (gdouble*)f.A;
+  gdouble* __restrict__ gq64 = (gdouble*)f.q64;
+  gfloat* __restrict__ gq32 = (gfloat*)f.q32;
   for (int e = tid; e < RMAX * RMAX; e += NT) {
     const int i = e / RMAX, c = e % RMAX;
-    sR0[i][c] = (i < R && c < R) ? f.R0[i + R * c] : 0.0;
+    sR0[i][c] = (i < R && c < R) ? ((const gdouble*)f.R0)[i + R * c] : 0.0;
   }
   const bool active = (f.extrap != 0) && st->active;
   const double beta = active ? st->beta : 0.0;
@@ -208,8 +213,8 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
     for (int c = 0; c < RMAX; ++c) {
       double vp = 0.0, vq = 0.0;
       if (row < I && c < R) {
-        vp = f.V[row + (int64_t)I * c];
-        vq = f.V[(int64_t)I * R + row + (int64_t)I * c];
+        vp = gV[row + (int64_t)I * c];
+        vq = gV[(int64_t)I * R + row + (int64_t)I * c];
       }
       vu[c] = active ? fma(cq, vq, cp * vp) : vp;
       sc[0] = fma(vp, vu[c], sc[0]);
@@ -264,7 +269,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
     if (__any(col && lam == 0.0)) bad |= FLAG_RANKDEF;
     if (__any(col && !isfinite(lam))) bad |= FLAG_NONFINITE;
     inv_l = (col && lam != 0.0) ? 1.0 / lam : 0.0;
-    if (tid < R) f.lambda[tid] = lam;
+    if (tid < R) ((gdouble*)f.lambda)[tid] = lam;
   }
 #pragma unroll
   for (int c = 0; c < RMAX; ++c) {
@@ -273,7 +278,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
     for (int p = 0; p < RPT; ++p) {
       const int row = tid + NT * p;
       a[p].set(c, a[p].get(c) * ic);
-      if (row < I && c < R) f.A[row + (int64_t)I * c] = a[p].get(c);
+      if (row < I && c < R) gA[row + (int64_t)I * c] = a[p].get(c);
     }
   }
   block_qr<RMAX, RPT>(a, R, sm);
@@ -281,15 +286,15 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
   for (int e = tid; e < R * R; e += NT) {
     const int i = e % R, c = e / R;
-    f.Rn[e] = wy.Rm[i][c];
+    ((gdouble*)f.Rn)[e] = wy.Rm[i][c];
   }
 #pragma unroll
   for (int p = 0; p < RPT; ++p) {
     const int row = tid + NT * p;
     if (row < I)
       block_qr_q_row<RMAX>(a[p], row, R, sm, wy, [&](int c, double val) {
-        if (f.q64) f.q64[row + (int64_t)I * c] = val;
-        if (f.q32) f.q32[row + (int64_t)I * c] = (float)val;
+        if (gq64) gq64[row + (int64_t)I * c] = val;
+        if (gq32) gq32[row + (int64_t)I * c] = (float)val;
       });
   }
   if (tid == 0) {
