@@ -213,37 +213,39 @@ __global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(FormArgs a0, const Fo
 // h = K-1 down to 0, then by the digits below h (base m+1, lowest fastest)
 // and above h (base m).  Positions below (c+1)^K are exactly the tuples with
 // every digit <= c, the profile of column c of Z_n.
-__device__ __forceinline__ int64_t ipow_d(int64_t b, int e) {
-  int64_t p = 1;
+__device__ __forceinline__ int ipow_i(int b, int e) {
+  int p = 1;
   for (int k = 0; k < e; ++k) p *= b;
   return p;
 }
 
+// 32-bit arithmetic throughout (Z_n of this kernel has at most 1024 rows);
+// the shell index comes from a float estimate of s^(1/K), corrected exactly.
 template <int KMAX>
-__device__ __forceinline__ void stair_digits(int64_t s, int K, int (&d)[KMAX]) {
-  int m = (int)floor(pow((double)s, 1.0 / (double)K));
-  while (ipow_d(m + 1, K) <= s) ++m;
-  while (m > 0 && ipow_d(m, K) > s) --m;
-  int64_t o = s - ipow_d(m, K);
+__device__ __forceinline__ void stair_digits(int s, int K, int (&d)[KMAX]) {
+  int m = (int)__builtin_exp2f(__builtin_log2f((float)s + 0.5f) / (float)K);
+  while (ipow_i(m + 1, K) <= s) ++m;
+  while (m > 0 && ipow_i(m, K) > s) --m;
+  int o = s - ipow_i(m, K);
   int h = K - 1;
-  int64_t lo = 1;
+  int lo = 1;
   for (; h >= 0; --h) {
-    lo = ipow_d(m + 1, h);
-    const int64_t cnt = lo * ipow_d(m, K - 1 - h);
+    lo = ipow_i(m + 1, h);
+    const int cnt = lo * ipow_i(m, K - 1 - h);
     if (o < cnt) break;
     o -= cnt;
   }
-  int64_t l = o % lo, u = o / lo;
+  int l = o % lo, u = o / lo;
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     int dk = 0;
     if (k < h) {
-      dk = (int)(l % (m + 1));
+      dk = l % (m + 1);
       l /= (m + 1);
     } else if (k == h) {
       dk = m;
     } else if (k < K) {
-      dk = (int)(u % m);
+      dk = u % m;
       u /= m;
     }
     d[k] = dk;
@@ -285,7 +287,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
     int d[KMAX];
     const int64_t s0 = tid;
     if (s0 < M) {
-      stair_digits<KMAX>(s0, K, d);
+      stair_digits<KMAX>((int)s0, K, d);
       int64_t kr = 0, w = 1;
 #pragma unroll
       for (int k = 0; k < KMAX; ++k)
@@ -311,7 +313,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
     for (int q = 0; q < NS; ++q) {
       const int64_t sq = (int64_t)NT * (q + 1) + tid;
       if (sq < M) {
-        stair_digits<KMAX>(sq, K, d);
+        stair_digits<KMAX>((int)sq, K, d);
         int64_t kr = 0, w = 1;
 #pragma unroll
         for (int k = 0; k < KMAX; ++k)

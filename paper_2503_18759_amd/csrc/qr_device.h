@@ -135,22 +135,31 @@ __device__ __forceinline__ void qr_reflector_scalars(double x0, double st, doubl
   *scale = neg ? -rd : rd;
 }
 
-// T (upper triangular) of the compact WY form, row by row from the U
-// entries collected during the factorisation: T[k][k] = tau_k and
-// T[k][j] = -tau_j sum_{m=k}^{j-1} T[k][m] U[m][j] for j > k.
+// T (upper triangular) of the compact WY form from the U entries collected
+// during the factorisation: T[k][k] = tau_k and
+// T[k][j] = -tau_j sum_{m=k}^{j-1} T[k][m] U[m][j] for j > k.  Lane k owns
+// row k in registers; the loops are unrolled so that the U reads (the same
+// address for every lane) are issued ahead of the arithmetic, and the term
+// of the newest entry T[k][j-1] is added last to keep the dependent chain
+// at one multiply-add per column.
 template <int RMAX>
 __device__ __forceinline__ void block_qr_build_t(int R, QrSmem<RMAX>& sm) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < RMAX * (RMAX + 1); e += QrCfg<RMAX>::NT) (&sm.T[0][0])[e] = 0.0;
-  __syncthreads();
-  if (tid < R) {
+  if (tid < RMAX) {
     const int k = tid;
-    sm.T[k][k] = sm.tau[k];
-    for (int j = k + 1; j < R; ++j) {
+    double t[RMAX];
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
       double acc = 0.0;
-      for (int m = k; m < j; ++m) acc = fma(sm.T[k][m], sm.U[m][j], acc);
-      sm.T[k][j] = -sm.tau[j] * acc;
+#pragma unroll
+      for (int m = 0; m + 1 < j; ++m) acc = fma(t[m], sm.U[m][j], acc);
+      if (j > 0) acc = fma(t[j - 1], sm.U[j - 1][j], acc);
+      // entries left of the diagonal are zero; columns j >= R are padding
+      // (their U entries are never written, so they are selected away)
+      t[j] = (j < k || j >= R) ? 0.0 : ((j == k) ? sm.tau[j] : -sm.tau[j] * acc);
     }
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) sm.T[k][j] = t[j];
   }
   __syncthreads();
 }
@@ -428,44 +437,64 @@ __device__ __forceinline__ void block_qr_publish(const QrRow<RMAX>& row0, int R,
 }
 
 // wy.M = T * (V1^T * B) where B (R x R) is row-major in LDS with leading
-// dimension ldb, or B = I when B == nullptr.
+// dimension ldb, or B = I when B == nullptr.  The inner products run over
+// the full (zero-padded) RMAX range, unrolled, so that their LDS reads are
+// issued together rather than one loop trip at a time.
 template <int RMAX>
 __device__ __forceinline__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWySmem<RMAX>& wy, int R,
                                                     const double* B, int ldb) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
-    const int k = e / RMAX, c = e % RMAX;
-    double acc = 0.0;
-    if (k < R && c < R) {
-      if (B == nullptr) {
-        acc = wy.V1[c][k];
-      } else {
-        for (int i = k; i < R; ++i) acc = fma(wy.V1[i][k], B[i * ldb + c], acc);
-      }
+  if (B != nullptr) {
+    // W = V1^T B (V1 is zero above its unit diagonal and beyond R)
+    for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
+      const int k = e / RMAX, c = e % RMAX;
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < RMAX; ++i) acc = fma(wy.V1[i][k], (c < R) ? B[i * ldb + (c < R ? c : 0)] : 0.0, acc);
+      wy.W[k][c] = acc;
     }
-    wy.W[k][c] = acc;
+  } else {
+    for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
+      const int k = e / RMAX, c = e % RMAX;
+      wy.W[k][c] = wy.V1[c][k];
+    }
   }
   __syncthreads();
+  // M = T W (T is zero below its diagonal and beyond R)
   for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
     const int k = e / RMAX, c = e % RMAX;
-    double acc = 0.0;
-    for (int m = k; m < R; ++m) acc = fma(sm.T[k][m], wy.W[m][c], acc);
-    wy.M[k][c] = acc;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < RMAX; m += 2) {
+      a0 = fma(sm.T[k][m], wy.W[m][c], a0);
+      a1 = fma(sm.T[k][m + 1], wy.W[m + 1][c], a1);
+    }
+    wy.M[k][c] = (k < R && c < R) ? a0 + a1 : 0.0;
   }
   __syncthreads();
 }
 
 // Row `row` of the explicit Q = (E - V M) * diag(sgn) with M = T V1^T, from
 // the row's reflector entries v[m] = V[row][OFF + m] (zero outside
-// [OFF, OFF + W)): store(c, value) for c < R; run-time loop over c.
+// [OFF, OFF + W)): store(c, value) for c < R.  Two columns per trip and two
+// partial sums per column keep four independent multiply-add chains, and
+// the two M entries of a trip are adjacent in LDS.
 template <int RMAX, int W, int OFF, typename Store>
 __device__ __forceinline__ void wy_q_row(const double (&v)[W], int64_t row, int R, const QrSmem<RMAX>& sm,
                                          const QrWySmem<RMAX>& wy, Store&& store) {
-  for (int c = 0; c < R; ++c) {
-    double acc = (row == c) ? 1.0 : 0.0;
+  static_assert(W % 2 == 0 && RMAX % 2 == 0, "pairs of rows and columns");
+  for (int c = 0; c < R; c += 2) {
+    // c + 1 <= RMAX - 1 (R <= RMAX, RMAX even); M is zero in columns >= R
+    double a0 = (row == c) ? 1.0 : 0.0, a1 = (row == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll
-    for (int m = 0; m < W; ++m) acc = fma(-v[m], wy.M[OFF + m][c], acc);
-    store(c, acc * sm.sgn[c]);
+    for (int m = 0; m < W; m += 2) {
+      a0 = fma(-v[m], wy.M[OFF + m][c], a0);
+      a1 = fma(-v[m], wy.M[OFF + m][c + 1], a1);
+      b0 = fma(-v[m + 1], wy.M[OFF + m + 1][c], b0);
+      b1 = fma(-v[m + 1], wy.M[OFF + m + 1][c + 1], b1);
+    }
+    store(c, (a0 + b0) * sm.sgn[c]);
+    if (c + 1 < R) store(c + 1, (a1 + b1) * sm.sgn[c + 1]);
   }
 }
 

@@ -23,7 +23,7 @@ static constexpr int AP_ROWS = 64;
 static constexpr int AP_KT = 32;
 
 template <typename TY, int RMAX>
-__global__ __launch_bounds__(AP_THREADS) void apply_partial(ApplyDev a0, const ApplyDev* __restrict__ batch) {
+__global__ __launch_bounds__(AP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 2))) void apply_partial(ApplyDev a0, const ApplyDev* __restrict__ batch) {
   const ApplyDev a = kernel_args(a0, batch, blockIdx.z);
   typedef __attribute__((address_space(1))) TY gTY;
   const gTY* __restrict__ Y = static_cast<const gTY*>((const gTY*)a.Y);
@@ -43,7 +43,11 @@ __global__ __launch_bounds__(AP_THREADS) void apply_partial(ApplyDev a0, const A
   const int64_t k0 = (int64_t)blockIdx.y * chunk;
   int64_t k1 = k0 + chunk;
   if (k1 > M) k1 = M;
-  const bool use_prev = (Q0prev != nullptr) && st->active;
+  // Q0prev is read whenever it is given; its product is used by the finish
+  // kernel only while the extrapolation is active (a select, so whatever the
+  // product holds before then is never mixed in)
+  const bool use_prev = (Q0prev != nullptr);
+  (void)st;
   const int i = tid & 63, rg = tid >> 6;
   constexpr int U = RMAX / 4;
   double ap[U], aq[U];
@@ -58,7 +62,8 @@ __global__ __launch_bounds__(AP_THREADS) void apply_partial(ApplyDev a0, const A
       const int64_t k = kt + kk;
       double y = 0.0;
       if (i0 + ii < I && k < k1) {
-        const int64_t s = k / L, l = k - s * L;
+        // k < M = L S < 2^31 (the Kolda column index): 32-bit division
+        const int s = (int)k / (int)L, l = (int)k - s * (int)L;
         y = (double)Y[l + L * (int64_t)(i0 + ii) + LI * s];
       }
       sY[kk][ii] = y;
@@ -103,8 +108,16 @@ __global__ void apply_reduce(ApplyDev a0, const ApplyDev* __restrict__ batch) {
   gdouble* __restrict__ V = (gdouble*)a.V;
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
        o += (int64_t)gridDim.x * blockDim.x) {
+    // chunks summed in a fixed order; four at a time so that their loads
+    // are in flight together
     double s = 0.0;
-    for (int c = 0; c < nchunks; ++c) s += partial[(int64_t)c * n + o];
+    int c = 0;
+    for (; c + 4 <= nchunks; c += 4) {
+      const double p0 = partial[(int64_t)c * n + o], p1 = partial[(int64_t)(c + 1) * n + o];
+      const double p2 = partial[(int64_t)(c + 2) * n + o], p3 = partial[(int64_t)(c + 3) * n + o];
+      s = (((s + p0) + p1) + p2) + p3;
+    }
+    for (; c < nchunks; ++c) s += partial[(int64_t)c * n + o];
     V[o] = s;
   }
 }
