@@ -150,10 +150,13 @@ __device__ __forceinline__ void block_qr_build_t(int R, QrSmem<RMAX>& sm) {
     double t[RMAX];
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
+      double u[RMAX];
+#pragma unroll
+      for (int m = 0; m < j; ++m) u[m] = sm.U[m][j];
       double acc = 0.0;
 #pragma unroll
-      for (int m = 0; m + 1 < j; ++m) acc = fma(t[m], sm.U[m][j], acc);
-      if (j > 0) acc = fma(t[j - 1], sm.U[j - 1][j], acc);
+      for (int m = 0; m + 1 < j; ++m) acc = fma(t[m], u[m], acc);
+      if (j > 0) acc = fma(t[j - 1], u[j - 1], acc);
       // entries left of the diagonal are zero; columns j >= R are padding
       // (their U entries are never written, so they are selected away)
       t[j] = (j < k || j >= R) ? 0.0 : ((j == k) ? sm.tau[j] : -sm.tau[j] * acc);
@@ -463,11 +466,16 @@ __device__ __forceinline__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWy
   // M = T W (T is zero below its diagonal and beyond R)
   for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
     const int k = e / RMAX, c = e % RMAX;
+    double tk[RMAX], wc[RMAX];
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m) tk[m] = sm.T[k][m];
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m) wc[m] = wy.W[m][c];
     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
     for (int m = 0; m < RMAX; m += 2) {
-      a0 = fma(sm.T[k][m], wy.W[m][c], a0);
-      a1 = fma(sm.T[k][m + 1], wy.W[m + 1][c], a1);
+      a0 = fma(tk[m], wc[m], a0);
+      a1 = fma(tk[m + 1], wc[m + 1], a1);
     }
     wy.M[k][c] = (k < R && c < R) ? a0 + a1 : 0.0;
   }
@@ -485,13 +493,19 @@ __device__ __forceinline__ void wy_q_row(const double (&v)[W], int64_t row, int 
   static_assert(W % 2 == 0 && RMAX % 2 == 0, "pairs of rows and columns");
   for (int c = 0; c < R; c += 2) {
     // c + 1 <= RMAX - 1 (R <= RMAX, RMAX even); M is zero in columns >= R
+    double m0[W], m1[W];
+#pragma unroll
+    for (int m = 0; m < W; ++m) {
+      m0[m] = wy.M[OFF + m][c];
+      m1[m] = wy.M[OFF + m][c + 1];
+    }
     double a0 = (row == c) ? 1.0 : 0.0, a1 = (row == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll
     for (int m = 0; m < W; m += 2) {
-      a0 = fma(-v[m], wy.M[OFF + m][c], a0);
-      a1 = fma(-v[m], wy.M[OFF + m][c + 1], a1);
-      b0 = fma(-v[m + 1], wy.M[OFF + m + 1][c], b0);
-      b1 = fma(-v[m + 1], wy.M[OFF + m + 1][c + 1], b1);
+      a0 = fma(-v[m], m0[m], a0);
+      a1 = fma(-v[m], m1[m], a1);
+      b0 = fma(-v[m + 1], m0[m + 1], b0);
+      b1 = fma(-v[m + 1], m1[m + 1], b1);
     }
     store(c, (a0 + b0) * sm.sgn[c]);
     if (c + 1 < R) store(c + 1, (a1 + b1) * sm.sgn[c + 1]);
