@@ -198,7 +198,7 @@ __global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(FormArgs a0, const Fo
     if (m < R) {
       const double v = V[row + ldv * m];
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) q[c] = fma(-v, wy.M[m][c], q[c]);
+      for (int c = 0; c < RMAX; ++c) q[c] = fma(-v, wy.Mt[c][m], q[c]);
     }
   }
 #pragma unroll
@@ -274,11 +274,27 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
     QrWySmem<RMAX> wy;
   } u;
   const int tid = threadIdx.x;
-  for (int e = tid; e < K * RMAX * RMAX; e += NT) {
-    const int q = e / (RMAX * RMAX), rem = e % (RMAX * RMAX);
-    const int i = rem % RMAX, c = rem / RMAX;
-    const int mode = (q < n) ? q : q + 1;
-    u.srf[e] = (i < R && c < R) ? ((const gdouble*)args.rf)[(int64_t)mode * R * R + i + (int64_t)R * c] : 0.0;
+  {
+    // R factors of the other modes, zero-padded to RMAX x RMAX; a fixed trip
+    // count with clamped indices so that all loads are in flight together
+    constexpr int TRIPS = (KMAX * RMAX * RMAX + NT - 1) / NT;
+    const gdouble* __restrict__ rf = (const gdouble*)args.rf;
+    double val[TRIPS];
+#pragma unroll
+    for (int t = 0; t < TRIPS; ++t) {
+      const int e = tid + NT * t;
+      const int q = e / (RMAX * RMAX), rem = e % (RMAX * RMAX);
+      const int i = rem % RMAX, c = rem / RMAX;
+      const int mode = (q < n) ? q : q + 1;
+      const bool in = (e < K * RMAX * RMAX) && i < R && c < R;
+      const double x = rf[in ? (int64_t)mode * R * R + i + (int64_t)R * c : 0];
+      val[t] = in ? x : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < TRIPS; ++t) {
+      const int e = tid + NT * t;
+      if (e < K * RMAX * RMAX) u.srf[e] = val[t];
+    }
   }
   __syncthreads();
   QrStair<RMAX, NS, RT, CS> z;

@@ -92,7 +92,7 @@ struct QrWySmem {
   double V1[RMAX][RMAX + 1];   // first R rows of V (unit lower triangular)
   double Rm[RMAX][RMAX + 1];   // R factor (after the sign fix when requested)
   double W[RMAX][RMAX + 1];    // scratch R x R product
-  double M[RMAX][RMAX + 1];    // T V1^T B
+  double Mt[RMAX][RMAX + 2];   // (T V1^T B)^T: row c holds column c (16-byte aligned rows)
 };
 
 // Reflector scalars from q = x0^2 + st (st = squared norm below the pivot):
@@ -439,7 +439,7 @@ __device__ __forceinline__ void block_qr_publish(const QrRow<RMAX>& row0, int R,
   __syncthreads();
 }
 
-// wy.M = T * (V1^T * B) where B (R x R) is row-major in LDS with leading
+// wy.Mt = (T * (V1^T * B))^T where B (R x R) is row-major in LDS with leading
 // dimension ldb, or B = I when B == nullptr.  The inner products run over
 // the full (zero-padded) RMAX range, unrolled, so that their LDS reads are
 // issued together rather than one loop trip at a time.
@@ -477,7 +477,7 @@ __device__ __forceinline__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWy
       a0 = fma(tk[m], wc[m], a0);
       a1 = fma(tk[m + 1], wc[m + 1], a1);
     }
-    wy.M[k][c] = (k < R && c < R) ? a0 + a1 : 0.0;
+    wy.Mt[c][k] = (k < R && c < R) ? a0 + a1 : 0.0;
   }
   __syncthreads();
 }
@@ -496,8 +496,8 @@ __device__ __forceinline__ void wy_q_row(const double (&v)[W], int64_t row, int 
     double m0[W], m1[W];
 #pragma unroll
     for (int m = 0; m < W; ++m) {
-      m0[m] = wy.M[OFF + m][c];
-      m1[m] = wy.M[OFF + m][c + 1];
+      m0[m] = wy.Mt[c][OFF + m];
+      m1[m] = wy.Mt[c + 1][OFF + m];
     }
     double a0 = (row == c) ? 1.0 : 0.0, a1 = (row == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll

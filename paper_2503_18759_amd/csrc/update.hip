@@ -222,16 +222,28 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   for (int p = 0; p < RPT; ++p) {
     const int row = tid + NT * p;
     double vu[RMAX];
+    // groups of eight columns: branch-free loads (index 0 outside the
+    // matrix, selected away) so that a group's loads are in flight together
 #pragma unroll
-    for (int c = 0; c < RMAX; ++c) {
-      double vp = 0.0, vq = 0.0;
-      if (row < I && c < R) {
-        vp = gV[row + (int64_t)I * c];
-        vq = gV[(int64_t)I * R + row + (int64_t)I * c];
+    for (int c0 = 0; c0 < RMAX; c0 += 8) {
+      double lp[8], lq[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u;
+        const int64_t e = (row < I && c < R) ? row + (int64_t)I * c : 0;
+        lp[u] = gV[e];
+        lq[u] = gV[(int64_t)I * R + e];
       }
-      vu[c] = active ? fma(cq, vq, cp * vp) : vp;
-      sc[0] = fma(vp, vu[c], sc[0]);
-      sc[1] = fma(vu[c], vu[c], sc[1]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u;
+        const bool in = row < I && c < R;
+        const double vp = in ? lp[u] : 0.0, vq = in ? lq[u] : 0.0;
+        vu[c] = active ? fma(cq, vq, cp * vp) : vp;
+        sc[0] = fma(vp, vu[c], sc[0]);
+        sc[1] = fma(vu[c], vu[c], sc[1]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     // back substitution of R0 ahat = vu (row of Ahat R0^T = Vu)
     static_for<0, RMAX>([&](auto ic) {
