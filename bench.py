@@ -140,6 +140,40 @@ def time_to_fit_study(max_sweeps: int = 200):
             "variants": out}
 
 
+def orders_4_5_study(steps: int, warmup: int):
+    """Sweeps/s of the order-4 (96^4, rank 20) and order-5 (40^5, rank 16)
+    workloads: ``warmup`` untimed sweeps, then ``steps`` sweeps replayed from
+    the per-sweep graphs between two synchronisations (restructured tree,
+    float32 TTMs, no extrapolation)."""
+    import torch
+
+    import paper_2503_18759_amd as P
+    import synthgen as G
+
+    out = {}
+    for name in ("fp32_96pow4_r20", "fp32_40pow5_r16"):
+        prob = G.workload(name)
+        x, dims = P.to_device(prob.X)
+        sess = P.Session(x, prob.rank, prob.init, warmup + steps, dims=dims, tree="restructured")
+        sess.sweeps(warmup)
+        sess.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sess.sweeps(steps)
+        sess.sync()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        fit = float(sess.result()["fit"])
+        sess.close()
+        del x
+        out[name] = {"dims": dims, "rank": prob.rank, "sweeps_per_s": steps / sec,
+                     "ms_per_sweep": sec / steps * 1e3, "fit_after": fit}
+        print(json.dumps({"workload": name, **out[name]}), file=sys.stderr, flush=True)
+    return {"study": "orders_4_5", "steps": steps, "warmup": warmup,
+            "timing": "graph replay of the timed sweeps, synchronised on both sides",
+            "workloads": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,7 +183,7 @@ def main():
     ap.add_argument("--tree", default="restructured", choices=["none", "standard", "restructured"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--study", choices=["time-to-fit"], default=None,
+    ap.add_argument("--study", choices=["time-to-fit", "orders-4-5"], default=None,
                     help="run a study instead of the benchmark (prints its own JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-MiB device buffer once (a plain copy "
@@ -172,6 +206,9 @@ def main():
     P.load_library()
     if args.study == "time-to-fit":
         print(json.dumps(time_to_fit_study()), flush=True)
+        return
+    if args.study == "orders-4-5":
+        print(json.dumps(orders_4_5_study(args.steps, args.warmup)), flush=True)
         return
     prob = G.workload(WORKLOAD)
     x, dims = P.to_device(prob.X)

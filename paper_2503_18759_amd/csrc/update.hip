@@ -22,6 +22,20 @@ static constexpr int AP_THREADS = 256;
 static constexpr int AP_ROWS = 64;
 static constexpr int AP_KT = 32;
 
+// Largest digit of the Kolda column index k of Y_(n) (base R, K digits).
+// Column c of Q0 is zero at every row whose largest digit exceeds c (the
+// staircase of Z_n; Section 3.2), so a tile's leading columns below the
+// smallest such digit are zero and need not be read.
+__device__ __forceinline__ int kolda_max_digit(int k, int R, int K) {
+  int m = 0;
+  for (int t = 0; t < K; ++t) {
+    const int d = k % R;
+    m = d > m ? d : m;
+    k /= R;
+  }
+  return m;
+}
+
 template <typename TY, int RMAX>
 __global__ __launch_bounds__(AP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 2))) void apply_partial(ApplyDev a0, const ApplyDev* __restrict__ batch) {
   const ApplyDev a = kernel_args(a0, batch, blockIdx.z);
@@ -32,93 +46,172 @@ __global__ __launch_bounds__(AP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 2
   const gdouble* __restrict__ Q0 = (const gdouble*)a.Q0;
   const gdouble* __restrict__ Q0prev = (const gdouble*)a.Q0prev;
   gdouble* __restrict__ partial = (gdouble*)a.partial;
-  const DevState* __restrict__ st = a.state;
   if ((int)blockIdx.x * AP_ROWS >= I || (int)blockIdx.y >= a.nchunks) return;
-  __shared__ double sY[AP_KT][AP_ROWS + 1];
-  __shared__ double sQ[AP_KT][RMAX];
-  __shared__ double sP[AP_KT][RMAX];
+  // rows padded by two so that each thread's pair of rows is one 16-byte read
+  __shared__ __attribute__((aligned(16))) double sY[AP_KT][AP_ROWS + 2];
+  __shared__ __attribute__((aligned(16))) double sQ[AP_KT][RMAX];
+  __shared__ __attribute__((aligned(16))) double sP[AP_KT][RMAX];
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * AP_ROWS;
   const int64_t M = L * S;
   const int64_t k0 = (int64_t)blockIdx.y * chunk;
   int64_t k1 = k0 + chunk;
   if (k1 > M) k1 = M;
+  // digits of the Kolda index: M = R^K
+  int K = 0;
+  for (int64_t m = M; m > 1; m /= R) ++K;
   // Q0prev is read whenever it is given; its product is used by the finish
   // kernel only while the extrapolation is active (a select, so whatever the
   // product holds before then is never mixed in)
   const bool use_prev = (Q0prev != nullptr);
-  (void)st;
-  const int i = tid & 63, rg = tid >> 6;
-  constexpr int U = RMAX / 4;
-  double ap[U], aq[U];
+  // Register tile: rows 2 ti and 2 ti + 1, columns cg CW .. cg CW + CW - 1
+  // of both Q0 and Q0prev.  A wave holds two column groups, i.e. the
+  // contiguous columns [2 w CW, 2 (w + 1) CW).
+  constexpr int CW = RMAX / 8;
+  const int ti = tid & 31, cg = tid >> 5, w = tid >> 6, lane = tid & 63;
+  constexpr int NY = AP_ROWS * AP_KT / AP_THREADS;   // Y elements per thread and tile
+  constexpr int NQ = AP_KT * RMAX / AP_THREADS;      // Q0 (and Q0prev) elements per thread and tile
+  double ap[2][CW], aq[2][CW];
 #pragma unroll
-  for (int u = 0; u < U; ++u) ap[u] = aq[u] = 0.0;
+  for (int m = 0; m < CW; ++m) ap[0][m] = ap[1][m] = aq[0][m] = aq[1][m] = 0.0;
   const int64_t LI = L * (int64_t)I;
-  for (int64_t kt = k0; kt < k1; kt += AP_KT) {
-    for (int e = tid; e < AP_ROWS * AP_KT; e += AP_THREADS) {
+  // The tiles of the chunk are software-pipelined: the global loads of the
+  // next tile are issued into registers before the current tile is used.
+  double ry[NY], rq[NQ], rp[NQ];
+  int cnext = 0;   // staircase bound of the tile held in ry/rq/rp
+  auto load_tile = [&](int64_t kt) __attribute__((always_inline)) {
+    // smallest largest-digit over the tile's columns (wave-wide minimum)
+    const int64_t kl = kt + (lane & (AP_KT - 1));
+    int md = (kl < k1) ? kolda_max_digit((int)kl, R, K) : RMAX;
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) {
+      const int o = __shfl_xor(md, m, 64);
+      md = o < md ? o : md;
+    }
+    const int cmin = __builtin_amdgcn_readfirstlane(md);
+    cnext = cmin;
+#pragma unroll
+    for (int t = 0; t < NY; ++t) {
+      const int e = tid + AP_THREADS * t;
       int ii, kk;
       if (L == 1) { ii = e & 63; kk = e >> 6; }
       else        { kk = e % AP_KT; ii = e / AP_KT; }
       const int64_t k = kt + kk;
-      double y = 0.0;
-      if (i0 + ii < I && k < k1) {
-        // k < M = L S < 2^31 (the Kolda column index): 32-bit division
-        const int s = (int)k / (int)L, l = (int)k - s * (int)L;
-        y = (double)Y[l + L * (int64_t)(i0 + ii) + LI * s];
-      }
-      sY[kk][ii] = y;
+      const bool in = (i0 + ii < I && k < k1);
+      // k < M = L S < 2^31 (the Kolda column index): 32-bit division
+      const int s = (int)k / (int)L, l = (int)k - s * (int)L;
+      const TY v = Y[in ? l + L * (int64_t)(i0 + ii) + LI * s : 0];
+      ry[t] = in ? (double)v : 0.0;
     }
-    for (int e = tid; e < AP_KT * RMAX; e += AP_THREADS) {
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      const int e = tid + AP_THREADS * t;
       const int kk = e % AP_KT, c = e / AP_KT;
       const int64_t k = kt + kk;
-      const bool in = (k < k1) && (c < R);
-      sQ[kk][c] = in ? Q0[k + M * c] : 0.0;
-      sP[kk][c] = (in && use_prev) ? Q0prev[k + M * c] : 0.0;
+      const bool in = (k < k1) && (c < R) && (c >= cmin);
+      const int64_t idx = in ? k + M * c : 0;
+      const double q = Q0[idx];
+      const double pq = use_prev ? Q0prev[idx] : 0.0;
+      rq[t] = in ? q : 0.0;
+      rp[t] = (in && use_prev) ? pq : 0.0;
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < AP_KT; ++kk) {
-      const double y = sY[kk][i];
+  };
+  if (k0 < k1) load_tile(k0);
+  for (int64_t kt = k0; kt < k1; kt += AP_KT) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        ap[u] = fma(y, sQ[kk][rg + 4 * u], ap[u]);
-        aq[u] = fma(y, sP[kk][rg + 4 * u], aq[u]);
+    for (int t = 0; t < NY; ++t) {
+      const int e = tid + AP_THREADS * t;
+      int ii, kk;
+      if (L == 1) { ii = e & 63; kk = e >> 6; }
+      else        { kk = e % AP_KT; ii = e / AP_KT; }
+      sY[kk][ii] = ry[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+      const int e = tid + AP_THREADS * t;
+      const int kk = e % AP_KT, c = e / AP_KT;
+      sQ[kk][c] = rq[t];
+      sP[kk][c] = rp[t];
+    }
+    const int ccur = cnext;
+    __syncthreads();
+    if (kt + AP_KT < k1) load_tile(kt + AP_KT);
+    // every column of this wave below the tile's staircase bound: its
+    // products are exact zeros and are skipped (wave-uniform branch)
+    if (2 * (w + 1) * CW > ccur) {
+#pragma unroll 4
+      for (int kk = 0; kk < AP_KT; ++kk) {
+        const double y0 = sY[kk][2 * ti], y1 = sY[kk][2 * ti + 1];
+        double q[CW], p[CW];
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+          q[m] = sQ[kk][cg * CW + m];
+          p[m] = sP[kk][cg * CW + m];
+        }
+#pragma unroll
+        for (int m = 0; m < CW; ++m) {
+          ap[0][m] = fma(y0, q[m], ap[0][m]);
+          ap[1][m] = fma(y1, q[m], ap[1][m]);
+          aq[0][m] = fma(y0, p[m], aq[0][m]);
+          aq[1][m] = fma(y1, p[m], aq[1][m]);
+        }
       }
     }
     __syncthreads();
   }
-  if (i0 + i < I) {
-    gdouble* out = partial + (int64_t)blockIdx.y * 2 * I * R;
+  gdouble* out = partial + (int64_t)blockIdx.y * 2 * I * R;
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = rg + 4 * u;
+  for (int r = 0; r < 2; ++r) {
+    const int row = i0 + 2 * ti + r;
+    if (row >= I) continue;
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+      const int c = cg * CW + m;
       if (c < R) {
-        out[(i0 + i) + (int64_t)I * c] = ap[u];
-        out[(int64_t)I * R + (i0 + i) + (int64_t)I * c] = aq[u];
+        out[row + (int64_t)I * c] = ap[r][m];
+        out[(int64_t)I * R + row + (int64_t)I * c] = aq[r][m];
       }
     }
   }
 }
 
-__global__ void apply_reduce(ApplyDev a0, const ApplyDev* __restrict__ batch) {
+// Waves per reduction workgroup: each wave sums a fixed, strided subset of
+// the chunks for 64 consecutive outputs and the subsets are then added in
+// wave order, so the result does not depend on scheduling.
+static constexpr int AR_WAVES = 16;
+
+__global__ __launch_bounds__(64 * AR_WAVES) void apply_reduce(ApplyDev a0, const ApplyDev* __restrict__ batch) {
   const ApplyDev a = kernel_args(a0, batch, blockIdx.y);
   const gdouble* __restrict__ partial = (const gdouble*)a.partial;
   const int nchunks = a.nchunks;
   const int64_t n = 2 * (int64_t)a.I * a.R;
   gdouble* __restrict__ V = (gdouble*)a.V;
-  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
-       o += (int64_t)gridDim.x * blockDim.x) {
-    // chunks summed in a fixed order; four at a time so that their loads
-    // are in flight together
+  __shared__ double sp[AR_WAVES][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t ob = (int64_t)blockIdx.x * 64; ob < n; ob += (int64_t)gridDim.x * 64) {
+    const int64_t o = ob + lane;
     double s = 0.0;
-    int c = 0;
-    for (; c + 4 <= nchunks; c += 4) {
-      const double p0 = partial[(int64_t)c * n + o], p1 = partial[(int64_t)(c + 1) * n + o];
-      const double p2 = partial[(int64_t)(c + 2) * n + o], p3 = partial[(int64_t)(c + 3) * n + o];
-      s = (((s + p0) + p1) + p2) + p3;
+    if (o < n) {
+      // chunks w, w + AR_WAVES, ... in increasing order, four loads in flight
+      int c = w;
+      for (; c + 3 * AR_WAVES < nchunks; c += 4 * AR_WAVES) {
+        const double p0 = partial[(int64_t)c * n + o];
+        const double p1 = partial[(int64_t)(c + AR_WAVES) * n + o];
+        const double p2 = partial[(int64_t)(c + 2 * AR_WAVES) * n + o];
+        const double p3 = partial[(int64_t)(c + 3 * AR_WAVES) * n + o];
+        s = (((s + p0) + p1) + p2) + p3;
+      }
+      for (; c < nchunks; c += AR_WAVES) s += partial[(int64_t)c * n + o];
     }
-    for (; c < nchunks; ++c) s += partial[(int64_t)c * n + o];
-    V[o] = s;
+    sp[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && o < n) {
+      double t = sp[0][lane];
+#pragma unroll
+      for (int q = 1; q < AR_WAVES; ++q) t += sp[q][lane];
+      V[o] = t;
+    }
+    __syncthreads();
   }
 }
 
@@ -153,7 +246,7 @@ static hipError_t apply_launch(int rm, bool y_f64, dim3 grid, dim3 rgrid, const 
   else if (rm == 32) { CPQR_APPLY(32) }
   else return hipErrorInvalidValue;
 #undef CPQR_APPLY
-  hipLaunchKernelGGL(apply_reduce, rgrid, dim3(256), 0, st, a, batch);
+  hipLaunchKernelGGL(apply_reduce, rgrid, dim3(64 * AR_WAVES), 0, st, a, batch);
   return hipGetLastError();
 }
 
@@ -161,8 +254,8 @@ unsigned apply_iblocks(int I) { return (unsigned)((I + AP_ROWS - 1) / AP_ROWS); 
 
 unsigned apply_reduce_blocks(int I, int R) {
   const int64_t n = 2 * (int64_t)I * R;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 1024) blocks = 1024;
+  int64_t blocks = (n + 63) / 64;
+  if (blocks > 4096) blocks = 4096;
   return (unsigned)blocks;
 }
 
