@@ -124,23 +124,24 @@ def khatri_rao(mats: Sequence[np.ndarray]) -> np.ndarray:
 # Section 2.4: compact QR (Householder) and triangular solve
 # ---------------------------------------------------------------------------
 def householder_qr(A: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
-    """Compact QR A = Q R of an M x R matrix (M >= R) by Householder
-    reflections, returning an explicit Q (M x R, orthonormal columns) and an
-    upper-triangular R with a non-negative diagonal.
+    """Compact QR A = Q R of an M x R matrix by Householder reflections, with
+    k = min(M, R): an explicit Q (M x k, orthonormal columns) and an upper
+    trapezoidal R (k x R) with a non-negative diagonal.  For M >= R this is
+    the thin QR of Section 2.4; a wide factor matrix (a mode smaller than the
+    rank) gets k = M reflectors.
 
     Reflector for column j: x = A[j:, j]; if x[1:] == 0 the reflector is the
     identity; otherwise beta = -sign(x0) ||x||, v = x / (x0 - beta) with
     v[0] = 1 and tau = (beta - x0) / beta.  Q is formed by applying the
-    reflectors in reverse order to the first R columns of the identity.  The
+    reflectors in reverse order to the first k columns of the identity.  The
     signs are fixed at the end so that diag(R) >= 0.
     """
     A = np.array(A, dtype=F64, copy=True)
     M, R = A.shape
-    if M < R:
-        raise ValueError("householder_qr needs at least as many rows as columns")
+    k = min(M, R)
     vs: List[np.ndarray] = []
     taus: List[float] = []
-    for j in range(R):
+    for j in range(k):
         x = A[j:, j].copy()
         sigma = float(np.dot(x[1:], x[1:]))
         if sigma == 0.0:
@@ -162,10 +163,10 @@ def householder_qr(A: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
         A[j + 1:, j] = 0.0
         vs.append(v)
         taus.append(tau)
-    Rm = np.triu(A[:R, :])
-    Q = np.zeros((M, R), dtype=F64)
-    Q[:R, :R] = np.eye(R)
-    for j in reversed(range(R)):
+    Rm = np.triu(A[:k, :])
+    Q = np.zeros((M, k), dtype=F64)
+    Q[:k, :k] = np.eye(k)
+    for j in reversed(range(k)):
         if taus[j] != 0.0:
             v = vs[j]
             w = v @ Q[j:, :]
@@ -277,6 +278,10 @@ def mode_update(Yn: np.ndarray, Rfs: Sequence[np.ndarray], n: int,
     """
     N = len(Rfs)
     Z = khatri_rao([Rfs[i] for i in reversed(range(N)) if i != n])
+    if Z.shape[0] < Z.shape[1]:
+        # fewer Khatri-Rao rows than the rank: P^(n) cannot have full column
+        # rank and the subproblem (6) has no unique solution
+        raise ValueError("Z_n has fewer rows than columns")
     Q0, R0 = householder_qr(Z)
     Vp = Yn @ Q0
     if Q0prev is not None and beta != 0.0:

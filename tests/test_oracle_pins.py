@@ -95,17 +95,23 @@ def test_multi_ttm_unfolding_identity_eq3(N):
 
 
 # ---------------------------------------------------------------- Section 2.4
-@pytest.mark.parametrize("shape", [(7, 3), (40, 5), (64, 16), (5, 5), (130, 33)])
+@pytest.mark.parametrize("shape", [(7, 3), (40, 5), (64, 16), (5, 5), (130, 33),
+                                   (3, 5), (1, 4), (6, 13), (2, 2)])
 def test_householder_matches_library_qr(shape):
+    """Thin QR for tall matrices; for wide ones (a mode smaller than the
+    rank) the compact Q is square and R upper trapezoidal, as numpy's
+    reduced QR."""
     A = rng(sum(shape)).standard_normal(shape)
     Q, R = O.householder_qr(A)
-    Ql, Rl = np.linalg.qr(A)
+    k = min(shape)
+    assert Q.shape == (shape[0], k) and R.shape == (k, shape[1])
+    Ql, Rl = np.linalg.qr(A, mode="reduced")
     s = np.sign(np.diag(Rl))
     Ql, Rl = Ql * s, s[:, None] * Rl
     assert np.all(np.diag(R) >= 0)
     assert np.allclose(Q, Ql, atol=1e-12)
     assert np.allclose(R, Rl, atol=1e-12)
-    assert np.linalg.norm(Q.T @ Q - np.eye(shape[1])) < 1e-13
+    assert np.linalg.norm(Q.T @ Q - np.eye(k)) < 1e-13
     assert np.allclose(Q @ R, A, atol=1e-12)
     assert np.array_equal(R, np.triu(R))
 
@@ -267,6 +273,55 @@ def test_extrapolation_activation_rule():
     assert res["beta"] == O.beta_from_fit(f[k - 1])
 
 
+@pytest.mark.parametrize("dims,R", [((3, 6, 7), 4), ((2, 5, 3, 4), 3), ((4, 3, 9), 5)])
+def test_mode_update_least_squares_with_a_mode_below_the_rank(dims, R):
+    """A mode smaller than the rank: its compact QR has min(I, R) columns, Z_n
+    has prod_k min(I_k, R) rows, and the update is still the least-squares
+    minimiser of eq. (6) whenever P^(n) has full column rank."""
+    r = rng(33 + len(dims))
+    N = len(dims)
+    X = r.standard_normal(dims)
+    A, Qs, Rs = _state(N, dims, R, seed=34 + N)
+    assert any(q.shape[1] < R for q in Qs)
+    for n in range(N):
+        P = O.khatri_rao([A[k] for k in reversed(range(N)) if k != n])
+        if np.prod([min(d, R) for k, d in enumerate(dims) if k != n]) < R:
+            Yn = O.unfold(O.multi_ttm_except(X, Qs, n), n)
+            with pytest.raises(ValueError):
+                O.mode_update(Yn, Rs, n, None, 0.0, 0.1)
+            continue
+        Yn = O.unfold(O.multi_ttm_except(X, Qs, n), n)
+        assert Yn.shape == (dims[n], int(np.prod([min(d, R) for k, d in enumerate(dims) if k != n])))
+        An, lam, Q0, R0, Vp, Vu = O.mode_update(Yn, Rs, n, None, 0.0, 0.1)
+        sol = np.linalg.lstsq(P, O.unfold(X, n).T, rcond=None)[0].T
+        assert np.allclose(An * lam, sol, atol=1e-10)
+
+
+def test_zero_padding_a_small_mode_leaves_the_update_unchanged():
+    """Padding the compact Q_m (I x min(I,R)) with zero columns to I x R and
+    R_m with zero rows to R x R gives Y_(n) and Z_n extra zero columns/rows;
+    the QR of Z_n has the same R0 (unique with a positive diagonal), Q0 is
+    zero on the extra rows, and Y_(n) Q0 is unchanged."""
+    dims, R = (3, 6, 7), 5
+    r = rng(36)
+    X = r.standard_normal(dims)
+    A, Qs, Rs = _state(3, dims, R, seed=37)
+    Qp = [np.hstack([q, np.zeros((q.shape[0], R - q.shape[1]))]) for q in Qs]
+    Rp = [np.vstack([rr, np.zeros((R - rr.shape[0], R))]) for rr in Rs]
+    for n in range(3):
+        Yn = O.unfold(O.multi_ttm_except(X, Qs, n), n)
+        Ypn = O.unfold(O.multi_ttm_except(X, Qp, n), n)
+        a1, l1, Q0, R0, Vp1, _ = O.mode_update(Yn, Rs, n, None, 0.0, 0.1)
+        a2, l2, Q0p, R0p, Vp2, _ = O.mode_update(Ypn, Rp, n, None, 0.0, 0.1)
+        assert np.allclose(R0, R0p, atol=1e-12)
+        assert np.allclose(Vp1, Vp2, atol=1e-12)
+        assert np.allclose(a1, a2, atol=1e-11) and np.allclose(l1, l2, rtol=1e-12)
+        Zp = O.khatri_rao([Rp[k] for k in reversed(range(3)) if k != n])
+        zero_rows = np.all(Zp == 0.0, axis=1)
+        assert zero_rows.any() == (n != 0)
+        assert np.abs(Q0p[zero_rows]).max(initial=0.0) < 1e-14
+
+
 # ------------------------------------------------------- whole-method pins
 def test_planted_noiseless_recovery():
     p = G.make_problem([12, 13, 14], 3, seed=50, rho=0.0)
@@ -278,6 +333,18 @@ def test_planted_noiseless_recovery():
         assert np.all(C.max(axis=1) > 1 - 1e-8)
     for q in res["Q"]:
         assert np.linalg.norm(q.T @ q - np.eye(3)) < 1e-13
+
+
+def test_planted_noiseless_recovery_with_a_mode_below_the_rank():
+    """Rank 4 planted in 3 x 12 x 13 (generic factors: Kruskal's condition
+    3 + 4 + 4 >= 2*4 + 2 holds, so the decomposition is unique)."""
+    p = G.make_problem([3, 12, 13], 4, seed=53, rho=0.0)
+    res = O.cp_als_qr(p.X, 4, p.init, iters=400)
+    assert 1.0 - res["fitx"] < 1e-10
+    assert res["Q"][0].shape == (3, 3) and res["R"][0].shape == (3, 4)
+    for n in range(3):
+        C = np.abs(res["factors"][n].T @ (p.truth[n] / np.linalg.norm(p.truth[n], axis=0)))
+        assert np.all(C.max(axis=1) > 1 - 1e-7)
 
 
 def test_noisy_fit_matches_first_order_closed_form():
