@@ -154,8 +154,13 @@ typedef struct {
  * tolerance, tree, extrapolation, precision, initial factors).  Outputs
  * (host, caller-owned): factor matrices with unit-norm columns, lambda, the
  * per-sweep fit history and update orders, and the final fit.
- * Limits of this build: 1 <= R <= 32; R <= I_n <= 512 for every mode
- * (I_n < R returns CPQR_EUNSUPPORTED); Z_n (R^(N-1) x R) must fit a
+ * A mode may be smaller than the rank: its factor gets the compact QR with
+ * min(I_n, R) reflectors (Q_n is I_n x I_n, R_n upper trapezoidal), held on
+ * the device zero-padded to I_n x R and R x R.  Every Z_n then has
+ * prod_{k != n} min(I_k, R) nonzero rows, which must be at least R
+ * (otherwise P^(n) cannot have full column rank: CPQR_EUNSUPPORTED).
+ * Limits of this build: 1 <= R <= 32; I_n <= 512 for every mode; Z_n
+ * (R^(N-1) x R, including the zero rows of padded modes) must fit a
  * two-level TSQR: ceil(R^(N-1) / B) * R <= B with B = 2048, 1024, 512 rows
  * for R <= 8, 16, 32 (for example 40^5 at R = 16 and 256^3 at R = 32 fit).
  * On a runtime error (CPQR_ERANKDEF, CPQR_ENONFINITE, CPQR_EHIP) the outputs

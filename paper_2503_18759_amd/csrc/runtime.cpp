@@ -440,8 +440,17 @@ cpqr_status check_args(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpq
     if (!o->init_factors[k]) return fail(h, CPQR_EINVAL, "null init factor %d", k);
   }
   if (rank > 32) return fail(h, CPQR_EUNSUPPORTED, "rank > 32 is not supported by this build");
+  // A mode smaller than the rank keeps min(I_k, R) nonzero rows of R_k, so
+  // Z_n has prod_{k != n} min(I_k, R) nonzero rows; fewer than R means P^(n)
+  // is rank-deficient and the least-squares update is not unique.
+  for (int n = 0; n < N; ++n) {
+    int64_t rows = 1;
+    for (int k = 0; k < N; ++k)
+      if (k != n) rows = std::min<int64_t>(rows * std::min<int64_t>(X->dims[k], rank), (int64_t)rank);
+    if (rows < rank)
+      return fail(h, CPQR_EUNSUPPORTED, "mode %d: the other modes give prod min(I_k, R) < rank %d rows of Z_n", n, rank);
+  }
   for (int k = 0; k < N; ++k) {
-    if (X->dims[k] < rank) return fail(h, CPQR_EUNSUPPORTED, "mode %d has size %lld < rank %d", k, (long long)X->dims[k], rank);
     if (X->dims[k] > CPQR_MAX_FACTOR_ROWS)
       return fail(h, CPQR_EUNSUPPORTED, "mode size > %d is not supported by this build", CPQR_MAX_FACTOR_ROWS);
   }

@@ -417,7 +417,9 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   }
   if (tid == 0) {
     if (!isfinite(sc[0]) || !isfinite(sc[1])) bad |= FLAG_NONFINITE;
-    for (int c = 0; c < R; ++c)
+    // a mode smaller than the rank has min(I, R) reflectors; the padded
+    // rows of R_n (c >= I) are zero by construction
+    for (int c = 0; c < R && c < I; ++c)
       if (!(wy.Rm[c][c] > 0.0)) bad |= FLAG_RANKDEF;
     if (bad) atomicOr(&st->flags, bad);
     st->vpvu = sc[0];

@@ -80,7 +80,10 @@ def test_schedule_rejects_bad_arguments():
     (dict(dims=[40, 40, 40], rank=5, dtype="f64", prec="fp64"), C.OK),
     (dict(dims=[256, 256, 256], rank=32), C.OK),
     (dict(dims=[40] * 5, rank=16), C.OK),
-    (dict(dims=[40, 40, 4], rank=5), C.EUNSUPPORTED),          # I_n < R
+    (dict(dims=[40, 40, 4], rank=5), C.OK),                    # I_n < R: compact factor QR
+    (dict(dims=[3, 40, 2, 30], rank=8), C.OK),                 # two modes below the rank
+    (dict(dims=[2, 2, 40], rank=5), C.EUNSUPPORTED),           # Z_3 has 2*2 < 5 nonzero rows
+    (dict(dims=[1, 40], rank=2, tree="none"), C.EUNSUPPORTED),  # order 2: Z_2 = R_1 has 1 row
     (dict(dims=[40, 40, 40], rank=33), C.EUNSUPPORTED),        # rank above this build's limit
     (dict(dims=[600, 40, 40], rank=5), C.EUNSUPPORTED),        # mode above the single-block QR limit
     (dict(dims=[40] * 5, rank=32), C.EUNSUPPORTED),            # R^(N-1) beyond two-level TSQR

@@ -101,6 +101,34 @@ def test_fp64_staircase_zqr_order3(P, dims, R, seed):
         assert np.max(np.abs(a - b)) <= 1e-10
 
 
+@pytest.mark.parametrize("zqr", ["stair", "dense"])
+@pytest.mark.parametrize("dims,R,seed", [([3, 30, 28], 5, 71), ([40, 40, 4], 8, 74),
+                                         ([2, 17, 3, 19], 6, 72), ([4, 9, 3, 8, 5], 4, 73)])
+def test_fp64_modes_below_the_rank(P, dims, R, seed, zqr):
+    """Modes smaller than the rank (compact factor QR with min(I, R)
+    reflectors, zero-padded on the device) against the oracle's compact
+    formulation, restructured tree with the paper's extrapolation."""
+    prob = G.make_problem(dims, R, seed=seed, rho=1e-2, dtype=np.float64)
+    g, o = _run(P, prob, 10, prec="fp64", tree="restructured", extrap="paper", zqr=zqr)
+    assert g["orders"] == o["orders"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+    assert np.max(np.abs(g["lam"] - o["lam"]) / o["lam"]) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("dims,R,seed", [([3, 64, 48], 16, 75), ([12, 70, 3, 40], 12, 76)])
+def test_fp32_modes_below_the_rank(P, dims, R, seed, prec):
+    prob = G.make_problem(dims, R, seed=seed, rho=1e-2, dtype=np.float32)
+    g, o = _run(P, prob, 10, prec=prec, tree="restructured")
+    if prec == "fp32":
+        _check_fp32(g, o)
+    else:
+        assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-4
+
+
 def test_fp64_fixed_beta_extrapolation(P):
     """eq. (19) with beta fixed from sweep 2 on: the GPU applies Qhat0 through
     Y_(n) Qhat0 = (1+beta) Y_(n) Q0 - alpha beta Y_(n) Q0prev."""
@@ -180,7 +208,7 @@ def test_tolerance_stop(P):
     assert abs(f[-1] - f[-2]) < 1e-9
 
 
-@pytest.mark.parametrize("mode", ["nan", "zero", "zero_column", "small_mode"])
+@pytest.mark.parametrize("mode", ["nan", "zero", "zero_column", "small_modes"])
 def test_error_paths(P, mode):
     import torch
     prob = G.make_problem([12, 10, 9], 3, seed=30, rho=0.01, dtype=np.float32)
@@ -199,8 +227,10 @@ def test_error_paths(P, mode):
         init[1][:, 2] = 0.0
         expect = P.cpqr.ERANKDEF
     else:
-        X = X[:, :, :2].copy()
-        init[2] = init[2][:2]
+        # two modes of size 1: Z_3 = R_2 (.) R_1 has 1 < 3 nonzero rows
+        X = X[:1, :1, :].copy()
+        init[0] = init[0][:1]
+        init[1] = init[1][:1]
         expect = P.cpqr.EUNSUPPORTED
     x, dims = P.to_device(X)
     with pytest.raises(P.CpqrError) as ei:

@@ -81,6 +81,17 @@ def test_batched_paper_extrapolation_vs_oracle(P):
         assert g["beta_sweep"] == o["beta_sweep"] and g["beta"] == o["beta"]
 
 
+def test_batched_modes_below_the_rank_vs_oracle(P):
+    """Problems with a mode smaller than the rank (compact factor QR) in one
+    batch with ordinary ones."""
+    probs = [G.make_problem([3, 30, 26], 6, seed=24, rho=0.01, dtype=np.float32),
+             G.make_problem([28, 5, 4], 12, seed=25, rho=0.01, dtype=np.float32),
+             G.make_problem([24, 28, 20], 11, seed=23, congruence=0.5, rho=0.03, dtype=np.float32)]
+    res = _run(P, probs, 10)
+    for g, p in zip(res, probs):
+        _check(g, p, 10)
+
+
 def test_batched_bf16x3(P):
     probs = _mixed_batch()[:4]
     res = _run(P, probs, 8, prec="bf16x3")

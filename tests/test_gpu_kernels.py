@@ -52,6 +52,8 @@ TTM_SHAPES = [
     ((33, 20, 70), 2, 5), ((20, 33, 70), 2, 33), ((12, 13, 14, 15), 2, 7),
     ((8, 16, 24, 4), 1, 12), ((7, 9, 8, 6, 10), 3, 4), ((100, 3, 50), 0, 64),
     ((1, 40, 1), 1, 1),
+    # contracted mode smaller than the rank (zero-padded Q of a small mode)
+    ((40, 3, 30), 1, 16), ((3, 50, 20), 0, 8), ((20, 30, 2), 2, 12),
 ]
 
 

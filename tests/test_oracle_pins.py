@@ -371,3 +371,24 @@ def test_generator_congruence_and_noise_level():
     ratio = np.linalg.norm((p.X - X0).ravel()) / np.linalg.norm(X0.ravel())
     assert abs(ratio - 0.01) < 1e-14
     assert abs(G.rho_from_l1(50.0) - 1.0) < 1e-15
+
+
+def test_generator_second_noise_term_and_per_mode_congruence():
+    """Section 4.3: the second noise term is rho2 ||X'|| relative to the
+    tensor after the first; each mode has its own congruence (Table 8)."""
+    r = np.random.default_rng(54)
+    B = G.congruent_factors(r, [40, 50, 30], 6, [0.5, 0.09, 0.9])
+    for b, c in zip(B, [0.5, 0.09, 0.9]):
+        assert np.allclose(b.T @ b, (1 - c) * np.eye(6) + c, atol=1e-14)
+    with pytest.raises(ValueError):
+        G.congruent_factors(r, [4, 50], 6, 0.5)
+    dims, R = [11, 9, 10], 3
+    p1 = G.make_problem(dims, R, seed=55, rho=0.05, congruence=[0.5, 0.09, 0.09])
+    p2 = G.make_problem(dims, R, seed=55, rho=0.05, rho2=0.2, congruence=[0.5, 0.09, 0.09])
+    # same draws up to the first noise term; the second is 0.2 of ||X'||
+    ratio = np.linalg.norm((p2.X - p1.X).ravel()) / np.linalg.norm(p1.X.ravel())
+    assert abs(ratio - 0.2) < 1e-14
+    # l2 in percent maps like l1: 0.1 % -> 1 / sqrt(999)
+    assert abs(G.rho_from_l1(0.1) - 1 / math.sqrt(999.0)) < 1e-16
+    t = G.table8_problem(10, dims=[24, 22, 21, 20], dtype=np.float64)
+    assert t.rank == 10 and t.meta["true_rank"] == 20 and t.X.shape == (24, 22, 21, 20)
