@@ -159,7 +159,12 @@ typedef struct {
  * the device zero-padded to I_n x R and R x R.  Every Z_n then has
  * prod_{k != n} min(I_k, R) nonzero rows, which must be at least R
  * (otherwise P^(n) cannot have full column rank: CPQR_EUNSUPPORTED).
- * Limits of this build: 1 <= R <= 32; I_n <= 512 for every mode; Z_n
+ * A mode of more than 512 rows has its factor QR done by the two-level
+ * TSQR (solve and normalisation stream the rows through one workgroup);
+ * its size must fit that TSQR: I_n <= 8192 at R <= 32, 65536 at R <= 16,
+ * 524288 at R <= 8 (CPQR_EUNSUPPORTED otherwise; the batched entry point
+ * keeps I_n <= 512).
+ * Limits of this build: 1 <= R <= 32; Z_n
  * (R^(N-1) x R, including the zero rows of padded modes) must fit a
  * two-level TSQR: ceil(R^(N-1) / B) * R <= B with B = 2048, 1024, 512 rows
  * for R <= 8, 16, 32 (for example 40^5 at R = 16 and 256^3 at R = 32 fit).

@@ -222,6 +222,13 @@ hipError_t launch_finish(const FinishArgs& f, hipStream_t st);
 // One workgroup per problem; every problem of the batch has rank class rmax
 // and factor rows-per-thread rpt.
 hipError_t launch_finish_batched(int count, int rmax, int rpt, const FinishArgs* args, hipStream_t st);
+// A factor with more than CPQR_MAX_FACTOR_ROWS rows: solve, lambda, A and the
+// fit in one streaming workgroup (f.Rn, f.q64, f.q32 unused); the factor QR is
+// then launch_tsqr on A (explicit source) followed by the tail, which writes
+// the float32 Q_n from the float64 one (q32 may be null) and checks R_n.
+hipError_t launch_finish_tall(const FinishArgs& f, hipStream_t st);
+hipError_t launch_tall_factor_tail(int I, int R, const double* q64, float* q32, const double* Rn,
+                                   DevState* state, hipStream_t st);
 
 // --- norms ----------------------------------------------------------------
 // partial sums of squares into `part` (nblocks doubles); returns nblocks

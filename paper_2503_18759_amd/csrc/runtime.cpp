@@ -137,6 +137,9 @@ struct Problem {
   double* lambda = nullptr;
   std::vector<double*> q0buf;  // per mode: 2 x M x R (ping-pong)
   double *tV = nullptr, *tT = nullptr, *tStack = nullptr, *tQtop = nullptr, *R0 = nullptr;
+  // factor TSQR of modes with more than CPQR_MAX_FACTOR_ROWS rows (sized for
+  // the largest such mode; fQ holds Q_n in float64 for the float32 chain)
+  double *fV = nullptr, *fT = nullptr, *fStack = nullptr, *fQtop = nullptr, *fQ = nullptr;
   double *partial = nullptr, *Vbuf = nullptr;
   DevState* state = nullptr;
   double* fit_hist = nullptr;
@@ -215,6 +218,23 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   WS(h, p.prefix + "tsqrS", (size_t)p.P * R * R * 8, p.tStack);
   WS(h, p.prefix + "tsqrQ", (size_t)p.P * R * R * 8, p.tQtop);
   WS(h, p.prefix + "R0", (size_t)R * R * 8, p.R0);
+  if (p.Imax > CPQR_MAX_FACTOR_ROWS) {
+    // a smaller mode can take more, shorter leaves than a larger one, so the
+    // buffers take the maximum over every tall mode's plan
+    int64_t vrows = 0, pmax = 0;
+    for (int k = 0; k < N; ++k) {
+      if (p.dims[k] <= CPQR_MAX_FACTOR_ROWS) continue;
+      const TsqrPlan fp = tsqr_plan(p.dims[k], R);
+      if (!fp.ok) return fail(h, CPQR_EUNSUPPORTED, "no TSQR plan for a %lld x %d factor", (long long)p.dims[k], R);
+      vrows = std::max<int64_t>(vrows, (int64_t)fp.P * fp.leaf_rows);
+      pmax = std::max<int64_t>(pmax, fp.P);
+    }
+    WS(h, p.prefix + "ftsqrV", (size_t)vrows * R * 8, p.fV);
+    WS(h, p.prefix + "ftsqrT", (size_t)pmax * R * R * 8, p.fT);
+    WS(h, p.prefix + "ftsqrS", (size_t)pmax * R * R * 8, p.fStack);
+    WS(h, p.prefix + "ftsqrQ", (size_t)pmax * R * R * 8, p.fQtop);
+    if (!p.f64) WS(h, p.prefix + "ftsqrQ64", (size_t)p.Imax * R * 8, p.fQ);
+  }
   int nch = 1;
   for (int k = 0; k < N; ++k) {
     const int c = apply_num_chunks(p.M, (int)p.dims[k]);
@@ -390,6 +410,35 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   f->sched_len = p.sched_len;
 }
 
+// Factor QR of a mode with more than CPQR_MAX_FACTOR_ROWS rows: two-level
+// TSQR of A_n (explicit source), then the float32 Q_n and the R_n check
+// (state == nullptr: no check, for the initial factors).
+hipError_t launch_tall_factor_qr(const Problem& p, int n, DevState* state, hipStream_t s) {
+  const int R = p.R;
+  const int I = (int)p.dims[n];
+  const TsqrPlan fp = tsqr_plan(I, R);
+  if (!fp.ok) return hipErrorInvalidValue;
+  double* Rn = p.rf + (size_t)n * R * R;
+  double* q64 = p.f64 ? (double*)p.Q[n] : p.fQ;
+  TsqrArgs t{};
+  t.N = 0;
+  t.n = 0;
+  t.R = R;
+  t.rf = nullptr;
+  t.src = p.A[n];
+  t.M = I;
+  t.P = fp.P;
+  t.V = p.fV;
+  t.T = p.fT;
+  t.stack = p.fStack;
+  t.R0 = Rn;
+  t.Qtop = p.fQtop;
+  t.Q0 = q64;
+  hipError_t e = launch_tsqr(t, s);
+  if (e != hipSuccess) return e;
+  return launch_tall_factor_tail(I, R, q64, p.f64 ? nullptr : (float*)p.Q[n], Rn, state, s);
+}
+
 StairArgs stair_args(const TsqrArgs& t) {
   return StairArgs{t.N, t.n, t.R, t.M, t.rf, t.R0, t.Q0, 1};
 }
@@ -404,7 +453,10 @@ hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const 
   if (e != hipSuccess) return e;
   e = launch_apply(a, s);
   if (e != hipSuccess) return e;
-  return launch_finish(f, s);
+  if (p.dims[n] <= CPQR_MAX_FACTOR_ROWS) return launch_finish(f, s);
+  e = launch_finish_tall(f, s);
+  if (e != hipSuccess) return e;
+  return launch_tall_factor_qr(p, n, p.state, s);
 }
 
 std::string sweep_key(const std::vector<Step>& sw, int parity, bool extrap) {
@@ -451,8 +503,11 @@ cpqr_status check_args(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpq
       return fail(h, CPQR_EUNSUPPORTED, "mode %d: the other modes give prod min(I_k, R) < rank %d rows of Z_n", n, rank);
   }
   for (int k = 0; k < N; ++k) {
-    if (X->dims[k] > CPQR_MAX_FACTOR_ROWS)
-      return fail(h, CPQR_EUNSUPPORTED, "mode size > %d is not supported by this build", CPQR_MAX_FACTOR_ROWS);
+    // modes above the single-workgroup factor QR go through the two-level
+    // TSQR, which bounds their size
+    if (X->dims[k] > CPQR_MAX_FACTOR_ROWS && (X->dims[k] > INT32_MAX || !tsqr_plan(X->dims[k], rank).ok))
+      return fail(h, CPQR_EUNSUPPORTED, "mode %d of size %lld is beyond the two-level factor TSQR at rank %d", k,
+                  (long long)X->dims[k], rank);
   }
   if (N > qr_max_order(rank) || !tsqr_plan(ipow(rank, N - 1), rank).ok)
     return fail(h, CPQR_EUNSUPPORTED, "R^(N-1) too large for a two-level TSQR at this rank");
@@ -675,8 +730,11 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   for (int k = 0; k < N; ++k) {
     HIP_TRY(h, hipMemcpyAsync(p.A[k], o->init_factors[k], (size_t)p.dims[k] * rank * 8,
                               hipMemcpyHostToDevice, s));
-    HIP_TRY(h, launch_factor_qr((int)p.dims[k], rank, p.A[k], p.rf + (size_t)k * rank * rank,
-                                p.f64 ? (double*)p.Q[k] : nullptr, p.f64 ? nullptr : (float*)p.Q[k], s));
+    if (p.dims[k] > CPQR_MAX_FACTOR_ROWS)
+      HIP_TRY(h, launch_tall_factor_qr(p, k, nullptr, s));
+    else
+      HIP_TRY(h, launch_factor_qr((int)p.dims[k], rank, p.A[k], p.rf + (size_t)k * rank * rank,
+                                  p.f64 ? (double*)p.Q[k] : nullptr, p.f64 ? nullptr : (float*)p.Q[k], s));
   }
   DevState hs;
   HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -1386,6 +1444,10 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
     if (o.tol != 0.0) return fail(h, CPQR_EINVAL, "batched runs a fixed number of sweeps: tol must be 0");
   }
   if (o0.prec == CPQR_PREC_FP64) return fail(h, CPQR_EUNSUPPORTED, "batched: FP32 or BF16X3 TTMs only");
+  for (int t = 0; t < count; ++t)
+    for (int k = 0; k < Xs[t].order; ++k)
+      if (Xs[t].dims[k] > CPQR_MAX_FACTOR_ROWS)
+        return fail(h, CPQR_EUNSUPPORTED, "batched problem %d: mode size > %d", t, CPQR_MAX_FACTOR_ROWS);
   if (o0.extrapolate == CPQR_EXTRAP_LEARNED)
     return fail(h, CPQR_EUNSUPPORTED, "batched: learned extrapolation is not supported");
   HIP_TRY(h, hipSetDevice(h->device));

@@ -281,6 +281,45 @@ __device__ inline double beta_from_fit(double fit) {
   return 1.0 / 250.0;
 }
 
+// Thread-0 tail of a mode update: store <Vp,Vu> and ||Vu||^2 and, after the
+// sweep's last update, the fit of Section 4.1 and the extrapolation
+// activation rule (Section 4.3, or a fixed/scheduled beta).
+__device__ __forceinline__ void finish_state_tail(const FinishArgs& f, DevState* st, const double (&sc)[2], int bad) {
+  if (!isfinite(sc[0]) || !isfinite(sc[1])) bad |= FLAG_NONFINITE;
+  if (bad) atomicOr(&st->flags, bad);
+  st->vpvu = sc[0];
+  st->vuvu = sc[1];
+  if (f.last_in_sweep) {
+    const double res2 = st->nx2 - 2.0 * sc[0] + sc[1];
+    const double fit = 1.0 - sqrt(res2 > 0.0 ? res2 : 0.0) / sqrt(st->nx2);
+    const int k0 = st->sweep;
+    f.fit_hist[k0] = fit;
+    if (!isfinite(fit)) atomicOr(&st->flags, FLAG_NONFINITE);
+    if (f.extrap != 0 && f.beta_sched != nullptr) {
+      // scheduled beta for the next sweep (k0 + 1 is its 0-based index)
+      if (k0 + 1 < f.sched_len) {
+        st->active = 1;
+        st->beta = f.beta_sched[k0 + 1];
+        st->beta_sweep = k0 + 1;
+      }
+    } else if (f.extrap != 0 && !st->active) {
+      if (f.fixed_beta > 0.0) {
+        if (k0 == 0) {
+          st->active = 1;
+          st->beta = f.fixed_beta;
+          st->beta_sweep = 1;
+        }
+      } else if (k0 >= 1 && fabs(fit - f.fit_hist[k0 - 1]) < f.delta) {
+        st->active = 1;
+        st->beta = beta_from_fit(fit);
+        st->beta_sweep = k0 + 1;
+      }
+    }
+    st->fit = fit;
+    st->sweep = k0 + 1;
+  }
+}
+
 template <int RMAX, int RPT>
 __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishArgs* __restrict__ batch) {
   const FinishArgs f = kernel_args(f0, batch, blockIdx.x);
@@ -416,44 +455,150 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
       });
   }
   if (tid == 0) {
-    if (!isfinite(sc[0]) || !isfinite(sc[1])) bad |= FLAG_NONFINITE;
     // a mode smaller than the rank has min(I, R) reflectors; the padded
     // rows of R_n (c >= I) are zero by construction
     for (int c = 0; c < R && c < I; ++c)
       if (!(wy.Rm[c][c] > 0.0)) bad |= FLAG_RANKDEF;
-    if (bad) atomicOr(&st->flags, bad);
-    st->vpvu = sc[0];
-    st->vuvu = sc[1];
-    if (f.last_in_sweep) {
-      const double res2 = st->nx2 - 2.0 * sc[0] + sc[1];
-      const double fit = 1.0 - sqrt(res2 > 0.0 ? res2 : 0.0) / sqrt(st->nx2);
-      const int k0 = st->sweep;
-      f.fit_hist[k0] = fit;
-      if (!isfinite(fit)) atomicOr(&st->flags, FLAG_NONFINITE);
-      if (f.extrap != 0 && f.beta_sched != nullptr) {
-        // scheduled beta for the next sweep (k0 + 1 is its 0-based index)
-        if (k0 + 1 < f.sched_len) {
-          st->active = 1;
-          st->beta = f.beta_sched[k0 + 1];
-          st->beta_sweep = k0 + 1;
-        }
-      } else if (f.extrap != 0 && !st->active) {
-        if (f.fixed_beta > 0.0) {
-          if (k0 == 0) {
-            st->active = 1;
-            st->beta = f.fixed_beta;
-            st->beta_sweep = 1;
-          }
-        } else if (k0 >= 1 && fabs(fit - f.fit_hist[k0 - 1]) < f.delta) {
-          st->active = 1;
-          st->beta = beta_from_fit(fit);
-          st->beta_sweep = k0 + 1;
-        }
-      }
-      st->fit = fit;
-      st->sweep = k0 + 1;
+    finish_state_tail(f, st, sc, bad);
+  }
+}
+
+// ------------------------------------------------------------ tall factors
+// A mode with more rows than the single-workgroup factor QR holds in
+// registers: this kernel streams the rows in chunks of its 256 threads for
+// the solve Ahat R0^T = Vu, lambda, A = Ahat / lambda and the fit (the same
+// arithmetic per row as finish_update), and leaves the factor QR of A to the
+// two-level TSQR (an explicit source matrix) followed by tall_factor_tail.
+static constexpr int FT_THREADS = 256;
+
+template <int RMAX>
+__global__ __launch_bounds__(FT_THREADS) void finish_tall(FinishArgs f) {
+  constexpr int NT = FT_THREADS, NW = NT / 64;
+  __shared__ double sR0[RMAX][RMAX + 1];
+  __shared__ double sred2[NW][2];
+  __shared__ double sredR[NW][RMAX];
+  __shared__ double sinv[RMAX], slam[RMAX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int I = f.I, R = f.R;
+  DevState* st = f.state;
+  const gdouble* __restrict__ gV = (const gdouble*)f.V;
+  gdouble* __restrict__ gA = (gdouble*)f.A;
+  for (int e = tid; e < RMAX * RMAX; e += NT) {
+    const int i = e / RMAX, c = e % RMAX;
+    sR0[i][c] = (i < R && c < R) ? ((const gdouble*)f.R0)[i + R * c] : 0.0;
+  }
+  const bool active = (f.extrap != 0) && st->active;
+  const double beta = active ? st->beta : 0.0;
+  const double cp = 1.0 + beta, cq = -f.alpha * beta;
+  __syncthreads();
+  int bad = 0;
+  for (int c = 0; c < R; ++c)
+    if (!(sR0[c][c] != 0.0)) bad |= FLAG_RANKDEF;
+  double sc[2] = {0.0, 0.0};
+  double cn[RMAX];
+#pragma unroll
+  for (int c = 0; c < RMAX; ++c) cn[c] = 0.0;
+  for (int r0 = 0; r0 < I; r0 += NT) {
+    // keeps the R0 reads (loop-invariant LDS loads) inside the row loop, so
+    // that they are not all held in registers across it
+    __asm__ volatile("" ::: "memory");
+    const int row = r0 + tid;
+    double vu[RMAX], ah[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+      const bool in = row < I && c < R;
+      const int64_t e = in ? row + (int64_t)I * c : 0;
+      const double vp = in ? gV[e] : 0.0, vq = in ? gV[(int64_t)I * R + e] : 0.0;
+      vu[c] = active ? fma(cq, vq, cp * vp) : vp;
+      sc[0] = fma(vp, vu[c], sc[0]);
+      sc[1] = fma(vu[c], vu[c], sc[1]);
+    }
+    // back substitution of R0 ahat = vu (row of Ahat R0^T = Vu)
+    static_for<0, RMAX>([&](auto ic) {
+      constexpr int c = RMAX - 1 - decltype(ic)::value;
+      double t = vu[c];
+      static_for<c + 1, RMAX>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
+        t = fma(-sR0[c][d], ah[d], t);
+      });
+      ah[c] = (c < R && row < I && sR0[c][c] != 0.0) ? t / sR0[c][c] : 0.0;
+      __builtin_amdgcn_sched_barrier(0);
+    });
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) {
+      cn[c] = fma(ah[c], ah[c], cn[c]);
+      if (row < I && c < R) gA[row + (int64_t)I * c] = ah[c];
     }
   }
+  block_allreduce<2, NW>(sc, sred2);
+  {
+    constexpr int H = RMAX > 16 ? 16 : RMAX;
+    constexpr int G = 64 / H;
+    static_for<0, RMAX / H>([&](auto hc) {
+      constexpr int h0 = decltype(hc)::value * H;
+      double part[H];
+#pragma unroll
+      for (int c = 0; c < H; ++c) part[c] = cn[h0 + c];
+      wave_transpose_reduce<H>(part);
+      if ((lane % G) == 0) sredR[wave][h0 + lane / G] = part[0];
+    });
+  }
+  __syncthreads();
+  if (tid < RMAX) {
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tot += sredR[w][tid];
+    const double lam = sqrt(tot);
+    slam[tid] = lam;
+    sinv[tid] = (tid < R && lam != 0.0) ? 1.0 / lam : 0.0;
+    if (tid < R) ((gdouble*)f.lambda)[tid] = lam;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int c = 0; c < R; ++c) {
+      if (slam[c] == 0.0) bad |= FLAG_RANKDEF;
+      if (!isfinite(slam[c])) bad |= FLAG_NONFINITE;
+    }
+  }
+  // A = Ahat / lambda (the rows were written by this workgroup above; the
+  // barriers since then order those stores before these loads)
+  for (int c = 0; c < R; ++c) {
+    const double ic = sinv[c];
+    for (int i = tid; i < I; i += NT) gA[i + (int64_t)I * c] = gA[i + (int64_t)I * c] * ic;
+  }
+  if (tid == 0) finish_state_tail(f, st, sc, bad);
+}
+
+// After the TSQR of a tall factor: the float32 copy of Q_n for the TTMs (the
+// TSQR wrote the float64 one) and the rank check of R_n's diagonal.
+__global__ void tall_factor_tail(int64_t n, int R, const double* __restrict__ q64, float* __restrict__ q32,
+                                 const double* __restrict__ Rn, DevState* st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q32 != nullptr && i < n) ((gfloat*)q32)[i] = (float)((const gdouble*)q64)[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && st != nullptr) {
+    int bad = 0;
+    for (int c = 0; c < R; ++c)
+      if (!(Rn[c + (int64_t)R * c] > 0.0)) bad |= FLAG_RANKDEF;
+    if (bad) atomicOr(&st->flags, bad);
+  }
+}
+
+hipError_t launch_finish_tall(const FinishArgs& f, hipStream_t st) {
+  const int rm = qr_rmax(f.R);
+  if (rm == 8) hipLaunchKernelGGL(finish_tall<8>, dim3(1), dim3(FT_THREADS), 0, st, f);
+  else if (rm == 16) hipLaunchKernelGGL(finish_tall<16>, dim3(1), dim3(FT_THREADS), 0, st, f);
+  else if (rm == 32) hipLaunchKernelGGL(finish_tall<32>, dim3(1), dim3(FT_THREADS), 0, st, f);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_factor_tail(int I, int R, const double* q64, float* q32, const double* Rn,
+                                   DevState* state, hipStream_t st) {
+  const int64_t n = (int64_t)I * R;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(tall_factor_tail, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, n, R, q64, q32, Rn,
+                     state);
+  return hipGetLastError();
 }
 
 static hipError_t finish_launch(int rm, int rp, unsigned blocks, const FinishArgs& f,

@@ -85,7 +85,10 @@ def test_schedule_rejects_bad_arguments():
     (dict(dims=[2, 2, 40], rank=5), C.EUNSUPPORTED),           # Z_3 has 2*2 < 5 nonzero rows
     (dict(dims=[1, 40], rank=2, tree="none"), C.EUNSUPPORTED),  # order 2: Z_2 = R_1 has 1 row
     (dict(dims=[40, 40, 40], rank=33), C.EUNSUPPORTED),        # rank above this build's limit
-    (dict(dims=[600, 40, 40], rank=5), C.EUNSUPPORTED),        # mode above the single-block QR limit
+    (dict(dims=[600, 40, 40], rank=5), C.OK),                  # mode above 512: factor TSQR
+    (dict(dims=[2048, 256, 256], rank=32), C.OK),              # Density-sized
+    (dict(dims=[8192, 40, 40], rank=32), C.OK),                # largest two-level factor TSQR at R 32
+    (dict(dims=[8193, 40, 40], rank=32), C.EUNSUPPORTED),
     (dict(dims=[40] * 5, rank=32), C.EUNSUPPORTED),            # R^(N-1) beyond two-level TSQR
     (dict(dims=[40, 40, 40], rank=0), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, prec="fp64"), C.EINVAL),  # f32 data with fp64 precision

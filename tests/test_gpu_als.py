@@ -129,6 +129,28 @@ def test_fp32_modes_below_the_rank(P, dims, R, seed, prec):
         assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-4
 
 
+@pytest.mark.parametrize("dims,R,seed", [([600, 14, 12], 6, 81), ([1100, 9, 8], 8, 82),
+                                         ([11, 700, 9], 3, 83), ([520, 6, 5, 7], 5, 84)])
+def test_fp64_modes_above_the_single_workgroup_qr(P, dims, R, seed):
+    """A mode with more than 512 rows: streaming solve/normalise kernel, then
+    the two-level TSQR of the factor (explicit source), against the oracle."""
+    prob = G.make_problem(dims, R, seed=seed, rho=1e-2, dtype=np.float64)
+    g, o = _run(P, prob, 8, prec="fp64", tree="restructured", extrap="paper")
+    assert g["orders"] == o["orders"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+    assert np.max(np.abs(g["lam"] - o["lam"]) / o["lam"]) <= 1e-9
+
+
+@pytest.mark.parametrize("dims,R,seed", [([700, 30, 20], 16, 85), ([800, 40, 36], 32, 86)])
+def test_fp32_modes_above_the_single_workgroup_qr(P, dims, R, seed):
+    prob = G.make_problem(dims, R, seed=seed, rho=1e-2, dtype=np.float32)
+    g, o = _run(P, prob, 8, prec="fp32", tree="restructured")
+    _check_fp32(g, o)
+
+
 def test_fp64_fixed_beta_extrapolation(P):
     """eq. (19) with beta fixed from sweep 2 on: the GPU applies Qhat0 through
     Y_(n) Qhat0 = (1+beta) Y_(n) Q0 - alpha beta Y_(n) Q0prev."""
