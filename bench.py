@@ -174,6 +174,52 @@ def orders_4_5_study(steps: int, warmup: int):
             "workloads": out}
 
 
+def paper_shapes_study(sweeps: int = 20, real_rank: int = 16):
+    """Sweep rates at the sizes of the paper's synthetic suite (Table 8, the
+    rows within this build's limits) and of its real-world tensors (stand-ins
+    of the same shapes; the data are not available): ``sweeps`` ALS-QR-BRE
+    sweeps (the paper runs 20 iterations per method), restructured tree,
+    float32 TTMs.  Sweep 1 (a standard sweep plus graph capture) is not
+    timed; the rest are timed as one replay between two synchronisations."""
+    import torch
+
+    import paper_2503_18759_amd as P
+    import synthgen as G
+
+    cases = [("table8_row%d" % r, lambda r=r: G.table8_problem(r)) for r in (1, 4, 7, 8, 10, 11)]
+    cases += [(name + "_standin", lambda name=name: G.real_shape_problem(name, real_rank))
+              for name in G.REAL_SHAPES]
+    out = {}
+    for name, make in cases:
+        t0 = time.perf_counter()
+        prob = make()
+        gen = time.perf_counter() - t0
+        x, dims = P.to_device(prob.X)
+        del prob.X
+        sess = P.Session(x, prob.rank, prob.init, sweeps, dims=dims, tree="restructured",
+                         extrapolate="paper", explicit_fit=True)
+        sess.sweeps(1)
+        sess.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sess.sweeps(sweeps - 1)
+        sess.sync()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        r = sess.result()
+        sess.close()
+        del x
+        torch.cuda.empty_cache()
+        out[name] = {"dims": dims, "rank": prob.rank, "true_rank": prob.meta.get("true_rank"),
+                     "ms_per_sweep": sec / (sweeps - 1) * 1e3, "fit": float(r["fit"]),
+                     "fit_explicit": float(r["fit_explicit"]),
+                     "beta": r["beta"], "beta_sweep": r["beta_sweep"], "host_generation_s": gen}
+        print(json.dumps({"case": name, **out[name]}), file=sys.stderr, flush=True)
+    return {"study": "paper_shapes", "sweeps": sweeps,
+            "timing": "sweeps 2..%d replayed between two synchronisations" % sweeps,
+            "cases": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,7 +229,7 @@ def main():
     ap.add_argument("--tree", default="restructured", choices=["none", "standard", "restructured"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--study", choices=["time-to-fit", "orders-4-5"], default=None,
+    ap.add_argument("--study", choices=["time-to-fit", "orders-4-5", "paper-shapes"], default=None,
                     help="run a study instead of the benchmark (prints its own JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-MiB device buffer once (a plain copy "
@@ -206,6 +252,9 @@ def main():
     P.load_library()
     if args.study == "time-to-fit":
         print(json.dumps(time_to_fit_study()), flush=True)
+        return
+    if args.study == "paper-shapes":
+        print(json.dumps(paper_shapes_study()), flush=True)
         return
     if args.study == "orders-4-5":
         print(json.dumps(orders_4_5_study(args.steps, args.warmup)), flush=True)

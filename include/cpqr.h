@@ -281,7 +281,7 @@ cpqr_status cpqr_schedule(int order, int tree, int sweeps, int *orders_out,
  * the TTM: float64 for FP64, float32 for FP32; for BF16X3 `q` is float32 and
  * is split on the device).  `out` (device) receives the tensor with
  * dims[mode] replaced by R.  in/out element type: float64 for FP64, float32
- * otherwise.  Limits: 1 <= R <= 64, dims[mode] * roundup(R,16) * 4 <= 64 KiB.
+ * otherwise.  Limits: 1 <= R <= 64, roundup(dims[mode],32) * roundup(R,16) * 4 <= 160 KiB.
  */
 cpqr_status cpqr_ttm(cpqr_handle *handle, int prec, int order, const int64_t *dims,
                      int mode, int rank, const void *in, const void *q, void *out);

@@ -640,7 +640,7 @@ cpqr_status cpqr_ttm(cpqr_handle* h, int prec, int order, const int64_t* dims, i
     HIP_TRY(h, launch_ttm_f64((const double*)in, (const double*)q, (double*)out, L, (int)I, S, rank, h->stream));
   } else {
     if (prec == CPQR_PREC_BF16X3 && !ttm_mfma_supported((int)I, rank))
-      return fail(h, CPQR_EUNSUPPORTED, "bf16x3 TTM needs rank <= 64 and I * roundup(R,16) * 4 <= 64 KiB");
+      return fail(h, CPQR_EUNSUPPORTED, "bf16x3 TTM needs rank <= 64 and roundup(I,32) * roundup(R,16) * 4 <= 160 KiB");
     HIP_TRY(h, launch_ttm_f32((const float*)in, (const float*)q, (float*)out, L, (int)I, S, rank,
                               prec == CPQR_PREC_BF16X3, h->stream));
   }

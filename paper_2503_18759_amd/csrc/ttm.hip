@@ -804,6 +804,11 @@ static int device_cu_count() {
   return cached[dev];
 }
 
+// LDS of one gfx950 workgroup (160 KiB per CU, all of it available to one
+// workgroup).  Q_m staged whole bounds the contracted mode size: up to 160 KiB
+// the MFMA kernels run (one workgroup per CU above 80 KiB); K splits and the
+// batched path keep within 64 KiB.
+static constexpr size_t TTM_LDS_WG_MAX = 160 * 1024;
 static size_t ttm_q_lds(int I, int NB) { return (size_t)((I + 31) / 32) * 32 * 16 * NB * 4; }
 static size_t ttm_red_lds(int ks, int NB) {
   return ks > 1 ? (size_t)(ks - 1) * (4 / ks) * 64 * 16 * NB * 4 : 0;
@@ -911,7 +916,7 @@ bool ttm_mfma_supported(int I, int R) {
   if (R < 1 || R > 64 || I < 1) return false;
   const int NB = (R + 15) / 16;
   // Q staged in LDS: I (padded to 32) x 16 NB floats (or bf16 hi + lo pairs)
-  return ttm_q_lds(I, NB) <= 64 * 1024;
+  return ttm_q_lds(I, NB) <= TTM_LDS_WG_MAX;
 }
 
 unsigned ttm_ks_options(int64_t L, int I, int64_t S, int R) {

@@ -234,7 +234,8 @@ def table8_problem(row: int, *, dims: Optional[Sequence[int]] = None, seed: Opti
 
 # Shapes of the paper's real-world tensors (Section 4.4).  The data are not
 # available here; ``real_shape_problem`` builds a stand-in of the same shape:
-# a planted rank-``true_rank`` tensor with iid N(0,1) factors and 1 % noise.
+# a planted rank-``true_rank`` tensor with iid N(0,1) factors and noise at
+# l1 = 1 (relative level 1 / sqrt(99), about 0.10).
 REAL_SHAPES = {
     "indian_pines": [145, 145, 224],
     "salinas": [512, 217, 224],

@@ -54,13 +54,15 @@ TTM_SHAPES = [
     ((1, 40, 1), 1, 1),
     # contracted mode smaller than the rank (zero-padded Q of a small mode)
     ((40, 3, 30), 1, 16), ((3, 50, 20), 0, 8), ((20, 30, 2), 2, 12),
+    # contracted mode above 64 KiB of staged Q (up to the 160 KiB LDS)
+    ((1500, 20, 9), 0, 16), ((30, 1000, 7), 1, 32), ((12, 9, 2100), 2, 8), ((7, 2500, 5), 1, 5),
 ]
 
 
 @pytest.mark.parametrize("dims,mode,R", TTM_SHAPES)
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
 def test_ttm_matches_oracle(P, dims, mode, R, prec):
-    if prec == "bf16x3" and dims[mode] * ((R + 15) // 16) * 16 * 4 > 65536:
+    if prec == "bf16x3" and ((dims[mode] + 31) // 32) * 32 * ((R + 15) // 16) * 16 * 4 > 160 * 1024:
         pytest.skip("outside the bf16x3 kernel limits")
     _ttm_case(P, list(dims), mode, R, prec, seed=sum(dims) + 7 * mode + R)
 
