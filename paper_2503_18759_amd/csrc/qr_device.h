@@ -59,6 +59,33 @@ struct QrRow {
   static constexpr int NH = RMAX / HW;
   using Vec = typename std::conditional<HW == 16, f64x16, f64x8>::type;
   Vec h[NH];
+  // Element c for a wave-uniform c, as a binary tree of uniform branches
+  // whose leaves read a fixed register (get_u).  get() with a variable index
+  // into two halves compiles to a select of the whole vectors, a move per
+  // element; the tree avoids those moves, which pays where a thread holds one
+  // row, and costs registers where it holds several.  The empty asm
+  // statements keep the branches from being merged into selects.
+  template <int LO, int HI>
+  __device__ __forceinline__ double get_tree(int c) const {
+    if constexpr (HI - LO == 1) {
+      return h[LO / HW][LO % HW];
+    } else {
+      constexpr int MID = (LO + HI) / 2;
+      double x;
+      if (c < MID) {
+        __asm__ volatile("");
+        x = get_tree<LO, MID>(c);
+      } else {
+        __asm__ volatile("");
+        x = get_tree<MID, HI>(c);
+      }
+      return x;
+    }
+  }
+  __device__ __forceinline__ double get_u(int c) const {
+    if constexpr (NH == 1) return h[0][c];
+    else return get_tree<0, RMAX>(c);
+  }
   __device__ __forceinline__ double get(int c) const {
     if constexpr (NH == 1) return h[0][c];
     else return (c < HW) ? h[0][c & (HW - 1)] : h[1][c & (HW - 1)];
@@ -237,7 +264,9 @@ __device__ __forceinline__ void block_qr(QrRow<RMAX> (&a)[RPT], int R, QrSmem<RM
 #pragma unroll
     for (int p = 0; p < RPT; ++p) {
       const int row = tid + NT * p;
-      const double an = (jn < RMAX) ? fma(-coef[p], wn, a[p].get(jn < RMAX ? jn : 0)) : 0.0;
+      const int jc = jn < RMAX ? jn : 0;
+      const double ajn = (RPT == 1) ? a[p].get_u(jc) : a[p].get(jc);
+      const double an = (jn < RMAX) ? fma(-coef[p], wn, ajn) : 0.0;
       xn[p] = (row > jn) ? an : 0.0;
     }
 #pragma unroll
