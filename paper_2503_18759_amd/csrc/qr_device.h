@@ -222,30 +222,37 @@ __device__ __forceinline__ void block_qr(QrRow<RMAX> (&a)[RPT], int R, QrSmem<RM
     if ((lane % G) == 0) sm.red[buf][wave][lane / G] = part[0];
     __syncthreads();
     // every wave: lane c < RMAX gets tot_c = sum_{i>j} x_i a_i[c]
-    double tot = 0.0;
+    // every LDS operand of this step is read before any is used, so that the
+    // reads are in flight together: the wave partials, the pivot row and the
+    // reflector scales of the previous columns (written before the barrier)
+    double tot = 0.0, pc = 0.0, scl = 0.0;
+    const double x0 = sm.piv[buf][j];
     if (lane < RMAX) {
+      double rv[QrCfg<RMAX>::NW];
 #pragma unroll
-      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
+      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) rv[w] = sm.red[buf][w][lane];
+      pc = sm.piv[buf][lane];
+      scl = sm.scale[lane];
+#pragma unroll
+      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += rv[w];
     }
     const double st = lane_read(tot, j);
-    const double x0 = sm.piv[buf][j];
     double tau, beta, scale;
     qr_reflector_scalars(x0, st, &tau, &beta, &scale);
     if (lane < RMAX) {
       // c > j: w_c = a_j[c] + scale * sum_{i>j} x_i a_i[c]  (v^T a_c with v_j = 1)
       // m < j: u_m = (V^T v_j)_m = scale_m (x_m[j] + scale * sum_{i>j} x_i x_m[i])
-      const double pc = sm.piv[buf][lane];
       const double wu = fma(scale, tot, pc);
       sm.w[wave][lane] = (lane > j) ? wu : 0.0;
-      if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * sm.scale[lane] : 0.0;
+      if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * scl : 0.0;
     }
     if (wave == 0 && lane == 0) {
       sm.tau[j] = tau;
       sm.beta[j] = beta;
       sm.scale[j] = scale;
     }
-    // the wave reads back its own copy of w (same wave: ordering only)
-    __builtin_amdgcn_wave_barrier();
+    // the wave reads back its own copy of w: one wave's LDS operations
+    // complete in order, so no wait is needed between the write and the reads
     double wv[RMAX];
 #pragma unroll
     for (int c = 0; c < RMAX; ++c) wv[c] = sm.w[wave][c];
@@ -347,20 +354,27 @@ __device__ __forceinline__ void block_qr_stair(QrStair<RMAX, NS, RT, CS>& z, int
     wave_transpose_reduce<RMAX>(part);
     if ((lane % G) == 0) sm.red[buf][wave][lane / G] = part[0];
     __syncthreads();
-    double tot = 0.0;
+    // every LDS operand of this step is read before any is used, so that the
+    // reads are in flight together: the wave partials, the pivot row and the
+    // reflector scales of the previous columns (written before the barrier)
+    double tot = 0.0, pc = 0.0, scl = 0.0;
+    const double xp = sm.piv[buf][j];
     if (lane < RMAX) {
+      double rv[QrCfg<RMAX>::NW];
 #pragma unroll
-      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += sm.red[buf][w][lane];
+      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) rv[w] = sm.red[buf][w][lane];
+      pc = sm.piv[buf][lane];
+      scl = sm.scale[lane];
+#pragma unroll
+      for (int w = 0; w < QrCfg<RMAX>::NW; ++w) tot += rv[w];
     }
     const double st = lane_read(tot, j);
-    const double xp = sm.piv[buf][j];
     double tau, beta, scale;
     qr_reflector_scalars(xp, st, &tau, &beta, &scale);
     if (lane < RMAX) {
-      const double pc = sm.piv[buf][lane];
       const double wu = fma(scale, tot, pc);
       sm.w[wave][lane] = (lane > j) ? wu : 0.0;
-      if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * sm.scale[lane] : 0.0;
+      if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * scl : 0.0;
     }
     if (wave == 0 && lane == 0) {
       sm.tau[j] = tau;
@@ -368,8 +382,8 @@ __device__ __forceinline__ void block_qr_stair(QrStair<RMAX, NS, RT, CS>& z, int
       sm.scale[j] = scale;
     }
     // the wave reads w back from its own LDS copy as the columns are updated
-    // (keeping all of w in registers as well would not fit beside the rows)
-    __builtin_amdgcn_wave_barrier();
+    // (keeping all of w in registers as well would not fit beside the rows);
+    // one wave's LDS operations complete in order
     const int jn = j + 1;
     // narrow slices inside the profile of column min(jn, R-1); the profile
     // of column j is contained in it, so every slice the reflector changes
