@@ -217,7 +217,7 @@ __global__ __launch_bounds__(64 * AR_WAVES) void apply_reduce(ApplyDev a0, const
 
 int apply_num_chunks(int64_t M, int I) {
   const int iblocks = (I + AP_ROWS - 1) / AP_ROWS;
-  int64_t want = (256 + iblocks - 1) / iblocks;            // about one workgroup per CU
+  int64_t want = (512 + iblocks - 1) / iblocks;            // about two workgroups per CU
   int64_t maxc = (M + AP_KT - 1) / AP_KT;                   // at least one k-tile each
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
