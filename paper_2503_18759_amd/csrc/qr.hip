@@ -366,17 +366,102 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
   block_qr_publish<RMAX>(z.a0, R, sm, u.wy, true);
   block_qr_wy_product<RMAX>(sm, u.wy, R, nullptr, 0);
   gdouble* __restrict__ Q0 = (gdouble*)args.Q0;
-  if (krow[0] >= 0)
-    block_qr_q_row<RMAX>(z.a0, tid, R, sm, u.wy, [&](int c, double val) { Q0[krow[0] + M * c] = val; });
+  if constexpr (NS == 0) {
+    if (krow[0] >= 0)
+      block_qr_q_row<RMAX>(z.a0, tid, R, sm, u.wy, [&](int c, double val) { Q0[krow[0] + M * c] = val; });
+  } else {
+    // Rows of Q0 = (E - V M) diag(sgn), M = T V1^T, for the slice-0 row and
+    // the narrow rows together.  A narrow row's v vanishes outside columns
+    // [CS, CS+RT) of V, and M vanishes at (m, c) for m > c (V1 is unit lower
+    // triangular), so a narrow row's entries in columns c < CS are exact
+    // zeros.  From column CS on, each pair of M entries read from LDS serves
+    // the slice-0 row and every narrow row.  The multiply-adds of each row
+    // run in the same order as for a row on its own.
+    double v0[RMAX];
 #pragma unroll
-  for (int q = 0; q < NS; ++q) {
-    if (krow[q + 1] < 0) continue;
-    double v[RT];
+    for (int m = 0; m < RMAX; ++m) v0[m] = (m < R) ? block_qr_v<RMAX>(z.a0, tid, m, sm) : 0.0;
+    double vn[NS][RT];
 #pragma unroll
-    for (int m = 0; m < RT; ++m) v[m] = (CS + m < R) ? z.at[q].get(m) * sm.scale[CS + m] : 0.0;
-    const int64_t kr = krow[q + 1];
-    wy_q_row<RMAX, RT, CS>(v, (int64_t)NT * (q + 1) + tid, R, sm, u.wy,
-                           [&](int c, double val) { Q0[kr + M * c] = val; });
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int m = 0; m < RT; ++m) vn[q][m] = (CS + m < R) ? z.at[q].get(m) * sm.scale[CS + m] : 0.0;
+    const bool have0 = krow[0] >= 0;
+    for (int c = 0; c < R; c += 2) {
+      // c + 1 <= RMAX - 1 (R <= RMAX, RMAX even); M is zero in columns >= R
+      double a0 = (tid == c) ? 1.0 : 0.0, a1 = (tid == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
+      {
+        double m0[CS], m1[CS];
+#pragma unroll
+        for (int m = 0; m < CS; ++m) {
+          m0[m] = u.wy.Mt[c][m];
+          m1[m] = u.wy.Mt[c + 1][m];
+        }
+#pragma unroll
+        for (int m = 0; m < CS; m += 2) {
+          a0 = fma(-v0[m], m0[m], a0);
+          a1 = fma(-v0[m], m1[m], a1);
+          b0 = fma(-v0[m + 1], m0[m + 1], b0);
+          b1 = fma(-v0[m + 1], m1[m + 1], b1);
+        }
+      }
+      double na0[NS], na1[NS], nb0[NS], nb1[NS];
+#pragma unroll
+      for (int q = 0; q < NS; ++q) na0[q] = na1[q] = nb0[q] = nb1[q] = 0.0;
+      if (c >= CS) {
+        constexpr int UP = RMAX - CS;
+        double m0[UP], m1[UP];
+#pragma unroll
+        for (int m = 0; m < UP; ++m) {
+          m0[m] = u.wy.Mt[c][CS + m];
+          m1[m] = u.wy.Mt[c + 1][CS + m];
+        }
+#pragma unroll
+        for (int m = 0; m < UP; m += 2) {
+          a0 = fma(-v0[CS + m], m0[m], a0);
+          a1 = fma(-v0[CS + m], m1[m], a1);
+          b0 = fma(-v0[CS + m + 1], m0[m + 1], b0);
+          b1 = fma(-v0[CS + m + 1], m1[m + 1], b1);
+          if (m < RT) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+              na0[q] = fma(-vn[q][m], m0[m], na0[q]);
+              na1[q] = fma(-vn[q][m], m1[m], na1[q]);
+              nb0[q] = fma(-vn[q][m + 1], m0[m + 1], nb0[q]);
+              nb1[q] = fma(-vn[q][m + 1], m1[m + 1], nb1[q]);
+            }
+          }
+        }
+      } else {
+        constexpr int UP = RMAX - CS;
+        double m0[UP], m1[UP];
+#pragma unroll
+        for (int m = 0; m < UP; ++m) {
+          m0[m] = u.wy.Mt[c][CS + m];
+          m1[m] = u.wy.Mt[c + 1][CS + m];
+        }
+#pragma unroll
+        for (int m = 0; m < UP; m += 2) {
+          a0 = fma(-v0[CS + m], m0[m], a0);
+          a1 = fma(-v0[CS + m], m1[m], a1);
+          b0 = fma(-v0[CS + m + 1], m0[m + 1], b0);
+          b1 = fma(-v0[CS + m + 1], m1[m + 1], b1);
+        }
+      }
+      const double s0 = sm.sgn[c], s1 = sm.sgn[c + 1];
+      if (have0) {
+        Q0[krow[0] + M * c] = (a0 + b0) * s0;
+        if (c + 1 < R) Q0[krow[0] + M * (c + 1)] = (a1 + b1) * s1;
+      }
+#pragma unroll
+      for (int q = 0; q < NS; ++q) {
+        if (krow[q + 1] < 0) continue;
+        // columns below CS: exact zeros
+        const double q0v = (c >= CS) ? (na0[q] + nb0[q]) * s0 : 0.0;
+        const double q1v = (c >= CS) ? (na1[q] + nb1[q]) * s1 : 0.0;
+        Q0[krow[q + 1] + M * c] = q0v;
+        if (c + 1 < R) Q0[krow[q + 1] + M * (c + 1)] = q1v;
+      }
+    }
   }
 }
 
