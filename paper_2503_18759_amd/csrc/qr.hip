@@ -389,62 +389,56 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
     for (int c = 0; c < R; c += 2) {
       // c + 1 <= RMAX - 1 (R <= RMAX, RMAX even); M is zero in columns >= R
       double a0 = (tid == c) ? 1.0 : 0.0, a1 = (tid == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
-      {
-        double m0[CS], m1[CS];
+      // M is upper triangular (M[m][c] = 0 for m > c): reflector blocks past
+      // c + 1 contribute exact zeros and are skipped
+      constexpr int MB = CS < 8 ? CS : 8;
+      static_assert(CS % MB == 0 && (RMAX - CS) % MB == 0 && RT % MB == 0, "blocks of reflectors");
 #pragma unroll
-        for (int m = 0; m < CS; ++m) {
-          m0[m] = u.wy.Mt[c][m];
-          m1[m] = u.wy.Mt[c + 1][m];
+      for (int mb = 0; mb < CS; mb += MB) {
+        if (mb > c + 1) break;
+        double m0[MB], m1[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          m0[m] = u.wy.Mt[c][mb + m];
+          m1[m] = u.wy.Mt[c + 1][mb + m];
         }
 #pragma unroll
-        for (int m = 0; m < CS; m += 2) {
-          a0 = fma(-v0[m], m0[m], a0);
-          a1 = fma(-v0[m], m1[m], a1);
-          b0 = fma(-v0[m + 1], m0[m + 1], b0);
-          b1 = fma(-v0[m + 1], m1[m + 1], b1);
+        for (int m = 0; m < MB; m += 2) {
+          a0 = fma(-v0[mb + m], m0[m], a0);
+          a1 = fma(-v0[mb + m], m1[m], a1);
+          b0 = fma(-v0[mb + m + 1], m0[m + 1], b0);
+          b1 = fma(-v0[mb + m + 1], m1[m + 1], b1);
         }
       }
       double na0[NS], na1[NS], nb0[NS], nb1[NS];
 #pragma unroll
       for (int q = 0; q < NS; ++q) na0[q] = na1[q] = nb0[q] = nb1[q] = 0.0;
-      if (c >= CS) {
-        constexpr int UP = RMAX - CS;
-        double m0[UP], m1[UP];
+      // from column CS on (the upper blocks are needed only then): the
+      // slice-0 row and every narrow row share the M entries
 #pragma unroll
-        for (int m = 0; m < UP; ++m) {
-          m0[m] = u.wy.Mt[c][CS + m];
-          m1[m] = u.wy.Mt[c + 1][CS + m];
+      for (int mb = 0; mb < RMAX - CS; mb += MB) {
+        if (CS + mb > c + 1) break;
+        double m0[MB], m1[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          m0[m] = u.wy.Mt[c][CS + mb + m];
+          m1[m] = u.wy.Mt[c + 1][CS + mb + m];
         }
 #pragma unroll
-        for (int m = 0; m < UP; m += 2) {
-          a0 = fma(-v0[CS + m], m0[m], a0);
-          a1 = fma(-v0[CS + m], m1[m], a1);
-          b0 = fma(-v0[CS + m + 1], m0[m + 1], b0);
-          b1 = fma(-v0[CS + m + 1], m1[m + 1], b1);
-          if (m < RT) {
+        for (int m = 0; m < MB; m += 2) {
+          a0 = fma(-v0[CS + mb + m], m0[m], a0);
+          a1 = fma(-v0[CS + mb + m], m1[m], a1);
+          b0 = fma(-v0[CS + mb + m + 1], m0[m + 1], b0);
+          b1 = fma(-v0[CS + mb + m + 1], m1[m + 1], b1);
+          if (mb + m < RT) {
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
-              na0[q] = fma(-vn[q][m], m0[m], na0[q]);
-              na1[q] = fma(-vn[q][m], m1[m], na1[q]);
-              nb0[q] = fma(-vn[q][m + 1], m0[m + 1], nb0[q]);
-              nb1[q] = fma(-vn[q][m + 1], m1[m + 1], nb1[q]);
+              na0[q] = fma(-vn[q][mb + m], m0[m], na0[q]);
+              na1[q] = fma(-vn[q][mb + m], m1[m], na1[q]);
+              nb0[q] = fma(-vn[q][mb + m + 1], m0[m + 1], nb0[q]);
+              nb1[q] = fma(-vn[q][mb + m + 1], m1[m + 1], nb1[q]);
             }
           }
-        }
-      } else {
-        constexpr int UP = RMAX - CS;
-        double m0[UP], m1[UP];
-#pragma unroll
-        for (int m = 0; m < UP; ++m) {
-          m0[m] = u.wy.Mt[c][CS + m];
-          m1[m] = u.wy.Mt[c + 1][CS + m];
-        }
-#pragma unroll
-        for (int m = 0; m < UP; m += 2) {
-          a0 = fma(-v0[CS + m], m0[m], a0);
-          a1 = fma(-v0[CS + m], m1[m], a1);
-          b0 = fma(-v0[CS + m + 1], m0[m + 1], b0);
-          b1 = fma(-v0[CS + m + 1], m1[m + 1], b1);
         }
       }
       const double s0 = sm.sgn[c], s1 = sm.sgn[c + 1];

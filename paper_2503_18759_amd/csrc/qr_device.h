@@ -534,21 +534,31 @@ template <int RMAX, int W, int OFF, typename Store>
 __device__ __forceinline__ void wy_q_row(const double (&v)[W], int64_t row, int R, const QrSmem<RMAX>& sm,
                                          const QrWySmem<RMAX>& wy, Store&& store) {
   static_assert(W % 2 == 0 && RMAX % 2 == 0, "pairs of rows and columns");
+  // M = T V1^T is upper triangular (T upper, V1 unit lower triangular):
+  // M[m][c] = 0 for m > c, so the blocks of reflectors past c + 1 contribute
+  // exact zeros to columns c, c + 1 and are skipped (a uniform test per
+  // block keeps every register index fixed)
+  constexpr int MB = W < 8 ? W : 8;
+  static_assert(W % MB == 0, "blocks of reflectors");
   for (int c = 0; c < R; c += 2) {
     // c + 1 <= RMAX - 1 (R <= RMAX, RMAX even); M is zero in columns >= R
-    double m0[W], m1[W];
-#pragma unroll
-    for (int m = 0; m < W; ++m) {
-      m0[m] = wy.Mt[c][OFF + m];
-      m1[m] = wy.Mt[c + 1][OFF + m];
-    }
     double a0 = (row == c) ? 1.0 : 0.0, a1 = (row == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
 #pragma unroll
-    for (int m = 0; m < W; m += 2) {
-      a0 = fma(-v[m], m0[m], a0);
-      a1 = fma(-v[m], m1[m], a1);
-      b0 = fma(-v[m + 1], m0[m + 1], b0);
-      b1 = fma(-v[m + 1], m1[m + 1], b1);
+    for (int mb = 0; mb < W; mb += MB) {
+      if (OFF + mb > c + 1) break;
+      double m0[MB], m1[MB];
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        m0[m] = wy.Mt[c][OFF + mb + m];
+        m1[m] = wy.Mt[c + 1][OFF + mb + m];
+      }
+#pragma unroll
+      for (int m = 0; m < MB; m += 2) {
+        a0 = fma(-v[mb + m], m0[m], a0);
+        a1 = fma(-v[mb + m], m1[m], a1);
+        b0 = fma(-v[mb + m + 1], m0[m + 1], b0);
+        b1 = fma(-v[mb + m + 1], m1[m + 1], b1);
+      }
     }
     store(c, (a0 + b0) * sm.sgn[c]);
     if (c + 1 < R) store(c + 1, (a1 + b1) * sm.sgn[c + 1]);
