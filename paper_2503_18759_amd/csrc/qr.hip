@@ -190,20 +190,31 @@ __global__ __launch_bounds__(QrCfg<RMAX>::NT) void form_q0(FormArgs a0, const Fo
   const int64_t row = row0 + tid;
   if (row >= M) return;
   const int64_t lr = row - leaf0;
-  double q[RMAX];
+  // row of V in registers, then two columns per trip with the M entries of
+  // a column adjacent in LDS (16-byte reads) and two partial sums per column
+  double v[RMAX];
 #pragma unroll
-  for (int c = 0; c < RMAX; ++c) q[c] = (lr < R && c < R) ? sQt[lr * RMAX + c] : 0.0;
+  for (int m = 0; m < RMAX; ++m) v[m] = (m < R) ? V[row + ldv * (m < R ? m : 0)] : 0.0;
+  for (int c = 0; c < R; c += 2) {
+    // c + 1 <= RMAX - 1 (R <= RMAX, RMAX even); M is zero in columns >= R
+    double m0[RMAX], m1[RMAX];
 #pragma unroll
-  for (int m = 0; m < RMAX; ++m) {
-    if (m < R) {
-      const double v = V[row + ldv * m];
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c) q[c] = fma(-v, wy.Mt[c][m], q[c]);
+    for (int m = 0; m < RMAX; ++m) {
+      m0[m] = wy.Mt[c][m];
+      m1[m] = wy.Mt[c + 1][m];
     }
-  }
+    double a0 = (lr < R) ? sQt[lr * RMAX + c] : 0.0, a1 = (lr < R) ? sQt[lr * RMAX + c + 1] : 0.0;
+    double b0 = 0.0, b1 = 0.0;
 #pragma unroll
-  for (int c = 0; c < RMAX; ++c)
-    if (c < R) Q0[row + M * c] = q[c];
+    for (int m = 0; m < RMAX; m += 2) {
+      a0 = fma(-v[m], m0[m], a0);
+      a1 = fma(-v[m], m1[m], a1);
+      b0 = fma(-v[m + 1], m0[m + 1], b0);
+      b1 = fma(-v[m + 1], m1[m + 1], b1);
+    }
+    Q0[row + M * c] = a0 + b0;
+    if (c + 1 < R) Q0[row + M * (c + 1)] = a1 + b1;
+  }
 }
 
 // --------------------------------------------------------------- staircase
