@@ -308,6 +308,19 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
     }
   }
   __syncthreads();
+  // Z[row][c] = prod_{k < K} R_k[d_k][c]; branch-free over the KMAX digit
+  // slots (unused slots read a valid entry and multiply by one), so that a
+  // row's LDS reads are issued together rather than one per branch
+  auto zval = [&](const int (&d)[KMAX], int c) __attribute__((always_inline)) {
+    double v = 1.0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const bool use = k < K;
+      const double f = u.srf[(use ? k * RMAX * RMAX + d[k] : 0) + RMAX * c];
+      v *= use ? f : 1.0;
+    }
+    return v;
+  };
   QrStair<RMAX, NS, RT, CS> z;
   int64_t krow[NS + 1];   // Kolda row of each held row (-1: beyond M)
   {
@@ -324,13 +337,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
         }
       krow[0] = kr;
 #pragma unroll
-      for (int c = 0; c < RMAX; ++c) {
-        double v = 1.0;
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < K) v *= u.srf[k * RMAX * RMAX + d[k] + RMAX * c];
-        z.a0.set(c, v);
-      }
+      for (int c = 0; c < RMAX; ++c) z.a0.set(c, zval(d, c));
     } else {
       krow[0] = -1;
 #pragma unroll
@@ -350,13 +357,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
           }
         krow[q + 1] = kr;
 #pragma unroll
-        for (int c = 0; c < RT; ++c) {
-          double v = 1.0;
-#pragma unroll
-          for (int k = 0; k < KMAX; ++k)
-            if (k < K) v *= u.srf[k * RMAX * RMAX + d[k] + RMAX * (CS + c)];
-          z.at[q].set(c, v);
-        }
+        for (int c = 0; c < RT; ++c) z.at[q].set(c, zval(d, CS + c));
       } else {
         krow[q + 1] = -1;
 #pragma unroll
