@@ -220,6 +220,66 @@ def paper_shapes_study(sweeps: int = 20, real_rank: int = 16):
             "cases": out}
 
 
+def batched_study(count: int = 64, short: int = 10, long: int = 60, single_sweeps: int = 20):
+    """Throughput of the batched sweep (every kernel covers all problems, one
+    graph per sweep) on the 64-problem order-3 workload (dims U{32..160}^3,
+    ranks U{4..24}, float32 TTMs, restructured tree).  Each batched call
+    includes set-up, the TTM autotuning of its first sweep and graph capture,
+    so the time per batch sweep is the difference of a ``long`` and a
+    ``short`` run (best of two each, after an untimed call) divided by the
+    extra sweeps.  For comparison the same
+    problems run one after another as single-problem sessions (sweep 1 not
+    timed, then ``single_sweeps`` replayed sweeps each)."""
+    import torch
+
+    import paper_2503_18759_amd as P
+    import synthgen as G
+
+    probs = G.batched_workload(count)
+    xs, dims = [], []
+    for p in probs:
+        x, d = P.to_device(p.X)
+        xs.append(x)
+        dims.append(d)
+    ranks = [p.rank for p in probs]
+    inits = [p.init for p in probs]
+    # an untimed call first (the handle's workspace is allocated once), then
+    # the best of two calls at each length
+    P.cp_als_qr_batched(xs, ranks, inits, short, dims=dims)
+    wall = {}
+    for it in (short, long):
+        best = float("inf")
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P.cp_als_qr_batched(xs, ranks, inits, it, dims=dims)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        wall[it] = best
+        print(json.dumps({"batched_sweeps": it, "seconds": wall[it]}), file=sys.stderr, flush=True)
+    per_batch_sweep = (wall[long] - wall[short]) / (long - short)
+    single = 0.0
+    for x, d, p in zip(xs, dims, probs):
+        sess = P.Session(x, p.rank, p.init, 1 + single_sweeps, dims=d, tree="restructured")
+        sess.sweeps(1)
+        sess.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sess.sweeps(single_sweeps)
+        sess.sync()
+        torch.cuda.synchronize()
+        single += (time.perf_counter() - t0) / single_sweeps
+        sess.close()
+    print(json.dumps({"single_sum_ms": single * 1e3}), file=sys.stderr, flush=True)
+    return {"study": "batched", "problems": count, "ranks": [min(ranks), max(ranks)],
+            "batch_sweep_ms": per_batch_sweep * 1e3,
+            "problem_sweeps_per_s": count / per_batch_sweep,
+            "one_by_one_sweep_ms": single * 1e3,
+            "speedup_over_one_by_one": single / per_batch_sweep,
+            "timing": "batched: (wall(%d sweeps) - wall(%d sweeps)) / %d; one by one: sum over problems "
+                      "of the mean replayed sweep" % (long, short, long - short)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,7 +289,7 @@ def main():
     ap.add_argument("--tree", default="restructured", choices=["none", "standard", "restructured"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--study", choices=["time-to-fit", "orders-4-5", "paper-shapes"], default=None,
+    ap.add_argument("--study", choices=["time-to-fit", "orders-4-5", "paper-shapes", "batched"], default=None,
                     help="run a study instead of the benchmark (prints its own JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-MiB device buffer once (a plain copy "
@@ -252,6 +312,9 @@ def main():
     P.load_library()
     if args.study == "time-to-fit":
         print(json.dumps(time_to_fit_study()), flush=True)
+        return
+    if args.study == "batched":
+        print(json.dumps(batched_study()), flush=True)
         return
     if args.study == "paper-shapes":
         print(json.dumps(paper_shapes_study()), flush=True)
