@@ -151,6 +151,16 @@ def test_fp32_modes_above_the_single_workgroup_qr(P, dims, R, seed):
     _check_fp32(g, o)
 
 
+@pytest.mark.parametrize("name,scale", [("tabby_cat", 0.1), ("density", 0.3), ("winter_landscape", 0.3)])
+def test_fp32_real_data_shaped_standins(P, name, scale):
+    """Stand-ins of the paper's real-world tensor shapes, scaled down: a mode
+    of size 3 (compact factor QR), a mode above 512 rows (factor TSQR) and
+    the paper's extrapolation, against the oracle."""
+    prob = G.real_shape_problem(name, 8, scale=scale)
+    g, o = _run(P, prob, 6, prec="fp32", tree="restructured", extrap="paper")
+    _check_fp32(g, o)
+
+
 def test_fp64_fixed_beta_extrapolation(P):
     """eq. (19) with beta fixed from sweep 2 on: the GPU applies Qhat0 through
     Y_(n) Qhat0 = (1+beta) Y_(n) Q0 - alpha beta Y_(n) Q0prev."""
