@@ -161,6 +161,16 @@ def test_fp32_real_data_shaped_standins(P, name, scale):
     _check_fp32(g, o)
 
 
+@pytest.mark.parametrize("row,dims", [(4, [40, 36, 32]), (10, [24, 22, 21, 20]), (8, [22, 21, 20, 23])])
+def test_fp32_table8_recipes(P, row, dims):
+    """Table 8 recipes (per-mode congruence, true rank 20, the second noise
+    term) at reduced mode sizes, paper extrapolation, against the oracle."""
+    prob = G.table8_problem(row, dims=dims)
+    g, o = _run(P, prob, 8, prec="fp32", tree="restructured", extrap="paper")
+    _check_fp32(g, o)
+    assert g["beta_sweep"] == o["beta_sweep"] and g["beta"] == o["beta"]
+
+
 def test_fp64_fixed_beta_extrapolation(P):
     """eq. (19) with beta fixed from sweep 2 on: the GPU applies Qhat0 through
     Y_(n) Qhat0 = (1+beta) Y_(n) Q0 - alpha beta Y_(n) Q0prev."""
