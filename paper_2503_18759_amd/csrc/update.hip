@@ -463,6 +463,325 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   }
 }
 
+// ------------------------------------------------------- half-row layout
+// finish_update for 32-column factors of at most 256 rows with 512 threads:
+// thread (wave w, lane l) holds columns 16 h .. 16 h + 15 (h = l >= 32) of
+// row 32 w + (l mod 32), so the two halves of a row sit in lanes l and l + 32
+// of one wave.  A Householder column step then updates 16 columns per lane,
+// reduces 16 values over the 32 lanes of a half-wave, and passes the next
+// column's entry between the halves with one cross-half swap; two waves per
+// SIMD hide each other's latencies.  The arithmetic per entry is that of
+// finish_update (same reflector convention, same T, WY product and explicit
+// Q); the back substitution runs row by row through LDS.
+static constexpr int FH_NT = 512;
+static constexpr int FH_NW = FH_NT / 64;
+
+// Transposed reduction of 16 doubles over each 32-lane half of the wave: on
+// exit a[0] of lane l holds the sum over the lane's half of value index
+// (l mod 32) >> 1.
+__device__ __forceinline__ void half_transpose_reduce16(double (&a)[16]) {
+  const int lane = threadIdx.x & 63;
+  static_for<0, 8>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    swap16_add(a[q], a[q + 8]);
+  });
+  static_for<0, 4>([&](auto bc) {
+    constexpr int bit = 3 - decltype(bc)::value;
+    constexpr int m = 1 << bit;
+    constexpr int ctrl = (bit == 3) ? 0x140 : (bit == 2) ? 0x141 : (bit == 1) ? 0x4E : 0xB1;
+    constexpr int half = 8 >> (4 - bit);
+    if constexpr (half >= 1) {
+      const bool upper = (lane & m) != 0;
+      static_for<0, half>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const double keep = upper ? a[q + half] : a[q];
+        const double send = upper ? a[q] : a[q + half];
+        a[q] = keep + dpp_d<ctrl>(send);
+      });
+    } else {
+      a[0] += dpp_d<ctrl>(a[0]);
+    }
+  });
+}
+
+// The value of `v` in the partner lane of the other half (l xor 32).
+__device__ __forceinline__ double other_half(double v) { return shfl_xor_d(v, 32); }
+
+__global__ __launch_bounds__(FH_NT) void finish_update_h(FinishArgs f) {
+  constexpr int RMAX = 32, HW = 16;
+  __shared__ QrSmem<RMAX> sm;            // piv, tau, beta, scale, U, T, sgn
+  __shared__ QrWySmem<RMAX> wy;
+  __shared__ double sR0[RMAX][RMAX + 1];
+  __shared__ double hred[2][FH_NW][RMAX];
+  __shared__ double hw[FH_NW][RMAX];
+  __shared__ double sA[256][RMAX + 1];   // rows between the two layouts
+  __shared__ double sred2[FH_NW][2];
+  __shared__ double slam[RMAX], sinv[RMAX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, r = 32 * wave + (lane & 31), c0 = HW * h;
+  const int I = f.I, R = f.R;
+  DevState* st = f.state;
+  const gdouble* __restrict__ gV = (const gdouble*)f.V;
+  gdouble* __restrict__ gA = (gdouble*)f.A;
+  gdouble* __restrict__ gq64 = (gdouble*)f.q64;
+  gfloat* __restrict__ gq32 = (gfloat*)f.q32;
+  for (int e = tid; e < RMAX * RMAX; e += FH_NT) {
+    const int i = e / RMAX, c = e % RMAX;
+    sR0[i][c] = (i < R && c < R) ? ((const gdouble*)f.R0)[i + R * c] : 0.0;
+  }
+  const bool active = (f.extrap != 0) && st->active;
+  const double beta = active ? st->beta : 0.0;
+  const double cp = 1.0 + beta, cq = -f.alpha * beta;
+  // Vu = (1 + beta) Vp - alpha beta Vq for this half row, <Vp,Vu>, ||Vu||^2
+  double sc[2] = {0.0, 0.0};
+  {
+    double lp[HW], lq[HW];
+#pragma unroll
+    for (int u = 0; u < HW; ++u) {
+      const int c = c0 + u;
+      const int64_t e = (r < I && c < R) ? r + (int64_t)I * c : 0;
+      lp[u] = gV[e];
+      lq[u] = gV[(int64_t)I * R + e];
+    }
+#pragma unroll
+    for (int u = 0; u < HW; ++u) {
+      const int c = c0 + u;
+      const bool in = r < I && c < R;
+      const double vp = in ? lp[u] : 0.0, vq = in ? lq[u] : 0.0;
+      const double vu = active ? fma(cq, vq, cp * vp) : vp;
+      sc[0] = fma(vp, vu, sc[0]);
+      sc[1] = fma(vu, vu, sc[1]);
+      sA[r][c] = vu;
+    }
+  }
+  block_allreduce<2, FH_NW>(sc, sred2);   // its barriers also publish sR0 and sA
+  int bad = 0;
+  for (int c = 0; c < R; ++c)
+    if (!(sR0[c][c] != 0.0)) bad |= FLAG_RANKDEF;
+  // back substitution of R0 ahat = vu, one row per thread of the first four
+  // waves, in place in sA
+  if (tid < 256) {
+    double x[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) x[c] = sA[tid][c];
+    static_for<0, RMAX>([&](auto ic) {
+      constexpr int c = RMAX - 1 - decltype(ic)::value;
+      double s = x[c];
+      static_for<c + 1, RMAX>([&](auto dc) {
+        constexpr int d = decltype(dc)::value;
+        s = fma(-sR0[c][d], x[d], s);
+      });
+      x[c] = (c < R && tid < I && sR0[c][c] != 0.0) ? s / sR0[c][c] : 0.0;
+      __builtin_amdgcn_sched_barrier(0);
+    });
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) sA[tid][c] = x[c];
+  }
+  __syncthreads();
+  // lambda = column norms of Ahat; A = Ahat / lambda
+  // the half row in one register vector (a variable index into it is an
+  // indexed register move; into a plain array it would go to scratch)
+  f64x16 a;
+#pragma unroll
+  for (int u = 0; u < HW; ++u) a[u] = sA[r][c0 + u];
+  {
+    double cn[HW];
+#pragma unroll
+    for (int u = 0; u < HW; ++u) cn[u] = a[u] * a[u];
+    half_transpose_reduce16(cn);
+    if ((lane & 1) == 0) hred[0][wave][c0 + ((lane & 31) >> 1)] = cn[0];
+  }
+  __syncthreads();
+  if (tid < RMAX) {
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < FH_NW; ++w) tot += hred[0][w][tid];
+    const double lam = sqrt(tot);
+    slam[tid] = lam;
+    sinv[tid] = (tid < R && lam != 0.0) ? 1.0 / lam : 0.0;
+    if (tid < R) ((gdouble*)f.lambda)[tid] = lam;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int c = 0; c < R; ++c) {
+      if (slam[c] == 0.0) bad |= FLAG_RANKDEF;
+      if (!isfinite(slam[c])) bad |= FLAG_NONFINITE;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < HW; ++u) {
+    const int c = c0 + u;
+    a[u] = a[u] * sinv[c];
+    if (r < I && c < R) gA[r + (int64_t)I * c] = a[u];
+  }
+  // Householder QR of A (rows beyond I are zero)
+  {
+    // column 0 lives in half 0.  The cross-lane read runs on every lane
+    // before the select: inside a branch only the reading half would be
+    // active, and a read from an inactive lane returns zero.
+    const double own0 = a[0];
+    const double oth0 = other_half(own0);
+    const double x0v = (h == 0) ? own0 : oth0;
+    double x = (r > 0) ? x0v : 0.0;
+    double part[HW];
+#pragma unroll
+    for (int u = 0; u < HW; ++u) part[u] = x * a[u];
+    if (r == 0) {
+#pragma unroll
+      for (int u = 0; u < HW; ++u) sm.piv[0][c0 + u] = a[u];
+    }
+    // (x of half 1 is its partner's column-0 entry, so every lane of a row
+    // holds the same x)
+    for (int j = 0; j < R; ++j) {
+      const int buf = j & 1;
+      half_transpose_reduce16(part);
+      if ((lane & 1) == 0) hred[buf][wave][c0 + ((lane & 31) >> 1)] = part[0];
+      __syncthreads();
+      double tot = 0.0, pc = 0.0, scl = 0.0;
+      const double xp = sm.piv[buf][j];
+      if (lane < RMAX) {
+        double rv[FH_NW];
+#pragma unroll
+        for (int w = 0; w < FH_NW; ++w) rv[w] = hred[buf][w][lane];
+        pc = sm.piv[buf][lane];
+        scl = sm.scale[lane];
+#pragma unroll
+        for (int w = 0; w < FH_NW; ++w) tot += rv[w];
+      }
+      const double stv = lane_read(tot, j);
+      double tau, bet, scale;
+      qr_reflector_scalars(xp, stv, &tau, &bet, &scale);
+      if (lane < RMAX) {
+        const double wu = fma(scale, tot, pc);
+        hw[wave][lane] = (lane > j) ? wu : 0.0;
+        if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * scl : 0.0;
+      }
+      if (wave == 0 && lane == 0) {
+        sm.tau[j] = tau;
+        sm.beta[j] = bet;
+        sm.scale[j] = scale;
+      }
+      // this wave's own copy of w, read back in order (one wave's LDS
+      // operations complete in order)
+      double wv[HW];
+#pragma unroll
+      for (int u = 0; u < HW; ++u) wv[u] = hw[wave][c0 + u];
+      const int jn = j + 1;
+      const double coef = (r > j) ? tau * x * scale : ((r == j) ? tau : 0.0);
+      const int jc = jn < RMAX ? jn : 0;
+      const double wn = hw[wave][jc];
+      // the next column's entry of this row, updated, from the half that
+      // holds it
+      const double cand = fma(-coef, wn, a[jc & (HW - 1)]);
+      const double oth = other_half(cand);
+      const double an = (jn < RMAX) ? (((jc >> 4) == h) ? cand : oth) : 0.0;
+      const double xn = (r > jn) ? an : 0.0;
+#pragma unroll
+      for (int u = 0; u < HW; ++u) {
+        const double v = fma(-coef, wv[u], a[u]);
+        a[u] = v;
+        part[u] = xn * v;
+      }
+      x = xn;
+      if (r == jn && jn < R) {
+#pragma unroll
+        for (int u = 0; u < HW; ++u) sm.piv[buf ^ 1][c0 + u] = a[u];
+      }
+    }
+  }
+  __syncthreads();
+  block_qr_build_t<RMAX>(R, sm);
+  // publish V1 and R (rows 0..31: wave 0) with the sign fix
+  if (wave == 0) {
+    const int row = lane & 31;
+    const double sg = (row < R && sm.beta[row] < 0.0) ? -1.0 : 1.0;
+    if (h == 0) sm.sgn[row] = sg;
+#pragma unroll
+    for (int u = 0; u < HW; ++u) {
+      const int c = c0 + u;
+      const bool in = (row < R) && (c < R);
+      const double v = (row > c) ? a[u] * sm.scale[c] : ((row == c) ? 1.0 : 0.0);
+      const double rr = (c > row) ? a[u] : ((c == row) ? sm.beta[row] : 0.0);
+      wy.V1[row][c] = in ? v : 0.0;
+      wy.Rm[row][c] = in ? sg * rr : 0.0;
+    }
+  }
+  __syncthreads();
+  block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
+  for (int e = tid; e < R * R; e += FH_NT) {
+    const int i = e % R, c = e / R;
+    ((gdouble*)f.Rn)[e] = wy.Rm[i][c];
+  }
+  // explicit Q rows: the whole row of V (both halves), then this half's 16
+  // columns
+  {
+    double vown[HW];
+#pragma unroll
+    for (int u = 0; u < HW; ++u) {
+      const int c = c0 + u;
+      vown[u] = (c < R) ? ((r > c) ? a[u] * sm.scale[c] : ((r == c) ? 1.0 : 0.0)) : 0.0;
+    }
+    double vlo[HW], vhi[HW];
+#pragma unroll
+    for (int u = 0; u < HW; ++u) {
+      const double o = other_half(vown[u]);
+      vlo[u] = (h == 0) ? vown[u] : o;
+      vhi[u] = (h == 0) ? o : vown[u];
+    }
+    for (int cc = 0; cc < HW; cc += 2) {
+      const int c = c0 + cc;
+      double a0 = (r == c) ? 1.0 : 0.0, a1 = (r == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
+      {
+        double m0[HW], m1[HW];
+#pragma unroll
+        for (int m = 0; m < HW; ++m) {
+          m0[m] = wy.Mt[c][m];
+          m1[m] = wy.Mt[c + 1][m];
+        }
+#pragma unroll
+        for (int m = 0; m < HW; m += 2) {
+          a0 = fma(-vlo[m], m0[m], a0);
+          a1 = fma(-vlo[m], m1[m], a1);
+          b0 = fma(-vlo[m + 1], m0[m + 1], b0);
+          b1 = fma(-vlo[m + 1], m1[m + 1], b1);
+        }
+      }
+      {
+        double m0[HW], m1[HW];
+#pragma unroll
+        for (int m = 0; m < HW; ++m) {
+          m0[m] = wy.Mt[c][HW + m];
+          m1[m] = wy.Mt[c + 1][HW + m];
+        }
+#pragma unroll
+        for (int m = 0; m < HW; m += 2) {
+          a0 = fma(-vhi[m], m0[m], a0);
+          a1 = fma(-vhi[m], m1[m], a1);
+          b0 = fma(-vhi[m + 1], m0[m + 1], b0);
+          b1 = fma(-vhi[m + 1], m1[m + 1], b1);
+        }
+      }
+      if (r < I) {
+        if (c < R) {
+          const double q = (a0 + b0) * sm.sgn[c];
+          if (gq64) gq64[r + (int64_t)I * c] = q;
+          if (gq32) gq32[r + (int64_t)I * c] = (float)q;
+        }
+        if (c + 1 < R) {
+          const double q = (a1 + b1) * sm.sgn[c + 1];
+          if (gq64) gq64[r + (int64_t)I * (c + 1)] = q;
+          if (gq32) gq32[r + (int64_t)I * (c + 1)] = (float)q;
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    for (int c = 0; c < R && c < I; ++c)
+      if (!(wy.Rm[c][c] > 0.0)) bad |= FLAG_RANKDEF;
+    finish_state_tail(f, st, sc, bad);
+  }
+}
+
 // ------------------------------------------------------------ tall factors
 // A mode with more rows than the single-workgroup factor QR holds in
 // registers: this kernel streams the rows in chunks of its 256 threads for
@@ -615,6 +934,11 @@ static hipError_t finish_launch(int rm, int rp, unsigned blocks, const FinishArg
 
 hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
   if (f.I > CPQR_MAX_FACTOR_ROWS) return hipErrorInvalidValue;
+  if (qr_rmax(f.R) == 32 && f.I <= 256) {
+    // half-row layout: 512 threads, rows r < 256
+    hipLaunchKernelGGL(finish_update_h, dim3(1), dim3(FH_NT), 0, st, f);
+    return hipGetLastError();
+  }
   return finish_launch(qr_rmax(f.R), factor_rpt(f.I), 1, f, nullptr, st);
 }
 
