@@ -1,5 +1,5 @@
-// Householder QR kernels (Section 2.4 / Algorithm 2, lines "QR of the factor
-// matrices" and "QR decomposition Z_n = Q0 R0").
+// Householder QR kernels (Section 2.4 and Algorithm 2: the QR of every factor
+// matrix and the QR decomposition Z_n = Q0 R0 of each mode update).
 //
 //  * zqr_leaf:  TSQR leaves of Z_n = R_N (.) ... (.) R_{n+1} (.) R_{n-1} (.) ... (.) R_1
 //               (Khatri-Rao of the R factors, rows in the Kolda order of the

@@ -485,14 +485,15 @@ __device__ __forceinline__ void block_qr_publish(const QrRow<RMAX>& row0, int R,
 // wy.Mt = (T * (V1^T * B))^T where B (R x R) is row-major in LDS with leading
 // dimension ldb, or B = I when B == nullptr.  The inner products run over
 // the full (zero-padded) RMAX range, unrolled, so that their LDS reads are
-// issued together rather than one loop trip at a time.
-template <int RMAX>
+// issued together rather than one loop trip at a time.  NTH is the
+// workgroup's thread count.
+template <int RMAX, int NTH = QrCfg<RMAX>::NT>
 __device__ __forceinline__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWySmem<RMAX>& wy, int R,
                                                     const double* B, int ldb) {
   const int tid = threadIdx.x;
   if (B != nullptr) {
     // W = V1^T B (V1 is zero above its unit diagonal and beyond R)
-    for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
+    for (int e = tid; e < RMAX * RMAX; e += NTH) {
       const int k = e / RMAX, c = e % RMAX;
       double acc = 0.0;
 #pragma unroll
@@ -500,14 +501,14 @@ __device__ __forceinline__ void block_qr_wy_product(const QrSmem<RMAX>& sm, QrWy
       wy.W[k][c] = acc;
     }
   } else {
-    for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
+    for (int e = tid; e < RMAX * RMAX; e += NTH) {
       const int k = e / RMAX, c = e % RMAX;
       wy.W[k][c] = wy.V1[c][k];
     }
   }
   __syncthreads();
   // M = T W (T is zero below its diagonal and beyond R)
-  for (int e = tid; e < RMAX * RMAX; e += QrCfg<RMAX>::NT) {
+  for (int e = tid; e < RMAX * RMAX; e += NTH) {
     const int k = e / RMAX, c = e % RMAX;
     double tk[RMAX], wc[RMAX];
 #pragma unroll

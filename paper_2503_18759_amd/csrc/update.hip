@@ -1,5 +1,6 @@
-// Mode-update kernels of QR-based ALS (Algorithm 2 lines 6-9, Algorithm 3
-// lines 5 and 7-10) and the norm kernels of the fit (Section 4.1).
+// Mode-update kernels of QR-based ALS (Algorithm 2: the product with Q0, the
+// triangular solve and the factor QR; Algorithm 3: the same update with the
+// extrapolated Q0) and the norm kernels of the fit (Section 4.1).
 //
 //  * apply_partial / apply_reduce:  [Vp | Vq] = Y_(n) [Q0 | Q0prev] in float64
 //    (Y_(n) columns in the Kolda order of the remaining modes, i.e. column
@@ -11,6 +12,10 @@
 //    fit, back substitution of Ahat R0^T = Vu, lambda = column norms,
 //    A = Ahat / lambda, Householder QR of A -> Q_n, R_n; after the last update
 //    of a sweep the fit and the extrapolation activation rule.
+//    finish_update_h does the same for rank class 32 and up to 256 rows with
+//    each row split over the two halves of a wave.
+//  * finish_tall / tall_factor_tail: the same update for modes beyond the
+//    single-workgroup factor QR (the factor QR then goes through the TSQR).
 //  * sumsq / residual: ||X||^2 and ||X - K||^2 with float64 accumulation.
 #include "common.h"
 #include "kernels.h"
@@ -707,7 +712,7 @@ __global__ __launch_bounds__(FH_NT) void finish_update_h(FinishArgs f) {
     }
   }
   __syncthreads();
-  block_qr_wy_product<RMAX>(sm, wy, R, nullptr, 0);
+  block_qr_wy_product<RMAX, FH_NT>(sm, wy, R, nullptr, 0);
   for (int e = tid; e < R * R; e += FH_NT) {
     const int i = e % R, c = e / R;
     ((gdouble*)f.Rn)[e] = wy.Rm[i][c];
