@@ -42,6 +42,8 @@ struct cpqr_handle {
   hipStream_t stream = nullptr;       // stream the library launches on
   bool own_stream = false;
   hipEvent_t ready = nullptr;
+  // second stream (default priority) for the Z QR branch of captured sweeps
+  hipStream_t side = nullptr;
   std::string err;
   std::map<std::string, DevBuf> bufs;
   bool busy = false;                  // a session is using the workspace
@@ -174,7 +176,8 @@ struct cpqr_session {
   int l1_count = 0;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   bool t0_recorded = false;
-  std::vector<hipEvent_t> evs;
+  std::vector<hipEvent_t> evs;        // timing pairs of the level-1 TTMs
+  std::vector<hipEvent_t> fork_evs;   // fork/join events of captured sweeps
   std::map<std::string, hipGraphExec_t> graphs;
   // learned extrapolation
   float* mlp_w = nullptr;        // device weights
@@ -186,6 +189,7 @@ struct cpqr_session {
   ~cpqr_session() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    for (hipEvent_t e : fork_evs) (void)hipEventDestroy(e);
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
   }
@@ -443,13 +447,26 @@ StairArgs stair_args(const TsqrArgs& t) {
   return StairArgs{t.N, t.n, t.R, t.M, t.rf, t.R0, t.Q0, 1};
 }
 
-hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
-                         hipStream_t s) {
+// The QR Z_n = Q0 R0 of a mode update.  It reads only the R factors, so it
+// may run beside the TTMs that produce the same update's Y_(n).
+hipError_t launch_zqr(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o, hipStream_t s) {
   TsqrArgs t;
   ApplyArgs a;
   FinishArgs f;
   update_args(p, n, sweep_k, last, o, &t, &a, &f);
-  hipError_t e = p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
+  return p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
+}
+
+// One mode update; with zqr_done the Z QR has been enqueued already (on a
+// branch that the stream has joined).
+hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
+                         hipStream_t s, bool zqr_done = false) {
+  TsqrArgs t;
+  ApplyArgs a;
+  FinishArgs f;
+  update_args(p, n, sweep_k, last, o, &t, &a, &f);
+  hipError_t e = hipSuccess;
+  if (!zqr_done) e = p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
   if (e != hipSuccess) return e;
   e = launch_apply(a, s);
   if (e != hipSuccess) return e;
@@ -579,6 +596,7 @@ cpqr_status cpqr_destroy(cpqr_handle* h) {
   for (auto& kv : h->bufs)
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (h->ready) (void)hipEventDestroy(h->ready);
+  if (h->side) (void)hipStreamDestroy(h->side);
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return CPQR_OK;
@@ -809,7 +827,58 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
   int last_update = -1;
   for (size_t i = 0; i < sw.size(); ++i)
     if (sw[i].kind == STEP_UPDATE) last_update = (int)i;
+  // In a captured sweep with the staircase Z QR, each update's Z QR (one
+  // workgroup) is forked onto the side stream as soon as the previous update
+  // is enqueued, so that it runs beside the TTMs producing the same update's
+  // Y_(n); the update joins the branch before its product with Q0.  (Measured
+  // at 256^3 rank 32: forking every update beats forking only those behind a
+  // level-1 TTM; the fork and join cost less than a level-2 TTM.)
+  bool fork = use_graph && p.stair.ok;
+  if (fork && h->side == nullptr &&
+      hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    h->side = nullptr;
+    fork = false;
+  }
+  // fork and join events of the captured branches, created before capture
+  std::vector<hipEvent_t> fev;
+  size_t fnext = 0;
+  auto make_fork_events = [&]() -> hipError_t {
+    for (const Step& st : sw) {
+      if (st.kind != STEP_UPDATE) continue;
+      for (int r = 0; r < 2; ++r) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        S->fork_evs.push_back(ev);
+        fev.push_back(ev);
+      }
+    }
+    return hipSuccess;
+  };
   auto enqueue = [&](hipStream_t q) -> hipError_t {
+    hipEvent_t join = nullptr;   // end of the forked Z QR of the next update
+    bool forked = false;         // the next update's Z QR is on the side branch
+    auto fork_next = [&](size_t from) -> hipError_t {
+      size_t j = from;
+      while (j < sw.size() && sw[j].kind != STEP_UPDATE) ++j;
+      forked = false;
+      if (j == sw.size()) return hipSuccess;
+      if (fnext + 2 > fev.size()) return hipErrorInvalidValue;
+      hipEvent_t a = fev[fnext++], b = fev[fnext++];
+      hipError_t e;
+      if ((e = hipEventRecord(a, q)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(h->side, a, 0)) != hipSuccess) return e;
+      if ((e = launch_zqr(p, sw[j].mode, k, (int)j == last_update, o, h->side)) != hipSuccess) return e;
+      if ((e = hipEventRecord(b, h->side)) != hipSuccess) return e;
+      join = b;
+      forked = true;
+      return hipSuccess;
+    };
+    if (fork) {
+      hipError_t e = fork_next(0);
+      if (e != hipSuccess) return e;
+    }
     for (size_t i = 0; i < sw.size(); ++i) {
       const Step& st = sw[i];
       hipError_t e;
@@ -845,6 +914,11 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
         } else {
           if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
         }
+      } else if (fork) {
+        const bool z = forked;
+        if (z && (e = hipStreamWaitEvent(q, join, 0)) != hipSuccess) return e;
+        if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q, z)) != hipSuccess) return e;
+        if ((e = fork_next(i + 1)) != hipSuccess) return e;
       } else {
         if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q)) != hipSuccess) return e;
       }
@@ -857,6 +931,7 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
     auto itg = S->graphs.find(key);
     if (itg == S->graphs.end()) {
       hipGraph_t g;
+      if (fork) HIP_TRY(h, make_fork_events());
       HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       hipError_t e = enqueue(s);
       hipError_t e2 = hipStreamEndCapture(s, &g);

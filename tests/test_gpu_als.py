@@ -237,6 +237,24 @@ def test_graph_replay_matches_eager(P):
         assert np.array_equal(u, v)
 
 
+@pytest.mark.parametrize("tree", ["restructured", "standard"])
+def test_graph_replay_with_forked_zqr_matches_eager(P, tree):
+    """Captured sweeps run each update's staircase Z QR on a side branch of
+    the graph, beside the TTMs of the same update; eager launches run every
+    kernel in order on one stream.  Same kernels, same inputs: the results
+    must agree bit for bit (order 3, rank class 32, extrapolation on so that
+    the Q0 ping-pong buffers of both parities are used)."""
+    prob = G.make_problem([40, 50, 60], 17, seed=83, rho=0.01, dtype=np.float32)
+    x, dims = P.to_device(prob.X)
+    kw = dict(dims=dims, tree=tree, extrapolate="paper", switch_delta=0.5)
+    a = P.cp_als_qr(x, prob.rank, prob.init, 12, use_graph=True, **kw)
+    b = P.cp_als_qr(x, prob.rank, prob.init, 12, use_graph=False, **kw)
+    assert np.array_equal(a["fits"], b["fits"])
+    assert np.array_equal(a["lam"], b["lam"])
+    for u, v in zip(a["factors"], b["factors"]):
+        assert np.array_equal(u, v)
+
+
 def test_tolerance_stop(P):
     """Stopping rule |fit_k - fit_{k-1}| < tol (float64 chain, so that the
     fit of Section 4.1 is accurate enough to settle below tol)."""
