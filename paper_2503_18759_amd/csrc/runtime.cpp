@@ -827,13 +827,14 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
   int last_update = -1;
   for (size_t i = 0; i < sw.size(); ++i)
     if (sw[i].kind == STEP_UPDATE) last_update = (int)i;
-  // In a captured sweep with the staircase Z QR, each update's Z QR (one
-  // workgroup) is forked onto the side stream as soon as the previous update
-  // is enqueued, so that it runs beside the TTMs producing the same update's
-  // Y_(n); the update joins the branch before its product with Q0.  (Measured
-  // at 256^3 rank 32: forking every update beats forking only those behind a
-  // level-1 TTM; the fork and join cost less than a level-2 TTM.)
-  bool fork = use_graph && p.stair.ok;
+  // In a captured sweep each update's Z QR (the one-workgroup staircase
+  // kernel, or the TSQR's few workgroups) is forked onto the side stream as
+  // soon as the previous update is enqueued, so that it runs beside the TTMs
+  // producing the same update's Y_(n); the update joins the branch before its
+  // product with Q0.  (Measured at 256^3 rank 32: forking every update beats
+  // forking only those behind a level-1 TTM; the fork and join cost less
+  // than a level-2 TTM.)
+  bool fork = use_graph;
   if (fork && h->side == nullptr &&
       hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();

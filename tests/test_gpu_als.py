@@ -237,16 +237,24 @@ def test_graph_replay_matches_eager(P):
         assert np.array_equal(u, v)
 
 
-@pytest.mark.parametrize("tree", ["restructured", "standard"])
-def test_graph_replay_with_forked_zqr_matches_eager(P, tree):
-    """Captured sweeps run each update's staircase Z QR on a side branch of
-    the graph, beside the TTMs of the same update; eager launches run every
-    kernel in order on one stream.  Same kernels, same inputs: the results
-    must agree bit for bit (order 3, rank class 32, extrapolation on so that
-    the Q0 ping-pong buffers of both parities are used)."""
-    prob = G.make_problem([40, 50, 60], 17, seed=83, rho=0.01, dtype=np.float32)
+@pytest.mark.parametrize("case", [
+    ("stair_o3", "restructured"), ("stair_o3", "standard"),
+    ("dense_o3", "restructured"), ("tsqr_o4", "restructured"), ("tsqr_o4", "standard")])
+def test_graph_replay_with_forked_zqr_matches_eager(P, case):
+    """Captured sweeps run each update's Z QR (staircase kernel or TSQR) on a
+    side branch of the graph, beside the TTMs of the same update; eager
+    launches run every kernel in order on one stream.  Same kernels, same
+    inputs: the results must agree bit for bit (extrapolation on so that the
+    Q0 ping-pong buffers of both parities are used)."""
+    kind, tree = case
+    if kind == "tsqr_o4":
+        # R^3 = 1728 rows of Z_n: beyond the staircase kernel, two-level TSQR
+        prob = G.make_problem([20, 18, 16, 14], 12, seed=84, rho=0.01, dtype=np.float32)
+    else:
+        prob = G.make_problem([40, 50, 60], 17, seed=83, rho=0.01, dtype=np.float32)
     x, dims = P.to_device(prob.X)
-    kw = dict(dims=dims, tree=tree, extrapolate="paper", switch_delta=0.5)
+    kw = dict(dims=dims, tree=tree, extrapolate="paper", switch_delta=0.5,
+              zqr="dense" if kind == "dense_o3" else "stair")
     a = P.cp_als_qr(x, prob.rank, prob.init, 12, use_graph=True, **kw)
     b = P.cp_als_qr(x, prob.rank, prob.init, 12, use_graph=False, **kw)
     assert np.array_equal(a["fits"], b["fits"])
