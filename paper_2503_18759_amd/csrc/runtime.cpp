@@ -1243,9 +1243,11 @@ struct BatchRun {
   cpqr_handle* h = nullptr;
   std::vector<cpqr_session*> S;
   std::map<std::string, hipGraphExec_t> graphs;
+  std::vector<hipEvent_t> fork_evs;   // fork/join events of the captured sweeps
   std::map<std::string, int> tuned_ks;
   ~BatchRun() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipEvent_t e : fork_evs) (void)hipEventDestroy(e);
     for (cpqr_session* x : S) delete x;
   }
 };
@@ -1561,11 +1563,63 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
       char* dblob = nullptr;
       WS(h, "batch:args:" + key, blob.size() + 64, dblob);
       HIP_TRY(h, hipMemcpy(dblob, blob.data(), blob.size(), hipMemcpyHostToDevice));
+      // As in the single-problem sweep, each update's Z QR groups (kinds 1
+      // and 4, contiguous in the plan) run on the side stream beside the
+      // TTM groups of the same update, forked after the previous update's
+      // finish groups and joined before the update's first Y*Q0 group.
+      const bool bfork = (h->side != nullptr) ||
+                         (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess);
+      if (!bfork) {
+        (void)hipGetLastError();
+        h->side = nullptr;
+      }
+      std::vector<hipEvent_t> bev;
+      if (bfork) {
+        for (const BatchItem& it : items)
+          if (it.kind == 2) {
+            for (int r = 0; r < 2; ++r) {
+              hipEvent_t ev;
+              HIP_TRY(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+              B.fork_evs.push_back(ev);
+              bev.push_back(ev);
+            }
+          }
+      }
+      const size_t ni = items.size();
+      auto is_qr = [&](size_t i) { return items[i].kind == 1 || items[i].kind == 4; };
       hipGraph_t g;
       HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipSuccess;
-      for (const BatchItem& it : items)
-        if ((e = launch_item(it, dblob, s)) != hipSuccess) break;
+      size_t qr_end = 0, bnext = 0;   // end of the forked QR groups; next event pair
+      hipEvent_t join = nullptr;
+      auto fork_from = [&](size_t from) -> hipError_t {
+        size_t j = from;
+        while (j < ni && !is_qr(j) && items[j].kind != 2) ++j;
+        if (j == ni || !is_qr(j)) return hipSuccess;
+        size_t j2 = j;
+        while (j2 < ni && is_qr(j2)) ++j2;
+        if (bnext + 2 > bev.size()) return hipErrorInvalidValue;
+        hipEvent_t a = bev[bnext++], b = bev[bnext++];
+        hipError_t ee;
+        if ((ee = hipEventRecord(a, s)) != hipSuccess) return ee;
+        if ((ee = hipStreamWaitEvent(h->side, a, 0)) != hipSuccess) return ee;
+        for (size_t q = j; q < j2; ++q)
+          if ((ee = launch_item(items[q], dblob, h->side)) != hipSuccess) return ee;
+        if ((ee = hipEventRecord(b, h->side)) != hipSuccess) return ee;
+        join = b;
+        qr_end = j2;
+        return hipSuccess;
+      };
+      if (bfork) e = fork_from(0);
+      for (size_t i = 0; i < ni && e == hipSuccess; ++i) {
+        if (bfork && is_qr(i) && i < qr_end) continue;   // already on the side branch
+        if (bfork && items[i].kind == 2 && join != nullptr) {
+          if ((e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) break;
+          join = nullptr;
+        }
+        if ((e = launch_item(items[i], dblob, s)) != hipSuccess) break;
+        if (bfork && items[i].kind == 3 && (i + 1 == ni || items[i + 1].kind != 3)) e = fork_from(i + 1);
+      }
       hipError_t e2 = hipStreamEndCapture(s, &g);
       if (e != hipSuccess) return fail(h, CPQR_EHIP, "batched launch during capture failed: %s", hipGetErrorString(e));
       if (e2 != hipSuccess) return fail(h, CPQR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e2));
