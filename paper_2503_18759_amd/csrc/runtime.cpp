@@ -142,7 +142,7 @@ struct Problem {
   // factor TSQR of modes with more than CPQR_MAX_FACTOR_ROWS rows (sized for
   // the largest such mode; fQ holds Q_n in float64 for the float32 chain)
   double *fV = nullptr, *fT = nullptr, *fStack = nullptr, *fQtop = nullptr, *fQ = nullptr;
-  double *partial = nullptr, *Vbuf = nullptr;
+  double *partial = nullptr, *Vbuf = nullptr, *qnbuf = nullptr;
   DevState* state = nullptr;
   double* fit_hist = nullptr;
   double* norm_part = nullptr;
@@ -247,6 +247,7 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   p.nchunks_max = nch;
   WS(h, p.prefix + "partial", (size_t)nch * 2 * p.Imax * R * 8, p.partial);
   WS(h, p.prefix + "V", (size_t)2 * p.Imax * R * 8, p.Vbuf);
+  WS(h, p.prefix + "qn", (size_t)CPQR_QN_WORDS * 8, p.qnbuf);
   WS(h, p.prefix + "state", sizeof(DevState), p.state);
   p.carried.clear();
   for (int k = 0; k < N; ++k) {
@@ -396,6 +397,7 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   f->I = (int)p.dims[n];
   f->R = R;
   f->V = p.Vbuf;
+  f->qn = p.qnbuf;
   f->R0 = p.R0;
   f->A = p.A[n];
   f->lambda = p.lambda;
@@ -458,9 +460,12 @@ hipError_t launch_zqr(const Problem& p, int n, int sweep_k, bool last, const cpq
 }
 
 // One mode update; with zqr_done the Z QR has been enqueued already (on a
-// branch that the stream has joined).
+// branch that the stream has joined).  With tail given, a Q_n kernel that
+// only the following TTMs need is left to the caller (*tail_pending set,
+// its arguments in *tail).
 hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
-                         hipStream_t s, bool zqr_done = false) {
+                         hipStream_t s, bool zqr_done = false, FinishArgs* tail = nullptr,
+                         bool* tail_pending = nullptr) {
   TsqrArgs t;
   ApplyArgs a;
   FinishArgs f;
@@ -470,7 +475,11 @@ hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const 
   if (e != hipSuccess) return e;
   e = launch_apply(a, s);
   if (e != hipSuccess) return e;
-  if (p.dims[n] <= CPQR_MAX_FACTOR_ROWS) return launch_finish(f, s);
+  if (p.dims[n] <= CPQR_MAX_FACTOR_ROWS) {
+    if (tail == nullptr) return launch_finish(f, s);
+    *tail = f;
+    return launch_finish_head(f, s, tail_pending);
+  }
   e = launch_finish_tall(f, s);
   if (e != hipSuccess) return e;
   return launch_tall_factor_qr(p, n, p.state, s);
@@ -918,8 +927,14 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
       } else if (fork) {
         const bool z = forked;
         if (z && (e = hipStreamWaitEvent(q, join, 0)) != hipSuccess) return e;
-        if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q, z)) != hipSuccess) return e;
+        // the next update's Z QR needs R_n only: fork it before the Q_n
+        // kernel, which only the following TTMs wait for
+        FinishArgs ft{};
+        bool tail = false;
+        if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q, z, &ft, &tail)) != hipSuccess)
+          return e;
         if ((e = fork_next(i + 1)) != hipSuccess) return e;
+        if (tail && (e = launch_finish_tail(ft, q)) != hipSuccess) return e;
       } else {
         if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q)) != hipSuccess) return e;
       }

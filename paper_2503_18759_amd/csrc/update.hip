@@ -712,78 +712,69 @@ __global__ __launch_bounds__(FH_NT) void finish_update_h(FinishArgs f) {
     }
   }
   __syncthreads();
-  block_qr_wy_product<RMAX, FH_NT>(sm, wy, R, nullptr, 0);
   for (int e = tid; e < R * R; e += FH_NT) {
     const int i = e % R, c = e / R;
     ((gdouble*)f.Rn)[e] = wy.Rm[i][c];
   }
-  // explicit Q rows: the whole row of V (both halves), then this half's 16
-  // columns
+  // hand the reflectors to form_qn_h: rows r < I of V (I x R, column-major),
+  // the published V1 and T (RMAX x RMAX, row-major) and the signs
   {
-    double vown[HW];
+    gdouble* __restrict__ qv = (gdouble*)f.qn;
+    gdouble* __restrict__ qv1 = qv + 256 * RMAX;
+    gdouble* __restrict__ qt = qv1 + RMAX * RMAX;
+    gdouble* __restrict__ qs = qt + RMAX * RMAX;
 #pragma unroll
     for (int u = 0; u < HW; ++u) {
       const int c = c0 + u;
-      vown[u] = (c < R) ? ((r > c) ? a[u] * sm.scale[c] : ((r == c) ? 1.0 : 0.0)) : 0.0;
+      const double v = (c < R) ? ((r > c) ? a[u] * sm.scale[c] : ((r == c) ? 1.0 : 0.0)) : 0.0;
+      if (r < I && c < R) qv[r + (int64_t)I * c] = v;
     }
-    double vlo[HW], vhi[HW];
-#pragma unroll
-    for (int u = 0; u < HW; ++u) {
-      const double o = other_half(vown[u]);
-      vlo[u] = (h == 0) ? vown[u] : o;
-      vhi[u] = (h == 0) ? o : vown[u];
+    for (int e = tid; e < RMAX * RMAX; e += FH_NT) {
+      const int k = e / RMAX, c = e % RMAX;
+      qv1[e] = wy.V1[k][c];
+      qt[e] = sm.T[k][c];
     }
-    for (int cc = 0; cc < HW; cc += 2) {
-      const int c = c0 + cc;
-      double a0 = (r == c) ? 1.0 : 0.0, a1 = (r == c + 1) ? 1.0 : 0.0, b0 = 0.0, b1 = 0.0;
-      {
-        double m0[HW], m1[HW];
-#pragma unroll
-        for (int m = 0; m < HW; ++m) {
-          m0[m] = wy.Mt[c][m];
-          m1[m] = wy.Mt[c + 1][m];
-        }
-#pragma unroll
-        for (int m = 0; m < HW; m += 2) {
-          a0 = fma(-vlo[m], m0[m], a0);
-          a1 = fma(-vlo[m], m1[m], a1);
-          b0 = fma(-vlo[m + 1], m0[m + 1], b0);
-          b1 = fma(-vlo[m + 1], m1[m + 1], b1);
-        }
-      }
-      {
-        double m0[HW], m1[HW];
-#pragma unroll
-        for (int m = 0; m < HW; ++m) {
-          m0[m] = wy.Mt[c][HW + m];
-          m1[m] = wy.Mt[c + 1][HW + m];
-        }
-#pragma unroll
-        for (int m = 0; m < HW; m += 2) {
-          a0 = fma(-vhi[m], m0[m], a0);
-          a1 = fma(-vhi[m], m1[m], a1);
-          b0 = fma(-vhi[m + 1], m0[m + 1], b0);
-          b1 = fma(-vhi[m + 1], m1[m + 1], b1);
-        }
-      }
-      if (r < I) {
-        if (c < R) {
-          const double q = (a0 + b0) * sm.sgn[c];
-          if (gq64) gq64[r + (int64_t)I * c] = q;
-          if (gq32) gq32[r + (int64_t)I * c] = (float)q;
-        }
-        if (c + 1 < R) {
-          const double q = (a1 + b1) * sm.sgn[c + 1];
-          if (gq64) gq64[r + (int64_t)I * (c + 1)] = q;
-          if (gq32) gq32[r + (int64_t)I * (c + 1)] = (float)q;
-        }
-      }
-    }
+    if (tid < RMAX) qs[tid] = sm.sgn[tid];
   }
   if (tid == 0) {
     for (int c = 0; c < R && c < I; ++c)
       if (!(wy.Rm[c][c] > 0.0)) bad |= FLAG_RANKDEF;
     finish_state_tail(f, st, sc, bad);
+  }
+}
+
+// Explicit Q_n = (E - V M) diag(sgn), M = T V1^T, of the half-row factor QR
+// from what finish_update_h leaves in f.qn: the same WY product and the same
+// row arithmetic (wy_q_row) as the single-kernel path, one row per thread.
+__global__ __launch_bounds__(256) void form_qn_h(FinishArgs f) {
+  constexpr int RMAX = 32;
+  __shared__ QrSmem<RMAX> sm;
+  __shared__ QrWySmem<RMAX> wy;
+  const int tid = threadIdx.x;
+  const int I = f.I, R = f.R;
+  const gdouble* __restrict__ qv = (const gdouble*)f.qn;
+  const gdouble* __restrict__ qv1 = qv + 256 * RMAX;
+  const gdouble* __restrict__ qt = qv1 + RMAX * RMAX;
+  const gdouble* __restrict__ qs = qt + RMAX * RMAX;
+  gdouble* __restrict__ gq64 = (gdouble*)f.q64;
+  gfloat* __restrict__ gq32 = (gfloat*)f.q32;
+  for (int e = tid; e < RMAX * RMAX; e += 256) {
+    const int k = e / RMAX, c = e % RMAX;
+    wy.V1[k][c] = qv1[e];
+    sm.T[k][c] = qt[e];
+  }
+  if (tid < RMAX) sm.sgn[tid] = qs[tid];
+  __syncthreads();
+  block_qr_wy_product<RMAX, 256>(sm, wy, R, nullptr, 0);
+  const int r = tid;
+  if (r < I) {
+    double v[RMAX];
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m) v[m] = (m < R) ? qv[r + (int64_t)I * (m < R ? m : 0)] : 0.0;
+    wy_q_row<RMAX, RMAX, 0>(v, r, R, sm, wy, [&](int c, double val) {
+      if (gq64) gq64[r + (int64_t)I * c] = val;
+      if (gq32) gq32[r + (int64_t)I * c] = (float)val;
+    });
   }
 }
 
@@ -937,14 +928,29 @@ static hipError_t finish_launch(int rm, int rp, unsigned blocks, const FinishArg
   return hipGetLastError();
 }
 
-hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
+hipError_t launch_finish_head(const FinishArgs& f, hipStream_t st, bool* tail) {
+  *tail = false;
   if (f.I > CPQR_MAX_FACTOR_ROWS) return hipErrorInvalidValue;
-  if (qr_rmax(f.R) == 32 && f.I <= 256) {
-    // half-row layout: 512 threads, rows r < 256
+  if (qr_rmax(f.R) == 32 && f.I <= 256 && f.qn != nullptr) {
+    // half-row layout: 512 threads, rows r < 256; Q_n in form_qn_h
     hipLaunchKernelGGL(finish_update_h, dim3(1), dim3(FH_NT), 0, st, f);
+    *tail = true;
     return hipGetLastError();
   }
   return finish_launch(qr_rmax(f.R), factor_rpt(f.I), 1, f, nullptr, st);
+}
+
+hipError_t launch_finish_tail(const FinishArgs& f, hipStream_t st) {
+  if (f.I > 256 || f.R > 32 || f.qn == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(form_qn_h, dim3(1), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
+  bool tail = false;
+  hipError_t e = launch_finish_head(f, st, &tail);
+  if (e != hipSuccess || !tail) return e;
+  return launch_finish_tail(f, st);
 }
 
 hipError_t launch_finish_batched(int count, int rmax, int rpt, const FinishArgs* args, hipStream_t st) {
