@@ -13,7 +13,8 @@
 //    A = Ahat / lambda, Householder QR of A -> Q_n, R_n; after the last update
 //    of a sweep the fit and the extrapolation activation rule.
 //    finish_update_h does the same for rank class 32 and up to 256 rows with
-//    each row split over the two halves of a wave.
+//    each row split over the two halves of a wave, and leaves the explicit
+//    Q_n to form_qn_h.
 //  * finish_tall / tall_factor_tail: the same update for modes beyond the
 //    single-workgroup factor QR (the factor QR then goes through the TSQR).
 //  * sumsq / residual: ||X||^2 and ||X - K||^2 with float64 accumulation.
