@@ -103,11 +103,14 @@ def test_fp64_staircase_zqr_order3(P, dims, R, seed):
 
 @pytest.mark.parametrize("zqr", ["stair", "dense"])
 @pytest.mark.parametrize("dims,R,seed", [([3, 30, 28], 5, 71), ([40, 40, 4], 8, 74),
-                                         ([2, 17, 3, 19], 6, 72), ([4, 9, 3, 8, 5], 4, 73)])
+                                         ([2, 17, 3, 19], 6, 72), ([4, 9, 3, 8, 5], 4, 73),
+                                         ([12, 40, 50], 20, 77), ([30, 6, 45], 24, 78)])
 def test_fp64_modes_below_the_rank(P, dims, R, seed, zqr):
     """Modes smaller than the rank (compact factor QR with min(I, R)
     reflectors, zero-padded on the device) against the oracle's compact
-    formulation, restructured tree with the paper's extrapolation."""
+    formulation, restructured tree with the paper's extrapolation.  Ranks 20
+    and 24 take the rank-32 half-row factor QR and its separate Q_n kernel
+    with padded reflector rows."""
     prob = G.make_problem(dims, R, seed=seed, rho=1e-2, dtype=np.float64)
     g, o = _run(P, prob, 10, prec="fp64", tree="restructured", extrap="paper", zqr=zqr)
     assert g["orders"] == o["orders"]
