@@ -254,6 +254,60 @@ def test_classical_extrapolation_keeps_first_row_and_column():
     assert np.all(custom[0, 1:] == 0) and np.all(custom[1:, 0] == 0)
 
 
+@pytest.mark.parametrize("N,dims", [(3, (6, 5, 7)), (4, (4, 5, 3, 4))])
+@pytest.mark.parametrize("alpha,beta", [(0.1, 0.05), (0.1, 1 / 500), (1.0, 0.3), (0.5, 0.02)])
+def test_mode_update_eq19_first_column(N, dims, alpha, beta):
+    """eq. (19) through the oracle's own mode update: Q0 and Q0prev both have
+    e1 as their first column (Section 3.2), so the extrapolated Q0hat has
+    (1 + beta (1 - alpha)) e1 there, and the first column of Vu = Y Q0hat is
+    that multiple of the first column of Vp = Y Q0.  With alpha = 1 (the
+    classical eq. (18)) the first column is unchanged."""
+    r = rng(60 + N)
+    X = r.standard_normal(dims)
+    R = 3
+    A, Qs, Rs = _state(N, dims, R, seed=61 + N)
+    A2 = [a + 0.2 * r.standard_normal(a.shape) for a in A]
+    Rs_prev = [O.householder_qr(a / np.linalg.norm(a, axis=0))[1] for a in A2]
+    for n in range(N):
+        Yn = O.unfold(O.multi_ttm_except(X, Qs, n), n)
+        Q0prev = O.mode_update(Yn, Rs_prev, n, None, 0.0, alpha)[2]
+        _, _, Q0, _, Vp, Vu = O.mode_update(Yn, Rs, n, Q0prev, beta, alpha)
+        scale = 1.0 + beta * (1.0 - alpha)
+        assert np.allclose(Vu[:, 0], scale * Vp[:, 0], rtol=1e-14, atol=1e-14)
+        # the other columns move: Q0prev differs from Q0 beyond column 0
+        assert np.abs(Vu[:, 1:] - scale * Vp[:, 1:]).max() > 1e-6
+        if alpha == 1.0:
+            assert np.array_equal(Vu[:, 0], Vp[:, 0]) or np.allclose(Vu[:, 0], Vp[:, 0], rtol=1e-15)
+
+
+@pytest.mark.parametrize("tree", ["standard", "restructured"])
+@pytest.mark.parametrize("alpha,beta", [(0.1, 0.05), (1.0, 0.2), (0.3, 0.01)])
+def test_eq19_at_a_fixed_point_scales_lambda_only(tree, alpha, beta):
+    """A noiseless rank-R tensor started at its exact factors is a fixed point
+    of the plain update (the least-squares subproblem, eq. (6), is solved
+    exactly).  There every mode's Q0 equals the previous sweep's Q0, so
+    eq. (19) with Q0^{k-1} taken as the same mode's un-extrapolated Q0 of the
+    previous sweep gives Q0hat = (1 + beta (1 - alpha)) Q0: the normalised
+    factors stay exactly where they are and lambda carries the factor
+    1 + beta (1 - alpha) after every sweep from sweep 2 on.  The cheap and the
+    explicit fit both read 1 - beta (1 - alpha) (Section 4.1 with <Vp, Vu>).
+    Taking Q0^{k-1} from another mode, or the previous extrapolated Q0hat,
+    breaks one of these."""
+    dims, R = (7, 6, 8), 3
+    truth = G.gaussian_factors(rng(70), dims, R)
+    unit = [a / np.linalg.norm(a, axis=0) for a in truth]
+    lam_true = np.prod([np.linalg.norm(a, axis=0) for a in truth], axis=0)
+    X = G.tensor_from_factors(truth)
+    res = O.cp_als_qr(X, R, unit, iters=6, tree=tree, fix_beta=beta, alpha=alpha,
+                      explicit_every_sweep=True)
+    scale = 1.0 + beta * (1.0 - alpha)
+    for a, u in zip(res["factors"], unit):
+        assert np.allclose(a, u, atol=1e-12)
+    assert np.allclose(res["lam"], scale * lam_true, rtol=1e-12)
+    assert np.allclose(res["fits"][1:], 1.0 - beta * (1.0 - alpha), atol=1e-12)
+    assert np.allclose(res["fitxs"][1:], 1.0 - beta * (1.0 - alpha), atol=1e-12)
+
+
 @pytest.mark.parametrize("fit,beta", [(0.99, 1 / 20000), (0.9500001, 1 / 20000), (0.95, 1 / 2000),
                                       (0.91, 1 / 2000), (0.90, 1 / 500), (0.7000001, 1 / 500),
                                       (0.70, 1 / 250), (0.3, 1 / 250)])
