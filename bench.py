@@ -52,6 +52,18 @@ def _traffic_from_profile(kernel_src: str):
         return None
 
 
+def _cpu_model() -> str:
+    """Host CPU model name (from /proc/cpuinfo), or "unknown"."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, budget_s: float):
     """Oracle sweeps/s on a bounded sample (first sweep excluded)."""
     import numpy as np
@@ -81,6 +93,7 @@ def cpu_baseline(prob, budget_s: float):
     n = len(stamps) - 1
     sec = stamps[-1] - stamps[0]
     return {"value": n / sec, "unit": "sweeps/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count() or 1,
             "sample": f"sweeps 2..{n + 1} of the same workload (restructured order, direct "
                       f"multi-TTM from X, float64 numpy), {sec:.1f} s"}
 

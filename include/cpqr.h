@@ -37,7 +37,9 @@ typedef enum {
   CPQR_EUNSUPPORTED = -2, /* valid but outside what this build handles (see limits) */
   CPQR_ENOMEM = -3,       /* device allocation failed */
   CPQR_EHIP = -4,         /* a HIP runtime call failed; see cpqr_last_error */
-  CPQR_ERANKDEF = -5,     /* a column norm (lambda_r) or a diagonal of R0 / R_n is zero */
+  CPQR_ERANKDEF = -5,     /* a column norm (lambda_r), a diagonal of R0 or R_n, or a diagonal of an
+                             initial factor's R is zero or at most 1e-13 times the largest of its
+                             set (numerically dependent columns, e.g. duplicate initial columns) */
   CPQR_ENONFINITE = -6    /* a NaN or Inf appeared in the fit or in lambda */
 } cpqr_status;
 
@@ -87,6 +89,9 @@ typedef enum { CPQR_DTYPE_F64 = 0, CPQR_DTYPE_F32 = 1 } cpqr_dtype;
 #define CPQR_FLAG_DENSE_ZQR    0x8u  /* factor Z_n by the dense two-level TSQR even where the
                                         one-workgroup staircase QR applies (Z_n of at most 256
                                         rows, or order 3 at ranks 17..32); for comparison */
+#define CPQR_FLAG_TIME_PHASES  0x10u /* fill cpqr_result.phase_seconds: kernels launch one by one
+                                        (no graphs) with HIP events between kernel groups, and the
+                                        host waits after every sweep; excludes TIME_KERNELS */
 
 typedef struct cpqr_handle cpqr_handle;
 
@@ -118,13 +123,20 @@ typedef struct {
   double alpha;         /* eq. (19) alpha; the paper uses 0.1 */
   double switch_delta;  /* activation threshold on the fit change; the paper uses 0.03 */
   double fixed_beta;    /* if > 0 with CPQR_EXTRAP_PAPER: use this beta from sweep 2 on instead of the rule */
-  const double *const *init_factors; /* host, N pointers to I_n x R column-major float64 initial factors */
+  const double *const *init_factors; /* host, N pointers to I_n x R column-major float64 initial factors,
+                                        or NULL: seeded N(0,1) factors (see `seed`) */
   unsigned flags;       /* CPQR_FLAG_* */
   const float *mlp_weights; /* host, CPQR_MLP_PARAMS floats; required with CPQR_EXTRAP_LEARNED, else ignored */
   const double *beta_schedule; /* host, `iters` values or NULL.  With CPQR_EXTRAP_PAPER: sweep k+1 uses
                                   beta = beta_schedule[k] (k >= 1; entry 0 is unused since sweep 1 has
                                   no previous Q0), overriding the rule and fixed_beta.  Used to label the
                                   training data of the learned extrapolation. */
+  uint64_t seed;        /* with init_factors == NULL: entry e of the initial factors (modes in order,
+                           each I_n x R column-major, e counting across modes) is the Box-Muller
+                           normal sqrt(-2 ln u_{2e}) cos(2 pi u_{2e+1}), u_j = ((z_j >> 11) + 0.5) 2^-53,
+                           z_j = output j (0-based) of SplitMix64 seeded with `seed`
+                           (z_j = mix64(seed + (j + 1) 0x9E3779B97F4A7C15), mix64 the finaliser of
+                           Steele, Lea and Flood, OOPSLA 2014); ignored otherwise */
 } cpqr_options;
 
 typedef struct {
@@ -146,6 +158,18 @@ typedef struct {
   double l1_ttm_flops;     /* flops of one level-1 TTM per launch (averaged) */
   double beta_learned;     /* CPQR_EXTRAP_LEARNED: the MLP's beta (0 otherwise) */
   int learned_fallback_sweep; /* CPQR_EXTRAP_LEARNED: sweep whose rejection switched to the paper's beta (0 if none) */
+  double phase_seconds[5]; /* with CPQR_FLAG_TIME_PHASES (else 0): summed device time of the sweeps in the
+                              five categories of the time breakdown of Section 4.2:
+                              [0] TTM (every TTM of the tree),
+                              [1] QR (the factor-QR kernels, which also carry the fused triangular
+                                  solve, normalisation, fit and beta rule of the update),
+                              [2] computation of Q0 (the QR of Z_n),
+                              [3] application of Q0 (Y_(n) [Q0 | Q0^{k-1}] and its reduction),
+                              [4] other (the gaps between kernel groups: launch and event latency) */
+  double *const *q_factors; /* host, N caller-owned I_n x R float64 outputs, or NULL: the explicit Q_n of
+                               the last factor QRs as the TTMs used them (float32 values for FP32 and
+                               BF16X3, widened exactly), for the orthonormality report ||Q_n^T Q_n - I||;
+                               a mode with I_n < R has zero columns beyond I_n */
 } cpqr_result;
 
 /*
@@ -287,10 +311,14 @@ cpqr_status cpqr_ttm(cpqr_handle *handle, int prec, int order, const int64_t *di
                      int mode, int rank, const void *in, const void *q, void *out);
 
 /*
- * cpqr_qr -- compact Householder QR of an M x R float64 matrix held on the
- * device (column-major): A = Q R with Q (device, M x R, orthonormal
- * columns) and R (device, R x R, upper triangular, non-negative diagonal).
- * Limits: 1 <= R <= 32, R <= M <= 2^20.
+ * cpqr_qr -- the compact QR of Section 2.4 (the QR of every factor matrix and
+ * of Z_n in Algorithm 2) for an M x R float64 matrix held on the device
+ * (column-major): A = Q R with Q (device, M x R, orthonormal columns) and R
+ * (device, R x R, upper triangular, non-negative diagonal), computed by
+ * Householder reflections (two-level TSQR for tall matrices).  A, Q and R
+ * are caller-owned; the handle owns the TSQR workspace (allocated on demand).
+ * Errors: CPQR_EINVAL for null pointers or R > M, CPQR_EUNSUPPORTED beyond
+ * the limits 1 <= R <= 32, M within the two-level TSQR (M <= 2^20 at R <= 8).
  */
 cpqr_status cpqr_qr(cpqr_handle *handle, int64_t M, int R, const double *A,
                     double *Q, double *Rout);

@@ -55,9 +55,62 @@ __all__ = [
     "householder_qr", "back_substitution", "sweep_order", "beta_from_fit",
     "sum_squares", "reconstruct", "explicit_fit", "cheap_fit", "mode_update",
     "cp_als_qr", "tree_schedule", "schedule_flops", "run_tree_schedule",
+    "RankDeficient", "RANK_REL", "splitmix64", "seeded_normal_factors",
 ]
 
 F64 = np.float64
+
+# Relative rank test (a library convention, not the paper's): a triangular
+# factor's diagonal, or the set of column norms lambda, is rank-deficient when
+# one entry is at most RANK_REL times the largest (zero included).
+RANK_REL = 1e-13
+
+
+class RankDeficient(FloatingPointError):
+    """Numerically dependent columns in an R factor, in R0 or in lambda."""
+
+
+def _check_rank(d: np.ndarray, what: str) -> None:
+    d = np.abs(np.asarray(d, F64))
+    if d.size and not np.all(d > RANK_REL * d.max()):
+        raise RankDeficient(what)
+
+
+# ---------------------------------------------------------------------------
+# Seeded N(0,1) initial factors (the "Initialize" step leaves the start open;
+# this is the library's documented default when no factors are passed)
+# ---------------------------------------------------------------------------
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, j: np.ndarray) -> np.ndarray:
+    """Outputs j (0-based, uint64 array) of SplitMix64 seeded with ``seed``
+    (Steele, Lea and Flood, OOPSLA 2014; the finaliser of Vigna's
+    splitmix64.c): the state after j + 1 steps is seed + (j + 1) * golden, and
+    the output is that state through the mix z ^= z >> 30, z *= 0xBF58476D1CE4E5B9,
+    z ^= z >> 27, z *= 0x94D049BB133111EB, z ^= z >> 31 (all mod 2^64)."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.asarray(j, np.uint64) + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def seeded_normal_factors(seed: int, dims: Sequence[int], rank: int) -> List[np.ndarray]:
+    """Initial factors drawn from ``seed``: entry e (modes in order, each
+    I_n x R column-major, e counting across modes) is the Box-Muller normal
+    sqrt(-2 ln u_{2e}) cos(2 pi u_{2e+1}) with u_j = ((z_j >> 11) + 0.5) / 2^53
+    and z_j = splitmix64(seed, j)."""
+    total = int(sum(int(d) for d in dims)) * int(rank)
+    j = np.arange(2 * total, dtype=np.uint64)
+    u = ((splitmix64(seed, j) >> np.uint64(11)).astype(F64) + 0.5) * 2.0 ** -53
+    z = np.sqrt(-2.0 * np.log(u[0::2])) * np.cos(2.0 * math.pi * u[1::2])
+    out, off = [], 0
+    for d in dims:
+        n = int(d) * int(rank)
+        out.append(np.reshape(z[off:off + n], (int(d), int(rank)), order="F").copy())
+        off += n
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -283,6 +336,7 @@ def mode_update(Yn: np.ndarray, Rfs: Sequence[np.ndarray], n: int,
         # rank and the subproblem (6) has no unique solution
         raise ValueError("Z_n has fewer rows than columns")
     Q0, R0 = householder_qr(Z)
+    _check_rank(np.diag(R0), "R0 (dependent R factors)")
     Vp = Yn @ Q0
     if Q0prev is not None and beta != 0.0:
         Q0hat = Q0 + beta * (Q0 - alpha * Q0prev)
@@ -291,8 +345,7 @@ def mode_update(Yn: np.ndarray, Rfs: Sequence[np.ndarray], n: int,
         Vu = Vp
     Ahat = back_substitution(R0, Vu.T).T
     lam = np.linalg.norm(Ahat, axis=0)
-    if np.any(lam == 0.0):
-        raise FloatingPointError("zero column in the updated factor")
+    _check_rank(lam, "lambda (zero column in the updated factor)")
     return Ahat / lam[None, :], lam, Q0, R0, Vp, Vu
 
 
@@ -300,7 +353,7 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
               tree: str = "none", extrap: str = "off", alpha: float = 0.1,
               delta: float = 0.03, tol: float = 0.0, fix_beta: Optional[float] = None,
               explicit_every_sweep: bool = False, explicit_final: bool = True,
-              sweep_callback=None, mlp_weights=None, beta_schedule=None) -> Dict:
+              sweep_callback=None, mlp_weights=None, beta_schedule=None, seed: int = 0) -> Dict:
     """CP-ALS-QR (Algorithm 2) / ALS-QR-BR(E) (Algorithm 3) in FP64 with
     direct multi-TTMs from X.  ``tree`` only selects the update order.
 
@@ -315,16 +368,22 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
     beta_schedule[k - 1] instead of the rule.  ``sweep_callback(k, fit)``
     (instrumentation hook) is called
     after each sweep; ``explicit_final=False`` skips the final explicit fit.
+    ``init=None`` draws the initial factors with seeded_normal_factors(seed).
+    Raises RankDeficient when an initial factor, R0, lambda or an R_n has
+    numerically dependent columns (relative test, RANK_REL).
     """
     import copy
     X = np.asarray(X, F64)
     N = X.ndim
     R = int(rank)
     nx2 = sum_squares(X)
+    if init is None:
+        init = seeded_normal_factors(seed, X.shape, R)
     A = [np.array(a, F64, copy=True) for a in init]
     Qs, Rfs = [], []
     for a in A:
         q, r = householder_qr(a)
+        _check_rank(np.diag(r), "initial factor (dependent columns)")
         Qs.append(q)
         Rfs.append(r)
     lam = np.ones(R)
@@ -344,6 +403,7 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
             A[n], lam, Q0, R0, Vp, Vu = mode_update(Yn, Rfs, n, Q0prev[n], b, alpha)
             Q0prev[n] = Q0
             Qs[n], Rfs[n] = householder_qr(A[n])
+            _check_rank(np.diag(Rfs[n]), "R_n (dependent columns)")
         return cheap_fit(nx2, Vp, Vu)
 
     for k in range(1, iters + 1):

@@ -28,6 +28,8 @@ MLP_FEATURES, MLP_HIDDEN = 8, 64
 MLP_PARAMS = MLP_HIDDEN * MLP_FEATURES + 2 * MLP_HIDDEN + 1
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 FLAG_EXPLICIT_FIT, FLAG_TIME_KERNELS, FLAG_NO_GRAPH, FLAG_DENSE_ZQR = 0x1, 0x2, 0x4, 0x8
+FLAG_TIME_PHASES = 0x10
+PHASES = ("ttm", "qr", "q0", "apply_q0", "other")
 ZQR = ("stair", "dense")
 
 
@@ -48,7 +50,8 @@ class _Options(ctypes.Structure):
                 ("switch_delta", ctypes.c_double), ("fixed_beta", ctypes.c_double),
                 ("init_factors", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
                 ("flags", ctypes.c_uint), ("mlp_weights", ctypes.POINTER(ctypes.c_float)),
-                ("beta_schedule", ctypes.POINTER(ctypes.c_double))]
+                ("beta_schedule", ctypes.POINTER(ctypes.c_double)),
+                ("seed", ctypes.c_uint64)]
 
 
 class _Result(ctypes.Structure):
@@ -62,7 +65,9 @@ class _Result(ctypes.Structure):
                 ("ttm_bytes", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("l1_ttm_seconds", ctypes.c_double), ("l1_ttm_launches", ctypes.c_int),
                 ("l1_ttm_bytes", ctypes.c_double), ("l1_ttm_flops", ctypes.c_double),
-                ("beta_learned", ctypes.c_double), ("learned_fallback_sweep", ctypes.c_int)]
+                ("beta_learned", ctypes.c_double), ("learned_fallback_sweep", ctypes.c_int),
+                ("phase_seconds", ctypes.c_double * 5),
+                ("q_factors", ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))]
 
 
 EXPORTS = ["cpqr_create", "cpqr_destroy", "cpqr_last_error", "cpqr_status_string",
@@ -213,23 +218,29 @@ def to_device(X: np.ndarray, dtype=None, device: int = 0):
 
 def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, switch_delta,
              fixed_beta, explicit_fit, time_kernels, use_graph, mlp_weights=None,
-             beta_schedule=None, zqr="stair"):
+             beta_schedule=None, zqr="stair", seed=0, time_phases=False):
     if zqr not in ZQR:
         raise ValueError(f"zqr must be one of {ZQR}")
     dims, dt, ptr = _dims_and_ptr(x, dims)
     N = len(dims)
-    inits = [np.asfortranarray(np.asarray(a, dtype=np.float64)) for a in init]
-    if len(inits) != N:
-        raise ValueError("need one initial factor per mode")
-    for k, a in enumerate(inits):
-        if a.shape != (dims[k], rank):
-            raise ValueError(f"init factor {k} must be {dims[k]} x {rank}")
-    keep = {"dims_c": (ctypes.c_int64 * N)(*dims), "inits": inits}
+    keep = {"dims_c": (ctypes.c_int64 * N)(*dims)}
     keep["ten"] = _Tensor(N, keep["dims_c"], dt, ctypes.c_void_p(ptr))
-    keep["init_ptrs"] = (ctypes.POINTER(ctypes.c_double) * N)(
-        *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in inits])
+    if init is None:
+        # the library draws seeded N(0,1) factors (cpqr_options.seed)
+        keep["init_ptrs"] = None
+    else:
+        inits = [np.asfortranarray(np.asarray(a, dtype=np.float64)) for a in init]
+        if len(inits) != N:
+            raise ValueError("need one initial factor per mode")
+        for k, a in enumerate(inits):
+            if a.shape != (dims[k], rank):
+                raise ValueError(f"init factor {k} must be {dims[k]} x {rank}")
+        keep["inits"] = inits
+        keep["init_ptrs"] = (ctypes.POINTER(ctypes.c_double) * N)(
+            *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in inits])
     flags = (FLAG_EXPLICIT_FIT if explicit_fit else 0) | (FLAG_TIME_KERNELS if time_kernels else 0) \
-        | (0 if use_graph else FLAG_NO_GRAPH) | (FLAG_DENSE_ZQR if zqr == "dense" else 0)
+        | (0 if use_graph else FLAG_NO_GRAPH) | (FLAG_DENSE_ZQR if zqr == "dense" else 0) \
+        | (FLAG_TIME_PHASES if time_phases else 0)
     wptr = None
     if mlp_weights is not None:
         w = np.ascontiguousarray(np.asarray(mlp_weights, dtype=np.float32).reshape(-1))
@@ -246,7 +257,7 @@ def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, sw
         sptr = sch.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     keep["opts"] = _Options(TREES[tree], EXTRAP[extrapolate], PRECS[prec], int(iters), float(tol),
                             float(alpha), float(switch_delta), float(fixed_beta),
-                            keep["init_ptrs"], flags, wptr, sptr)
+                            keep["init_ptrs"], flags, wptr, sptr, int(seed) & 0xFFFFFFFFFFFFFFFF)
     return dims, keep
 
 
@@ -256,17 +267,20 @@ def _result_buffers(dims, rank, iters):
     lam = np.zeros(rank)
     fits = np.full(max(iters, 1), np.nan)
     orders = np.zeros((max(iters, 1), N), dtype=np.int32)
+    qs = [np.zeros((dims[k], rank), order="F") for k in range(N)]
     res = _Result()
     res.factors = (ctypes.POINTER(ctypes.c_double) * N)(
         *[o.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for o in outs])
+    res.q_factors = (ctypes.POINTER(ctypes.c_double) * N)(
+        *[q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for q in qs])
     res.lambda_ = lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     res.fit_history = fits.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     res.sweep_orders = orders.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
-    return res, (outs, lam, fits, orders)
+    return res, (outs, lam, fits, orders, qs)
 
 
 def _result_dict(res, bufs):
-    outs, lam, fits, orders = bufs
+    outs, lam, fits, orders, qs = bufs
     n = res.sweeps_done
     return {
         "factors": outs, "lam": lam, "fits": fits[:n].copy(), "fit": res.fit,
@@ -276,20 +290,24 @@ def _result_dict(res, bufs):
         "l1_ttm_seconds": res.l1_ttm_seconds, "l1_ttm_launches": res.l1_ttm_launches,
         "l1_ttm_bytes": res.l1_ttm_bytes, "l1_ttm_flops": res.l1_ttm_flops,
         "beta_learned": res.beta_learned, "learned_fallback_sweep": res.learned_fallback_sweep,
+        "phase_seconds": dict(zip(PHASES, list(res.phase_seconds))), "Q": qs,
     }
 
 
-def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
+def cp_als_qr(x, rank: int, init: Optional[Sequence[np.ndarray]], iters: int = 100, *,
               dims: Optional[Sequence[int]] = None, tree: str = "restructured",
               extrapolate: str = "off", prec: str = "fp32", tol: float = 0.0,
               alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
               explicit_fit: bool = False, time_kernels: bool = False, use_graph: bool = True,
-              mlp_weights=None, beta_schedule=None, zqr: str = "stair",
-              handle: Optional[Handle] = None) -> Dict:
+              mlp_weights=None, beta_schedule=None, zqr: str = "stair", seed: int = 0,
+              time_phases: bool = False, handle: Optional[Handle] = None) -> Dict:
     """CP-ALS-QR / ALS-QR-BR(E) on the GPU (Algorithms 2 and 3).
 
     ``zqr="dense"`` factors Z_n by the two-level TSQR even where the
-    one-workgroup staircase QR applies (for comparison).
+    one-workgroup staircase QR applies (for comparison).  ``init=None`` lets
+    the library draw seeded N(0,1) initial factors from ``seed``.
+    ``time_phases`` fills ``phase_seconds`` (TTM, QR, computation and
+    application of Q0, other) with kernels launched one by one.
 
     Returns a dict with factors (list of I_n x R float64 arrays), lam, fits
     (per-sweep fit history), fit, fit_explicit, orders, beta, beta_sweep,
@@ -298,7 +316,7 @@ def cp_als_qr(x, rank: int, init: Sequence[np.ndarray], iters: int = 100, *,
     L = load_library()
     dims, keep = _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha,
                           switch_delta, fixed_beta, explicit_fit, time_kernels, use_graph,
-                          mlp_weights, beta_schedule, zqr)
+                          mlp_weights, beta_schedule, zqr, seed, time_phases)
     h = handle or default_handle(x.device.index or 0)
     res, bufs = _result_buffers(dims, rank, iters)
     st = L.cpqr_als_qr(h._h, ctypes.byref(keep["ten"]), int(rank), ctypes.byref(keep["opts"]),
@@ -315,8 +333,8 @@ def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequen
                       handle: Optional[Handle] = None) -> List[Dict]:
     """Independent decompositions run together (cpqr_als_qr_batched): every
     sweep of the whole batch is one HIP graph of batched kernels.  Returns one
-    result dict per problem (as :func:`cp_als_qr`).  ``fixed_beta`` may be one
-    value or one per problem."""
+    result dict per problem (as :func:`cp_als_qr`).  ``alpha``,
+    ``switch_delta`` and ``fixed_beta`` may be one value or one per problem."""
     L = load_library()
     count = len(xs)
     if not (len(ranks) == len(inits) == count) or count < 1:
@@ -325,10 +343,13 @@ def cp_als_qr_batched(xs: Sequence, ranks: Sequence[int], inits: Sequence[Sequen
     tens = (_Tensor * count)()
     optv = (_Options * count)()
     resv = (_Result * count)()
+    def each(v, t):
+        return v[t] if isinstance(v, (list, tuple, np.ndarray)) else v
+
     for t in range(count):
-        fb = fixed_beta[t] if isinstance(fixed_beta, (list, tuple, np.ndarray)) else fixed_beta
         d, keep = _prepare(xs[t], ranks[t], inits[t], iters, dims[t] if dims else None, tree,
-                           extrapolate, prec, 0.0, alpha, switch_delta, fb, explicit_fit,
+                           extrapolate, prec, 0.0, each(alpha, t), each(switch_delta, t),
+                           each(fixed_beta, t), explicit_fit,
                            False, True, None,
                            beta_schedules[t] if beta_schedules is not None else None, zqr)
         keeps.append(keep)
@@ -400,7 +421,8 @@ def check_args(dims: Sequence[int], rank: int, *, dtype: str = "f32", iters: int
                tree: str = "restructured", extrapolate: str = "off", prec: str = "fp32",
                tol: float = 0.0, alpha: float = 0.1, switch_delta: float = 0.03,
                fixed_beta: float = 0.0, init: Optional[Sequence[np.ndarray]] = None,
-               data_ptr: int = 1, mlp_weights=None, raw: Optional[dict] = None) -> int:
+               data_ptr: int = 1, mlp_weights=None, flags: int = 0,
+               raw: Optional[dict] = None) -> int:
     """Host-only argument checks of cpqr_als_qr (no device needed); returns
     the status code.  ``raw`` overrides fields with raw integers/None to
     exercise invalid inputs."""
@@ -425,7 +447,7 @@ def check_args(dims: Sequence[int], rank: int, *, dtype: str = "f32", iters: int
     opts = _Options(raw.get("tree", TREES.get(tree, 9)), raw.get("extrapolate", EXTRAP.get(extrapolate, 9)),
                     raw.get("prec", PRECS.get(prec, 9)), int(iters), float(tol), float(alpha),
                     float(switch_delta), float(fixed_beta),
-                    None if raw.get("null_init") else ptrs, 0,
+                    None if raw.get("null_init") else ptrs, int(flags),
                     None if wbuf is None else wbuf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     return int(L.cpqr_check_args(ctypes.byref(ten), int(rank), ctypes.byref(opts)))
 

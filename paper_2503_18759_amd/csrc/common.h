@@ -170,6 +170,30 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
+// Relative rank test of a triangular factor's diagonal (or of a set of column
+// norms) d(0..n-1): rank-deficient when some entry is at most kRankRel times
+// the largest magnitude (zero included) or is not a number.  Dependent
+// columns (duplicate initial columns, say) leave rounding-level diagonals,
+// about 1e-16 of the largest, which a test for exact zeros misses; a ratio
+// of 1e-13 is a condition number beyond what float64 resolves.
+constexpr double kRankRel = 1e-13;
+
+template <typename Get>
+__device__ __forceinline__ bool rank_deficient(int n, Get&& d) {
+  double mx = 0.0;
+  for (int c = 0; c < n; ++c) mx = fmax(mx, fabs(d(c)));
+  bool bad = false;
+  for (int c = 0; c < n; ++c) bad = bad || !(fabs(d(c)) > kRankRel * mx);
+  return bad;
+}
+
+// Largest value of `v` over the lanes of the wave.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, CPQR_WAVE));
+  return v;
+}
+
 // Round-to-nearest-even split of a float into bf16 hi + bf16 lo.
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;

@@ -243,6 +243,11 @@ hipError_t launch_tall_factor_tail(int I, int R, const double* q64, float* q32, 
 int sumsq_blocks(int64_t n);
 hipError_t launch_sumsq(const void* x, bool f64, int64_t n, double* part, hipStream_t st);
 hipError_t launch_state_init(DevState* s, const double* part, int nparts, hipStream_t st);
+// Flags FLAG_RANKDEF in *st if a mode's R factor (rf, N x R x R) has a
+// diagonal entry that is relatively zero (rank_deficient) among its first
+// min(dims[n], R) entries.
+hipError_t launch_init_rank_check(const double* rf, int N, int R, const int64_t* dims, DevState* st,
+                                  hipStream_t s);
 hipError_t launch_residual(const void* x, bool f64, int N, const int64_t* dims_host,
                            double* const* factors, const double* lambda, int R, double* part,
                            hipStream_t st);

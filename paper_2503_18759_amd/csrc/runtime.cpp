@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -111,6 +112,38 @@ cpqr_status ws(cpqr_handle* h, const std::string& name, size_t bytes, void** out
 // Back-to-back launches per timed level-1 TTM (CPQR_FLAG_TIME_KERNELS).
 constexpr int kTimeReps = 8;
 
+// Seeded N(0,1) initial factors (the "Initialize" step of Algorithms 2 and 3
+// leaves the initialisation open).  Uniforms come from SplitMix64 (Steele,
+// Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA
+// 2014, with the finaliser of Vigna's splitmix64.c): output j (0-based) of the
+// sequence seeded with s is mix(s + (j + 1) * 0x9E3779B97F4A7C15), mapped to
+// (0, 1) as ((z >> 11) + 0.5) 2^-53.  Entry e of the factors (modes in order,
+// each I_n x R column-major, e counting across modes) is the Box-Muller
+// normal sqrt(-2 ln u(2e)) cos(2 pi u(2e + 1)).
+uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+  uint64_t z = seed + (j + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+double unit_open(uint64_t z) { return ((double)(z >> 11) + 0.5) * 0x1.0p-53; }
+
+std::vector<std::vector<double>> seeded_init_factors(uint64_t seed, const std::vector<int64_t>& dims, int R) {
+  std::vector<std::vector<double>> out(dims.size());
+  uint64_t e = 0;
+  for (size_t k = 0; k < dims.size(); ++k) {
+    out[k].resize((size_t)dims[k] * R);
+    for (double& v : out[k]) {
+      const double u1 = unit_open(splitmix64_at(seed, 2 * e));
+      const double u2 = unit_open(splitmix64_at(seed, 2 * e + 1));
+      v = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+      ++e;
+    }
+  }
+  return out;
+}
+
 int64_t ipow(int64_t b, int e) {
   int64_t r = 1;
   for (int i = 0; i < e; ++i) r *= b;
@@ -179,6 +212,11 @@ struct cpqr_session {
   std::vector<hipEvent_t> evs;        // timing pairs of the level-1 TTMs
   std::vector<hipEvent_t> fork_evs;   // fork/join events of captured sweeps
   std::map<std::string, hipGraphExec_t> graphs;
+  // CPQR_FLAG_TIME_PHASES: events at the kernel-group boundaries of a sweep,
+  // the phase of the interval each one closes, and the accumulated times
+  std::vector<hipEvent_t> ph_ev;
+  std::vector<int> ph_lab;
+  double phase[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   // learned extrapolation
   float* mlp_w = nullptr;        // device weights
   float* mlp_io = nullptr;       // device features (CPQR_MLP_FEATURES) + output (1)
@@ -190,6 +228,7 @@ struct cpqr_session {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     for (hipEvent_t e : fork_evs) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ph_ev) (void)hipEventDestroy(e);
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);
   }
@@ -463,26 +502,43 @@ hipError_t launch_zqr(const Problem& p, int n, int sweep_k, bool last, const cpq
 // branch that the stream has joined).  With tail given, a Q_n kernel that
 // only the following TTMs need is left to the caller (*tail_pending set,
 // its arguments in *tail).
+// Phases of the time breakdown of Section 4.2 (cpqr_result.phase_seconds).
+enum { PH_TTM = 0, PH_QR = 1, PH_Q0 = 2, PH_APPLY = 3, PH_OTHER = 4 };
+// Records a phase boundary: the interval that ends here belongs to `phase`.
+using PhaseMark = std::function<hipError_t(int phase)>;
+
 hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o,
                          hipStream_t s, bool zqr_done = false, FinishArgs* tail = nullptr,
-                         bool* tail_pending = nullptr) {
+                         bool* tail_pending = nullptr, const PhaseMark* mark = nullptr) {
   TsqrArgs t;
   ApplyArgs a;
   FinishArgs f;
   update_args(p, n, sweep_k, last, o, &t, &a, &f);
   hipError_t e = hipSuccess;
-  if (!zqr_done) e = p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
-  if (e != hipSuccess) return e;
+  auto at = [&](int phase) { return mark ? (*mark)(phase) : hipSuccess; };
+  if (!zqr_done) {
+    if ((e = at(PH_OTHER)) != hipSuccess) return e;
+    e = p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
+    if (e != hipSuccess) return e;
+    if ((e = at(PH_Q0)) != hipSuccess) return e;
+  }
+  if ((e = at(PH_OTHER)) != hipSuccess) return e;
   e = launch_apply(a, s);
   if (e != hipSuccess) return e;
+  if ((e = at(PH_APPLY)) != hipSuccess) return e;
+  if ((e = at(PH_OTHER)) != hipSuccess) return e;
   if (p.dims[n] <= CPQR_MAX_FACTOR_ROWS) {
-    if (tail == nullptr) return launch_finish(f, s);
-    *tail = f;
-    return launch_finish_head(f, s, tail_pending);
+    if (tail == nullptr) e = launch_finish(f, s);
+    else {
+      *tail = f;
+      e = launch_finish_head(f, s, tail_pending);
+    }
+  } else {
+    e = launch_finish_tall(f, s);
+    if (e == hipSuccess) e = launch_tall_factor_qr(p, n, p.state, s);
   }
-  e = launch_finish_tall(f, s);
   if (e != hipSuccess) return e;
-  return launch_tall_factor_qr(p, n, p.state, s);
+  return at(PH_QR);
 }
 
 std::string sweep_key(const std::vector<Step>& sw, int parity, bool extrap) {
@@ -512,10 +568,12 @@ cpqr_status check_args(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpq
     return fail(h, CPQR_EINVAL, "FP64 precision needs a float64 tensor; FP32/BF16X3 need float32");
   if (!(o->tol >= 0.0) || !(o->alpha == o->alpha) || !(o->switch_delta >= 0.0) || !(o->fixed_beta >= 0.0))
     return fail(h, CPQR_EINVAL, "bad tol/alpha/switch_delta/fixed_beta");
-  if (!o->init_factors) return fail(h, CPQR_EINVAL, "init_factors is required");
+  if ((o->flags & CPQR_FLAG_TIME_PHASES) && (o->flags & CPQR_FLAG_TIME_KERNELS))
+    return fail(h, CPQR_EINVAL, "CPQR_FLAG_TIME_PHASES and CPQR_FLAG_TIME_KERNELS exclude each other");
   for (int k = 0; k < N; ++k) {
     if (X->dims[k] < 1) return fail(h, CPQR_EINVAL, "dims must be >= 1");
-    if (!o->init_factors[k]) return fail(h, CPQR_EINVAL, "null init factor %d", k);
+    // init_factors == NULL: seeded N(0,1) factors (seeded_init_factors)
+    if (o->init_factors && !o->init_factors[k]) return fail(h, CPQR_EINVAL, "null init factor %d", k);
   }
   if (rank > 32) return fail(h, CPQR_EUNSUPPORTED, "rank > 32 is not supported by this build");
   // A mode smaller than the rank keeps min(I_k, R) nonzero rows of R_k, so
@@ -753,16 +811,20 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   // ||X||^2 and the device state
   HIP_TRY(h, launch_sumsq(p.X, p.f64, S.nelem, p.norm_part, s));
   HIP_TRY(h, launch_state_init(p.state, p.norm_part, sumsq_blocks(S.nelem), s));
-  // initial factors and their QRs (Algorithm 2, "Initialize")
+  // initial factors and their QRs (Algorithm 2, "Initialize"): the caller's,
+  // or seeded N(0,1) ones
+  std::vector<std::vector<double>> gen;
+  if (!o->init_factors) gen = seeded_init_factors(o->seed, p.dims, rank);
   for (int k = 0; k < N; ++k) {
-    HIP_TRY(h, hipMemcpyAsync(p.A[k], o->init_factors[k], (size_t)p.dims[k] * rank * 8,
-                              hipMemcpyHostToDevice, s));
+    const double* a0 = o->init_factors ? o->init_factors[k] : gen[k].data();
+    HIP_TRY(h, hipMemcpyAsync(p.A[k], a0, (size_t)p.dims[k] * rank * 8, hipMemcpyHostToDevice, s));
     if (p.dims[k] > CPQR_MAX_FACTOR_ROWS)
       HIP_TRY(h, launch_tall_factor_qr(p, k, nullptr, s));
     else
       HIP_TRY(h, launch_factor_qr((int)p.dims[k], rank, p.A[k], p.rf + (size_t)k * rank * rank,
                                   p.f64 ? (double*)p.Q[k] : nullptr, p.f64 ? nullptr : (float*)p.Q[k], s));
   }
+  HIP_TRY(h, launch_init_rank_check(p.rf, N, rank, p.dims.data(), p.state, s));
   DevState hs;
   HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIP_TRY(h, hipStreamSynchronize(s));
@@ -770,6 +832,9 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
     if (hs.flags & FLAG_NONFINITE) return fail(h, CPQR_ENONFINITE, "tensor contains NaN or Inf");
     return fail(h, CPQR_EINVAL, "||X|| = 0");
   }
+  if (hs.flags & FLAG_NONFINITE) return fail(h, CPQR_ENONFINITE, "tensor contains NaN or Inf");
+  if (hs.flags & FLAG_RANKDEF)
+    return fail(h, CPQR_ERANKDEF, "an initial factor has (numerically) dependent columns");
   S.nx2 = hs.nx2;
   stt = tune_ttm_steps(h, p, S.sched);
   if (stt != CPQR_OK) return stt;
@@ -818,9 +883,23 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
   Problem& p = S->p;
   const int N = p.N;
   const bool timing = (o->flags & CPQR_FLAG_TIME_KERNELS) != 0;
-  const bool use_graph = !timing && !(o->flags & CPQR_FLAG_NO_GRAPH);
+  const bool phases = (o->flags & CPQR_FLAG_TIME_PHASES) != 0;
+  const bool use_graph = !timing && !phases && !(o->flags & CPQR_FLAG_NO_GRAPH);
   const uint32_t full = (1u << N) - 1u;
   const auto& sw = S->sched[k - 1];
+  // phase timing: an event at every kernel-group boundary, kernel by kernel
+  size_t ph_n = 0;
+  const PhaseMark mark = [&](int phase) -> hipError_t {
+    if (ph_n == S->ph_ev.size()) {
+      hipEvent_t ev;
+      hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return e;
+      S->ph_ev.push_back(ev);
+      S->ph_lab.push_back(PH_OTHER);
+    }
+    S->ph_lab[ph_n] = phase;
+    return hipEventRecord(S->ph_ev[ph_n++], s);
+  };
   for (const Step& st : sw)
     if (st.kind == STEP_TTM) {
       const int64_t in = inter_elems(p, st.src);
@@ -889,6 +968,10 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
       hipError_t e = fork_next(0);
       if (e != hipSuccess) return e;
     }
+    if (phases) {
+      hipError_t e = mark(-1);
+      if (e != hipSuccess) return e;
+    }
     for (size_t i = 0; i < sw.size(); ++i) {
       const Step& st = sw[i];
       hipError_t e;
@@ -922,7 +1005,9 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
           if ((e = hipGraphLaunch(itr->second, q)) != hipSuccess) return e;
           if ((e = hipEventRecord(b, q)) != hipSuccess) return e;
         } else {
+          if (phases && (e = mark(PH_OTHER)) != hipSuccess) return e;
           if ((e = launch_ttm_step(p, st, q)) != hipSuccess) return e;
+          if (phases && (e = mark(PH_TTM)) != hipSuccess) return e;
         }
       } else if (fork) {
         const bool z = forked;
@@ -936,7 +1021,9 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
         if ((e = fork_next(i + 1)) != hipSuccess) return e;
         if (tail && (e = launch_finish_tail(ft, q)) != hipSuccess) return e;
       } else {
-        if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q)) != hipSuccess) return e;
+        if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q, false, nullptr, nullptr,
+                               phases ? &mark : nullptr)) != hipSuccess)
+          return e;
       }
     }
     return hipSuccess;
@@ -963,6 +1050,15 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
   } else {
     hipError_t e = enqueue(s);
     if (e != hipSuccess) return fail(h, CPQR_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    if (phases && ph_n > 0) {
+      HIP_TRY(h, hipEventSynchronize(S->ph_ev[ph_n - 1]));
+      for (size_t i = 1; i < ph_n; ++i) {
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, S->ph_ev[i - 1], S->ph_ev[i]));
+        const int lab = S->ph_lab[i];
+        if (lab >= 0 && lab < 5) S->phase[lab] += ms * 1e-3;
+      }
+    }
   }
   return CPQR_OK;
 }
@@ -1149,6 +1245,18 @@ cpqr_status cpqr_session_result(cpqr_session* S, cpqr_result* res) {
       if (res->factors[k])
         HIP_TRY(h, hipMemcpy(res->factors[k], p.A[k], (size_t)p.dims[k] * rank * 8, hipMemcpyDeviceToHost));
   if (res->lambda) HIP_TRY(h, hipMemcpy(res->lambda, p.lambda, (size_t)rank * 8, hipMemcpyDeviceToHost));
+  if (res->q_factors)
+    for (int k = 0; k < N; ++k) {
+      if (!res->q_factors[k]) continue;
+      const size_t n = (size_t)p.dims[k] * rank;
+      if (p.f64) {
+        HIP_TRY(h, hipMemcpy(res->q_factors[k], p.Q[k], n * 8, hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> q(n);
+        HIP_TRY(h, hipMemcpy(q.data(), p.Q[k], n * 4, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) res->q_factors[k][i] = (double)q[i];
+      }
+    }
   if (res->sweep_orders)
     for (int k = 0; k < done; ++k) {
       int u = 0;
@@ -1168,6 +1276,7 @@ cpqr_status cpqr_session_result(cpqr_session* S, cpqr_result* res) {
   res->l1_ttm_flops = S->l1_count ? S->l1_flops / S->l1_count : 0.0;
   res->beta_learned = S->beta_learned;
   res->learned_fallback_sweep = S->fallback_sweep;
+  for (int i = 0; i < 5; ++i) res->phase_seconds[i] = S->phase[i];
   res->fit_explicit = std::nan("");
   if (S->opts.flags & CPQR_FLAG_EXPLICIT_FIT) {
     std::vector<double*> fac(p.A.begin(), p.A.end());
@@ -1208,6 +1317,7 @@ cpqr_status cpqr_als_qr(cpqr_handle* h, const cpqr_tensor* X, int rank, const cp
     cpqr_result tmp = *res;
     tmp.factors = nullptr;
     tmp.lambda = nullptr;
+    tmp.q_factors = nullptr;
     (void)cpqr_session_result(S, &tmp);
     res->sweeps_done = tmp.sweeps_done;
     h->err = msg;
@@ -1338,7 +1448,10 @@ void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpq
       std::vector<TsqrArgs> ts(count);
       std::vector<ApplyArgs> as(count);
       std::vector<FinishArgs> fs(count);
-      for (int t = 0; t < count; ++t) update_args(B.S[t]->p, st.mode, k, last, o, &ts[t], &as[t], &fs[t]);
+      // each problem's own alpha, switch_delta and fixed_beta (the batch
+      // shares only the tree, extrapolation mode, precision and sweep count)
+      for (int t = 0; t < count; ++t)
+        update_args(B.S[t]->p, st.mode, k, last, &B.S[t]->opts, &ts[t], &as[t], &fs[t]);
       // staircase Z QR groups: kernel shape; TSQR groups: rank class and plan
       std::map<std::pair<int, int>, std::vector<int>> sg;
       std::map<std::tuple<int, int, int>, std::vector<int>> tg;

@@ -352,8 +352,8 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   __syncthreads();
 
   int bad = 0;
-  for (int c = 0; c < R; ++c)
-    if (!(sR0[c][c] != 0.0)) bad |= FLAG_RANKDEF;   // singular Z_n (dependent R factors)
+  // singular or nearly singular Z_n (dependent R factors)
+  if (rank_deficient(R, [&](int c) { return sR0[c][c]; })) bad |= FLAG_RANKDEF;
   QrRow<RMAX> a[RPT];
   double sc[2] = {0.0, 0.0};
 #pragma unroll
@@ -429,7 +429,8 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
     }
     const bool col = lane < R;
     const double lam = sqrt(tot);
-    if (__any(col && lam == 0.0)) bad |= FLAG_RANKDEF;
+    const double lmax = wave_max(col ? lam : 0.0);
+    if (__any(col && !(lam > kRankRel * lmax))) bad |= FLAG_RANKDEF;
     if (__any(col && !isfinite(lam))) bad |= FLAG_NONFINITE;
     inv_l = (col && lam != 0.0) ? 1.0 / lam : 0.0;
     if (tid < R) ((gdouble*)f.lambda)[tid] = lam;
@@ -463,8 +464,7 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
   if (tid == 0) {
     // a mode smaller than the rank has min(I, R) reflectors; the padded
     // rows of R_n (c >= I) are zero by construction
-    for (int c = 0; c < R && c < I; ++c)
-      if (!(wy.Rm[c][c] > 0.0)) bad |= FLAG_RANKDEF;
+    if (rank_deficient(R < I ? R : I, [&](int c) { return wy.Rm[c][c]; })) bad |= FLAG_RANKDEF;
     finish_state_tail(f, st, sc, bad);
   }
 }
@@ -562,8 +562,7 @@ __global__ __launch_bounds__(FH_NT) void finish_update_h(FinishArgs f) {
   }
   block_allreduce<2, FH_NW>(sc, sred2);   // its barriers also publish sR0 and sA
   int bad = 0;
-  for (int c = 0; c < R; ++c)
-    if (!(sR0[c][c] != 0.0)) bad |= FLAG_RANKDEF;
+  if (rank_deficient(R, [&](int c) { return sR0[c][c]; })) bad |= FLAG_RANKDEF;
   // back substitution of R0 ahat = vu, one row per thread of the first four
   // waves, in place in sA
   if (tid < 256) {
@@ -609,10 +608,9 @@ __global__ __launch_bounds__(FH_NT) void finish_update_h(FinishArgs f) {
   }
   __syncthreads();
   if (tid == 0) {
-    for (int c = 0; c < R; ++c) {
-      if (slam[c] == 0.0) bad |= FLAG_RANKDEF;
+    if (rank_deficient(R, [&](int c) { return slam[c]; })) bad |= FLAG_RANKDEF;
+    for (int c = 0; c < R; ++c)
       if (!isfinite(slam[c])) bad |= FLAG_NONFINITE;
-    }
   }
 #pragma unroll
   for (int u = 0; u < HW; ++u) {
@@ -738,8 +736,7 @@ __global__ __launch_bounds__(FH_NT) void finish_update_h(FinishArgs f) {
     if (tid < RMAX) qs[tid] = sm.sgn[tid];
   }
   if (tid == 0) {
-    for (int c = 0; c < R && c < I; ++c)
-      if (!(wy.Rm[c][c] > 0.0)) bad |= FLAG_RANKDEF;
+    if (rank_deficient(R < I ? R : I, [&](int c) { return wy.Rm[c][c]; })) bad |= FLAG_RANKDEF;
     finish_state_tail(f, st, sc, bad);
   }
 }
@@ -808,8 +805,7 @@ __global__ __launch_bounds__(FT_THREADS) void finish_tall(FinishArgs f) {
   const double cp = 1.0 + beta, cq = -f.alpha * beta;
   __syncthreads();
   int bad = 0;
-  for (int c = 0; c < R; ++c)
-    if (!(sR0[c][c] != 0.0)) bad |= FLAG_RANKDEF;
+  if (rank_deficient(R, [&](int c) { return sR0[c][c]; })) bad |= FLAG_RANKDEF;
   double sc[2] = {0.0, 0.0};
   double cn[RMAX];
 #pragma unroll
@@ -871,10 +867,9 @@ __global__ __launch_bounds__(FT_THREADS) void finish_tall(FinishArgs f) {
   }
   __syncthreads();
   if (tid == 0) {
-    for (int c = 0; c < R; ++c) {
-      if (slam[c] == 0.0) bad |= FLAG_RANKDEF;
+    if (rank_deficient(R, [&](int c) { return slam[c]; })) bad |= FLAG_RANKDEF;
+    for (int c = 0; c < R; ++c)
       if (!isfinite(slam[c])) bad |= FLAG_NONFINITE;
-    }
   }
   // A = Ahat / lambda (the rows were written by this workgroup above; the
   // barriers since then order those stores before these loads)
@@ -892,10 +887,7 @@ __global__ void tall_factor_tail(int64_t n, int R, const double* __restrict__ q6
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q32 != nullptr && i < n) ((gfloat*)q32)[i] = (float)((const gdouble*)q64)[i];
   if (blockIdx.x == 0 && threadIdx.x == 0 && st != nullptr) {
-    int bad = 0;
-    for (int c = 0; c < R; ++c)
-      if (!(Rn[c + (int64_t)R * c] > 0.0)) bad |= FLAG_RANKDEF;
-    if (bad) atomicOr(&st->flags, bad);
+    if (rank_deficient(R, [&](int c) { return Rn[c + (int64_t)R * c]; })) atomicOr(&st->flags, FLAG_RANKDEF);
   }
 }
 
@@ -1013,6 +1005,38 @@ __global__ void state_init_kernel(DevState* s, const double* part, int nparts) {
 
 hipError_t launch_state_init(DevState* s, const double* part, int nparts, hipStream_t st) {
   hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, st, s, part, nparts);
+  return hipGetLastError();
+}
+
+// Rank test of the initial factors' R factors (after the QRs of the
+// "Initialize" step of Algorithms 2 and 3): mode n's diagonal has
+// min(I_n, R) entries; a relative test (rank_deficient) flags dependent
+// initial columns before the first sweep.
+struct InitRank {
+  const double* rf;   // N x R x R column-major R factors
+  int N, R;
+  int rows[CPQR_MAX_ORDER];   // min(I_n, R)
+  DevState* st;
+};
+
+__global__ void init_rank_check(InitRank a) {
+  const int n = threadIdx.x;
+  if (n >= a.N) return;
+  const gdouble* r = (const gdouble*)a.rf + (int64_t)n * a.R * a.R;
+  if (rank_deficient(a.rows[n], [&](int c) { return r[c + (int64_t)a.R * c]; }))
+    atomicOr(&a.st->flags, FLAG_RANKDEF);
+}
+
+hipError_t launch_init_rank_check(const double* rf, int N, int R, const int64_t* dims, DevState* st,
+                                  hipStream_t s) {
+  if (N < 1 || N > CPQR_MAX_ORDER) return hipErrorInvalidValue;
+  InitRank a{};
+  a.rf = rf;
+  a.N = N;
+  a.R = R;
+  for (int k = 0; k < N; ++k) a.rows[k] = (int)(dims[k] < R ? dims[k] : R);
+  a.st = st;
+  hipLaunchKernelGGL(init_rank_check, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

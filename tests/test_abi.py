@@ -103,7 +103,9 @@ def test_schedule_rejects_bad_arguments():
     (dict(dims=[40, 40, 40], rank=5, raw={"extrapolate": 4}), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, extrapolate="learned"), C.EINVAL),   # learned needs mlp_weights
     (dict(dims=[40, 40, 40], rank=5, extrapolate="learned", mlp_weights=True), C.OK),
-    (dict(dims=[40, 40, 40], rank=5, raw={"null_init": True}), C.EINVAL),
+    (dict(dims=[40, 40, 40], rank=5, raw={"null_init": True}), C.OK),      # seeded N(0,1) factors
+    (dict(dims=[40, 40, 40], rank=5, flags=0x10 | 0x2), C.EINVAL),        # phase and kernel timing
+    (dict(dims=[40, 40, 40], rank=5, flags=0x10), C.OK),
     (dict(dims=[40, 40, 40], rank=5, raw={"null_init_k": 1}), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, raw={"null_dims": True}), C.EINVAL),
     (dict(dims=[40, 0, 40], rank=5), C.EINVAL),

@@ -279,7 +279,7 @@ def test_tolerance_stop(P):
     assert abs(f[-1] - f[-2]) < 1e-9
 
 
-@pytest.mark.parametrize("mode", ["nan", "zero", "zero_column", "small_modes"])
+@pytest.mark.parametrize("mode", ["nan", "zero", "zero_column", "duplicate_column", "small_modes"])
 def test_error_paths(P, mode):
     import torch
     prob = G.make_problem([12, 10, 9], 3, seed=30, rho=0.01, dtype=np.float32)
@@ -296,6 +296,14 @@ def test_error_paths(P, mode):
         # a zero initial column makes R_2 and hence Z_1 = R_3 (.) R_2 lose a
         # column exactly, so R0 has a zero diagonal at the first update
         init[1][:, 2] = 0.0
+        expect = P.cpqr.ERANKDEF
+    elif mode == "duplicate_column":
+        # duplicate initial columns: the initial R_2 has a rounding-level
+        # diagonal entry, which the relative rank test flags (the oracle
+        # raises on the same input)
+        init[1][:, 2] = init[1][:, 0]
+        with pytest.raises(O.RankDeficient):
+            O.cp_als_qr(X.astype(np.float64), 3, init, 5, tree="restructured")
         expect = P.cpqr.ERANKDEF
     else:
         # two modes of size 1: Z_3 = R_2 (.) R_1 has 1 < 3 nonzero rows
@@ -341,3 +349,41 @@ def test_full_size_order4_and_order5_first_sweep(P):
             cos = np.abs(np.sum(a * b, axis=0))
             assert np.all(cos > 1 - 1e-4)
         del x
+
+
+@pytest.mark.parametrize("prec,seed", [("fp64", 0), ("fp32", 12345)])
+def test_seeded_initial_factors_match_the_oracle(P, prec, seed):
+    """init_factors == NULL: the library draws the initial factors from its
+    own SplitMix64 / Box-Muller generator; the oracle draws them from its own
+    implementation of the same published definition.  Same run to the
+    float64 / float32 tolerances."""
+    dt = np.float64 if prec == "fp64" else np.float32
+    prob = G.make_problem([14, 11, 13], 4, seed=61, rho=0.01, dtype=dt)
+    x, dims = P.to_device(prob.X)
+    g = P.cp_als_qr(x, 4, None, 12, dims=dims, tree="restructured", prec=prec, seed=seed,
+                    explicit_fit=True)
+    o = O.cp_als_qr(prob.X.astype(np.float64), 4, None, 12, tree="restructured", seed=seed)
+    if prec == "fp64":
+        assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+        for a, b in zip(g["factors"], o["factors"]):
+            assert np.max(np.abs(a - b)) <= 1e-8
+    else:
+        _check_fp32(g, o)
+
+
+def test_phase_seconds_cover_the_sweep(P):
+    """CPQR_FLAG_TIME_PHASES: the Section 4.2 categories are all timed, the
+    results equal the graph-replayed run bit for bit, and the phases add up
+    to the device time of the sweeps (up to the host waits between sweeps)."""
+    prob = G.workload("small_o4")
+    x, dims = P.to_device(prob.X)
+    t = P.cp_als_qr(x, prob.rank, prob.init, 6, dims=dims, tree="restructured", time_phases=True)
+    g = P.cp_als_qr(x, prob.rank, prob.init, 6, dims=dims, tree="restructured")
+    assert np.array_equal(t["fits"], g["fits"])
+    ph = t["phase_seconds"]
+    assert set(ph) == {"ttm", "qr", "q0", "apply_q0", "other"}
+    for k in ("ttm", "qr", "q0", "apply_q0"):
+        assert ph[k] > 0.0, ph
+    assert ph["other"] >= 0.0
+    assert sum(ph.values()) <= t["seconds"] * 1.001 + 1e-6, (ph, t["seconds"])
+    assert all(v == 0.0 for v in g["phase_seconds"].values())

@@ -81,6 +81,27 @@ def test_batched_paper_extrapolation_vs_oracle(P):
         assert g["beta_sweep"] == o["beta_sweep"] and g["beta"] == o["beta"]
 
 
+def test_batched_per_problem_extrapolation_settings(P):
+    """alpha, switch_delta and fixed_beta are per-problem options: a batch with
+    different values runs each problem with its own, compared with that
+    problem's own oracle run."""
+    probs = [G.make_problem([20, 22, 18], 4, seed=31, congruence=0.6, rho=0.05, dtype=np.float32),
+             G.make_problem([26, 24, 22], 5, seed=32, congruence=0.7, rho=0.02, dtype=np.float32),
+             G.make_problem([24, 28, 20], 6, seed=33, congruence=0.5, rho=0.03, dtype=np.float32)]
+    fbs, alphas = [0.05, 0.0, 0.01], [0.1, 0.5, 1.0]
+    res = _run(P, probs, 12, extrapolate="paper", fixed_beta=fbs, alpha=alphas,
+               switch_delta=[0.03, 0.2, 0.03])
+    for g, p, fb, al, dl in zip(res, probs, fbs, alphas, [0.03, 0.2, 0.03]):
+        o = O.cp_als_qr(p.X.astype(np.float64), p.rank, p.init, 12, tree="restructured",
+                        extrap="paper", alpha=al, delta=dl, fix_beta=(fb if fb > 0 else None))
+        assert g["orders"] == o["orders"]
+        for fg, fo in zip(g["fits"], o["fits"]):
+            assert abs(fg - fo) <= _fit_tol(fo), (fg, fo)
+        assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-6, (g["fit_explicit"], o["fitx"])
+        if fb == 0.0:
+            assert g["beta_sweep"] == o["beta_sweep"] and g["beta"] == o["beta"]
+
+
 def test_batched_modes_below_the_rank_vs_oracle(P):
     """Problems with a mode smaller than the rank (compact factor QR) in one
     batch with ordinary ones."""

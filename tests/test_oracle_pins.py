@@ -446,3 +446,48 @@ def test_generator_second_noise_term_and_per_mode_congruence():
     assert abs(G.rho_from_l1(0.1) - 1 / math.sqrt(999.0)) < 1e-16
     t = G.table8_problem(10, dims=[24, 22, 21, 20], dtype=np.float64)
     assert t.rank == 10 and t.meta["true_rank"] == 20 and t.X.shape == (24, 22, 21, 20)
+
+
+# ------------------------------------------- seeded initial factors, rank test
+def test_splitmix64_reference_outputs():
+    """SplitMix64 seeded with 0: the first outputs of the published reference
+    implementation (splitmix64.c, Vigna) are e220a8397b1dcdaf,
+    6e789e6aa1b965f4, 06c45d188009454f; output j is the state after j + 1
+    golden-ratio steps through the finaliser, so it is independent of how the
+    outputs are requested."""
+    z = O.splitmix64(0, np.arange(3, dtype=np.uint64))
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    # counter form: output 1000 on its own equals the 1001st of a run
+    run = O.splitmix64(12345, np.arange(1001, dtype=np.uint64))
+    assert int(O.splitmix64(12345, np.array([1000], dtype=np.uint64))[0]) == int(run[-1])
+
+
+def test_seeded_normal_factors_are_standard_normal():
+    import scipy.stats
+    f = O.seeded_normal_factors(7, [400, 300, 250], 64)
+    assert [a.shape for a in f] == [(400, 64), (300, 64), (250, 64)]
+    z = np.concatenate([a.ravel(order="F") for a in f])
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 5 / math.sqrt(z.size) and abs(z.var() - 1) < 5 * math.sqrt(2 / z.size)
+    # consecutive entries are uncorrelated; another seed gives other values
+    assert abs(np.corrcoef(z[:-1], z[1:])[0, 1]) < 5 / math.sqrt(z.size)
+    g = O.seeded_normal_factors(8, [400], 64)[0]
+    assert not np.allclose(g, f[0])
+    # the counter runs across modes: mode 2 continues where mode 1 ended
+    h = O.seeded_normal_factors(7, [400 + 300], 64)[0]
+    assert np.array_equal(np.concatenate([f[0].ravel(order="F"), f[1].ravel(order="F")]),
+                          h.ravel(order="F")[:(400 + 300) * 64])
+
+
+def test_rank_test_flags_duplicate_initial_columns_and_passes_ill_conditioned_ones():
+    p = G.make_problem([12, 10, 9], 3, seed=30, rho=0.01)
+    init = [a.copy() for a in p.init]
+    init[1][:, 2] = init[1][:, 0]
+    with pytest.raises(O.RankDeficient):
+        O.cp_als_qr(p.X, 3, init, 3)
+    # near-collinear but resolvable columns (an independent perturbation of
+    # relative size 1e-6) still run
+    init = [a.copy() for a in p.init]
+    init[1][:, 2] = init[1][:, 0] + 1e-6 * rng(31).standard_normal(init[1].shape[0])
+    res = O.cp_als_qr(p.X, 3, init, 3)
+    assert np.isfinite(res["fitx"])
