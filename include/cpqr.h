@@ -102,7 +102,8 @@ cpqr_status cpqr_create(cpqr_handle **handle, int device, void *hip_stream);
 cpqr_status cpqr_destroy(cpqr_handle *handle);
 
 /* Message describing the last error on this handle ("" if none).  The
- * string is owned by the handle. */
+ * string is owned by the handle.  With handle == NULL: the message of the
+ * last failed cpqr_qr_noalloc call on the calling host thread. */
 const char *cpqr_last_error(const cpqr_handle *handle);
 /* Static name of a status code. */
 const char *cpqr_status_string(int status);
@@ -322,6 +323,34 @@ cpqr_status cpqr_ttm(cpqr_handle *handle, int prec, int order, const int64_t *di
  */
 cpqr_status cpqr_qr(cpqr_handle *handle, int64_t M, int R, const double *A,
                     double *Q, double *Rout);
+
+/*
+ * cpqr_qr_noalloc -- cpqr_qr for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arithmetic and results as cpqr_qr (the same kernels),
+ * but no handle: the TSQR scratch lives in a fixed device array of
+ * CPQR_QR_NOALLOC_SCRATCH_BYTES per device, held until the process ends, and
+ * the call allocates nothing (no hipMalloc/hipFree, no allocating library
+ * routine).  Runs on the current device (hipSetDevice) and enqueues on
+ * `hip_stream` (a hipStream_t; NULL = the default stream) without
+ * synchronising: Q and Rout are ready when the stream reaches the call.
+ *  A    : device, M x R float64, column-major (caller-owned, read only).
+ *  Q    : device, M x R float64, column-major (caller-owned output).
+ *  Rout : device, R x R float64, column-major, upper triangular with a
+ *         non-negative diagonal (caller-owned output).
+ * All calls on one device share that device's scratch, which keeps the last
+ * call's contents: calls that overlap on one device (several streams or
+ * host threads) race and must be serialised by the caller.
+ * Errors (checked before any device work; message via cpqr_last_error(NULL)):
+ * CPQR_EINVAL for null pointers or R > M; CPQR_EUNSUPPORTED for R > 32,
+ * sizes beyond the two-level TSQR, or when the TSQR's scratch
+ * (P leaves x leaf rows x R + 3 P R^2 doubles) exceeds the fixed array
+ * (M <= 8192 at R = 32, 29,696 at R = 16, 59,904 at R = 8); CPQR_EHIP if the
+ * scratch's device address cannot be obtained or a launch fails.
+ */
+#define CPQR_QR_NOALLOC_SCRATCH_BYTES (4LL * 1024 * 1024)
+cpqr_status cpqr_qr_noalloc(int64_t M, int R, const double *A, double *Q,
+                            double *Rout, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -74,7 +74,7 @@ EXPORTS = ["cpqr_create", "cpqr_destroy", "cpqr_last_error", "cpqr_status_string
            "cpqr_check_args", "cpqr_als_qr", "cpqr_session_create", "cpqr_session_sweeps",
            "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy",
            "cpqr_schedule", "cpqr_ttm", "cpqr_qr", "cpqr_als_qr_batched",
-           "cpqr_mlp_forward", "cpqr_mlp_grad", "cpqr_mlp_train"]
+           "cpqr_mlp_forward", "cpqr_mlp_grad", "cpqr_mlp_train", "cpqr_qr_noalloc"]
 
 _lib = None
 
@@ -113,13 +113,14 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.cpqr_ttm.argtypes = [vp, i32, i32, ctypes.POINTER(i64), i32, i32, vp, vp, vp]
     L.cpqr_qr.argtypes = [vp, i64, i32, vp, vp, vp]
+    L.cpqr_qr_noalloc.argtypes = [i64, i32, vp, vp, vp, vp]
     L.cpqr_als_qr_batched.argtypes = [vp, i32, ctypes.POINTER(_Tensor), ctypes.POINTER(i32),
                                       ctypes.POINTER(_Options), ctypes.POINTER(_Result)]
     L.cpqr_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
     L.cpqr_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     L.cpqr_mlp_train.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
     for f in ("cpqr_create", "cpqr_destroy", "cpqr_check_args", "cpqr_als_qr", "cpqr_schedule",
-              "cpqr_ttm", "cpqr_qr", "cpqr_session_create", "cpqr_session_sweeps",
+              "cpqr_ttm", "cpqr_qr", "cpqr_qr_noalloc", "cpqr_session_create", "cpqr_session_sweeps",
               "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy"):
         getattr(L, f).restype = i32
     _lib = L
@@ -489,6 +490,32 @@ def qr(A, handle: Optional[Handle] = None):
                    ctypes.c_void_p(Rm.data_ptr()))
     h.check(st)
     return Q, Rm
+
+
+def qr_noalloc(A, Q, Rm, stream=None) -> int:
+    """Householder QR of a column-major float64 M x R torch tensor into the
+    caller's Q (M x R) and Rm (R x R), both column-major float64 on A's
+    device, through the entry point that allocates nothing.  Enqueued on
+    `stream` (default: torch's current stream of A's device) without
+    synchronising.  Returns the status code; raises on a malformed call."""
+    import torch
+    L = load_library()
+    M, R = int(A.shape[0]), int(A.shape[1])
+    for name, t, shape in (("A", A, (M, R)), ("Q", Q, (M, R)), ("Rm", Rm, (R, R))):
+        if t.dtype != torch.float64 or tuple(t.shape) != shape or t.stride() != (1, shape[0]) \
+                or t.device != A.device:
+            raise ValueError(f"{name} must be a column-major float64 {shape[0]} x {shape[1]} tensor "
+                             "on A's device")
+    if stream is None:
+        stream = torch.cuda.current_stream(A.device)
+    with torch.cuda.device(A.device):
+        return int(L.cpqr_qr_noalloc(M, R, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(Q.data_ptr()),
+                                     ctypes.c_void_p(Rm.data_ptr()), ctypes.c_void_p(stream.cuda_stream)))
+
+
+def noalloc_last_error() -> str:
+    """Message of the last failed cpqr_qr_noalloc call on this thread."""
+    return load_library().cpqr_last_error(None).decode()
 
 
 def schedule(order: int, tree: str, sweeps: int) -> Tuple[List[List[int]], List[Tuple[int, int, int]], Dict]:

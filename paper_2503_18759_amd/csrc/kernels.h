@@ -100,6 +100,8 @@ struct TsqrArgs {
   double* Q0;           // M x R output (explicit Q)
 };
 hipError_t launch_tsqr(const TsqrArgs& t, hipStream_t st);
+// Message of the last failed cpqr_qr_noalloc call on this host thread.
+const char* noalloc_last_error();
 
 // Per-problem arguments of the TSQR kernels (one entry per problem of a
 // batch; a single problem passes its entry by value).

@@ -669,7 +669,7 @@ cpqr_status cpqr_destroy(cpqr_handle* h) {
   return CPQR_OK;
 }
 
-const char* cpqr_last_error(const cpqr_handle* h) { return h ? h->err.c_str() : ""; }
+const char* cpqr_last_error(const cpqr_handle* h) { return h ? h->err.c_str() : noalloc_last_error(); }
 
 cpqr_status cpqr_schedule(int order, int tree, int sweeps, int* orders_out, int* steps_out,
                           int max_steps, int* n_steps, double* flops_out) {
