@@ -1,0 +1,189 @@
+// Column-distributed Householder QR of a block held in registers (the
+// compact QRs of Section 2.4: the factor QR of every mode update and the QR
+// Z_n = Q0 R0 of Algorithm 2), for one workgroup of NW waves (4: one per
+// SIMD, 8: two per SIMD, for blocks whose rows do not fit four waves'
+// registers).
+//
+// Layout: wave w owns the CPW = RMAX / NW consecutive columns
+// [CPW w, CPW w + CPW) of the block, every row of them: lane l holds rows
+// l + 64 p (p < RPL) of its columns in a[p][q].  A column step then needs no
+// workgroup-wide reduction: every wave reads the current column x_j (below
+// the pivot) from an LDS broadcast buffer written by the wave that owns it,
+// forms the dot products of x_j with its own columns and ||x_j||^2 in
+// registers, reduces those CPW + 1 values over its own 64 lanes, computes the
+// reflector scalars redundantly and updates only its own columns.  The owner
+// of column j+1 then publishes its columns (updated) into the other half of
+// the double buffer, and one barrier per column separates the steps.
+//
+// Reflector convention, storage and T are those of block_qr (qr_device.h):
+// x = column j from row j down; beta = -sign(x0) ||x||, v = x / (x0 - beta)
+// with v_j = 1, tau = (beta - x0) / beta (tau = 0 when the part below the
+// pivot is exactly zero); below the diagonal column j keeps x, R[j][j] = beta_j
+// and scale_j = 1 / (x0 - beta) are kept in LDS, U[m][j] = v_m^T v_j (m < j)
+// feeds block_qr_build_t.
+//
+// prof(j) bounds the rows of column j that can be nonzero (below it the
+// column is exactly zero, and the reflector leaves those rows untouched):
+// the row count for a dense block, or (j+1)^K for Z_n with its rows in
+// staircase order.  It must be non-decreasing in j.  Row chunks of 64 at or
+// beyond prof(j) are skipped in step j (STAIR below).
+#pragma once
+
+#include "common.h"
+#include "qr_device.h"
+
+namespace cpqr {
+
+template <int RMAX, int NW>
+struct ColCfg {
+  static constexpr int NT = 64 * NW;
+  static constexpr int CPW = RMAX / NW;                          // columns per wave
+  // values reduced per column step: CPW dot products and ||x||^2, padded to
+  // a power of two
+  static constexpr int NV = CPW + 1 <= 2 ? 2 : (CPW + 1 <= 4 ? 4 : (CPW + 1 <= 8 ? 8 : 16));
+  static_assert(CPW >= 1 && CPW * NW == RMAX, "RMAX must be a multiple of the wave count");
+};
+
+// Column q (a compile-time index) of this wave's register block into the
+// broadcast buffer, rows of the first `nch` chunks.
+template <int Q, int RMAX, int RPL, int NW>
+__device__ __forceinline__ void col_publish(const double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)], int nch,
+                                            double* __restrict__ xb) {
+  const int lane = threadIdx.x & 63;
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    if (p < nch) xb[lane + 64 * p] = a[p][Q];
+  });
+}
+
+// STAIR: prof(j) may be below the block's rows, and each column step runs
+// a body compiled for the number of active chunks rounded up to a power of
+// two (one branch per step); otherwise every chunk is active in every step.
+// The loops over chunks need no guard beyond that: rows outside prof(j) hold
+// zeros in x_j, so their coefficients are zero and their products exact
+// zeros.  The column loop is unrolled by CPW, so that the wave that owns
+// column j (wave j / CPW) and the local column of j are known when the body
+// is compiled: the owner updates only its columns after j, waves with
+// earlier columns only form the entries of U, and the next column is
+// published from a fixed register.
+template <int RMAX, int RPL, int NW, bool STAIR, typename Prof>
+__device__ __forceinline__ void col_qr(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)], int R, Prof&& prof,
+                                       double (*xb)[64 * RPL], QrSmem<RMAX>& sm) {
+  constexpr int CPW = ColCfg<RMAX, NW>::CPW, NV = ColCfg<RMAX, NW>::NV;
+  constexpr int G = 64 / NV;   // lanes per reduced value
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto chunks = [&](int j) __attribute__((always_inline)) { return STAIR ? (prof(j) + 63) >> 6 : RPL; };
+  // column 0 (wave 0, local column 0) into buffer 0
+  if (wave == 0) col_publish<0, RMAX, RPL, NW>(a, chunks(0), xb[0]);
+  __syncthreads();
+  for (int jb = 0; jb * CPW < R; ++jb) {
+    static_for<0, CPW>([&](auto jjc) __attribute__((always_inline)) {
+      constexpr int jj = decltype(jjc)::value;
+      const int j = jb * CPW + jj;
+      if (j >= R) return;
+      const int buf = j & 1;
+      auto step = [&](auto nchc) __attribute__((always_inline)) {
+        constexpr int NCH = decltype(nchc)::value;   // active chunks
+        const double x0 = xb[buf][j];
+        // x_j below the pivot (rows > j; the pivot row is in chunk 0, j < 64)
+        double x[NCH];
+        static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          const double v = xb[buf][lane + 64 * p];
+          x[p] = (p > 0 || lane > j) ? v : 0.0;
+        });
+        // dot products with this wave's columns and ||x||^2 (value CPW)
+        double d[NV];
+        static_for<0, NV>([&](auto vc) __attribute__((always_inline)) { d[decltype(vc)::value] = 0.0; });
+        static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            d[q] = fma(x[p], a[p][q], d[q]);
+          });
+          d[CPW] = fma(x[p], x[p], d[CPW]);
+        });
+        wave_transpose_reduce<NV>(d);
+        const double st = lane_read(d[0], G * CPW);
+        double tau, beta, scale;
+        qr_reflector_scalars(x0, st, &tau, &beta, &scale);
+        // w_c = v^T a_c = a[j][c] + scale sum_{i>j} x_i a[i][c] (wave-uniform)
+        auto wcol = [&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          return fma(scale, lane_read(d[0], G * q), lane_read(a[0][q], j));
+        };
+        // a -= tau v w^T for columns q in [Q0, CPW) (v = x scale below the
+        // pivot, v_j = 1)
+        auto update = [&](auto q0c) __attribute__((always_inline)) {
+          constexpr int Q0 = decltype(q0c)::value;
+          double w[CPW];
+          static_for<Q0, CPW>([&](auto qc) __attribute__((always_inline)) { w[decltype(qc)::value] = wcol(qc); });
+          const double ts = tau * scale;
+          static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+            constexpr int p = decltype(pc)::value;
+            const double coef = (p > 0 || lane > j) ? ts * x[p] : ((lane == j) ? tau : 0.0);
+            static_for<Q0, CPW>([&](auto qc) __attribute__((always_inline)) {
+              constexpr int q = decltype(qc)::value;
+              a[p][q] = fma(-coef, w[q], a[p][q]);
+            });
+          });
+        };
+        // U[c][j] = v_c^T v_j = scale_c w_c for finished columns c < j; the
+        // scale_c factor is applied after the loop
+        auto ustore = [&](auto q1c) __attribute__((always_inline)) {
+          constexpr int Q1 = decltype(q1c)::value;
+          double w[CPW > 0 ? CPW : 1];
+          static_for<0, Q1>([&](auto qc) __attribute__((always_inline)) { w[decltype(qc)::value] = wcol(qc); });
+          if (lane == 0) {
+            static_for<0, Q1>([&](auto qc) __attribute__((always_inline)) {
+              constexpr int q = decltype(qc)::value;
+              sm.U[CPW * wave + q][j] = w[q];
+            });
+          }
+        };
+        if (wave > jb) {
+          update(std::integral_constant<int, 0>{});
+        } else if (wave == jb) {
+          update(std::integral_constant<int, jj + 1>{});
+          ustore(std::integral_constant<int, jj>{});
+        } else {
+          ustore(std::integral_constant<int, CPW>{});
+        }
+        if (tid == 0) {
+          sm.tau[j] = tau;
+          sm.beta[j] = beta;
+          sm.scale[j] = scale;
+        }
+      };
+      if constexpr (!STAIR) {
+        step(std::integral_constant<int, RPL>{});
+      } else {
+        const int nch = chunks(j);
+        if (nch <= 1) step(std::integral_constant<int, 1>{});
+        else if (nch <= 2 || RPL <= 2) step(std::integral_constant<int, (RPL < 2 ? RPL : 2)>{});
+        else if (nch <= 4 || RPL <= 4) step(std::integral_constant<int, (RPL < 4 ? RPL : 4)>{});
+        else if (nch <= 8 || RPL <= 8) step(std::integral_constant<int, (RPL < 8 ? RPL : 8)>{});
+        else step(std::integral_constant<int, RPL>{});
+      }
+      // the owner of column j + 1 publishes it (updated) for the next step
+      const int jn = j + 1;
+      if (jn < R) {
+        if constexpr (jj + 1 < CPW) {
+          if (wave == jb) col_publish<jj + 1, RMAX, RPL, NW>(a, chunks(jn), xb[buf ^ 1]);
+        } else {
+          if (wave == jb + 1) col_publish<0, RMAX, RPL, NW>(a, chunks(jn), xb[buf ^ 1]);
+        }
+      }
+      __syncthreads();
+    });
+  }
+  // U entries were stored without the scale of their earlier column
+  for (int e = tid; e < RMAX * RMAX; e += ColCfg<RMAX, NW>::NT) {
+    const int m = e / RMAX, jc = e % RMAX;
+    if (m < jc && jc < R) sm.U[m][jc] *= sm.scale[m];
+  }
+  __syncthreads();
+  block_qr_build_t<RMAX>(R, sm);
+}
+
+}  // namespace cpqr

@@ -21,6 +21,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "qr_device.h"
+#include "colqr_device.h"
 
 namespace cpqr {
 
@@ -776,6 +777,209 @@ __global__ __launch_bounds__(256) void form_qn_h(FinishArgs f) {
   }
 }
 
+// ------------------------------------------------ column-distributed layout
+// finish_update for factors of at most 256 rows, the factor QR in the
+// column-distributed layout of col_qr (colqr_device.h) with four waves (one
+// per SIMD): wave w owns columns [CPW w, CPW w + CPW) of every row, so the
+// column norms (lambda) and every reduction of a Householder step stay
+// inside one wave.  The arithmetic per entry is that of finish_update (same
+// Vu, solve, lambda, reflector convention and T) except that the solve
+// multiplies by the reciprocals of R0's diagonal; the reflectors go to
+// form_qn for the explicit Q_n, off the next update's Z QR path.  Layout of
+// f.qn: V rows (I x R column-major) at 0, V1 and T (RMAX x RMAX row-major)
+// at QN_V1 and QN_T, the signs of diag(R) at QN_SGN.
+static constexpr int QN_V1 = 256 * 32, QN_T = QN_V1 + 32 * 32, QN_SGN = QN_T + 32 * 32;
+static constexpr int FC_NW = 4, FC_NT = 64 * FC_NW;
+
+template <int RMAX, int RPL>
+__global__ __launch_bounds__(FC_NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void finish_col(FinishArgs f0, const FinishArgs* __restrict__ batch) {
+  const FinishArgs f = kernel_args(f0, batch, blockIdx.x);
+  using Cfg = ColCfg<RMAX, FC_NW>;
+  constexpr int CPW = Cfg::CPW, NV = Cfg::NV, G = 64 / NV, NT = FC_NT;
+  constexpr int MR = 64 * RPL;
+  constexpr int LDR = RMAX + 2;   // 16-byte aligned rows of R0
+  __shared__ QrSmem<RMAX> sm;
+  __shared__ __attribute__((aligned(16))) double sR0[RMAX][LDR];
+  __shared__ double rinv[RMAX];
+  __shared__ double sA[MR][RMAX + 1];
+  __shared__ double xb[2][MR];
+  __shared__ double sred2[FC_NW][2];
+  __shared__ double slam[RMAX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = CPW * wave;
+  const int I = f.I, R = f.R;
+  DevState* st = f.state;
+  const gdouble* __restrict__ gV = (const gdouble*)f.V;
+  for (int e = tid; e < RMAX * RMAX; e += NT) {
+    const int i = e / RMAX, c = e % RMAX;
+    const double r0 = ((const gdouble*)f.R0)[(i < R && c < R) ? i + R * c : 0];
+    sR0[i][c] = (i < R && c < R) ? r0 : 0.0;
+    if (i == c) rinv[c] = (c < R && r0 != 0.0) ? 1.0 / r0 : 0.0;
+  }
+  const bool active = (f.extrap != 0) && st->active;
+  const double beta = active ? st->beta : 0.0;
+  const double cp = 1.0 + beta, cq = -f.alpha * beta;
+  // Vu = (1 + beta) Vp - alpha beta Vq element by element (coalesced reads of
+  // the column-major I x R halves, all issued before they are used),
+  // <Vp,Vu> and ||Vu||^2
+  double sc[2] = {0.0, 0.0};
+  {
+    constexpr int NE = MR * RMAX / NT;
+    double vp[NE], vq[NE];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + NT * t;
+      const int r = e % MR, c = e / MR;
+      const int64_t g = (r < I && c < R) ? r + (int64_t)I * c : 0;
+      vp[t] = gV[g];
+      vq[t] = gV[(int64_t)I * R + g];
+    }
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + NT * t;
+      const int r = e % MR, c = e / MR;
+      const bool in = r < I && c < R;
+      const double p = in ? vp[t] : 0.0, q = in ? vq[t] : 0.0;
+      const double vu = active ? fma(cq, q, cp * p) : p;
+      sc[0] = fma(p, vu, sc[0]);
+      sc[1] = fma(vu, vu, sc[1]);
+      sA[r][c] = vu;
+    }
+  }
+  block_allreduce<2, FC_NW>(sc, sred2);   // its barriers also publish sR0, rinv and sA
+  // back substitution of R0 ahat = vu, one row per thread, in place in sA
+  static_assert(MR <= NT, "one row per thread");
+  if (tid < MR) {
+    double x[RMAX];
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) x[c] = sA[tid][c];
+    const bool row_in = tid < I;
+    static_for<0, RMAX>([&](auto ic) __attribute__((always_inline)) {
+      constexpr int c = RMAX - 1 - decltype(ic)::value;
+      double s = x[c];
+      static_for<c + 1, RMAX>([&](auto dc) __attribute__((always_inline)) {
+        constexpr int d = decltype(dc)::value;
+        s = fma(-sR0[c][d], x[d], s);
+      });
+      x[c] = row_in ? s * rinv[c] : 0.0;
+      __builtin_amdgcn_sched_barrier(0);
+    });
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) sA[tid][c] = x[c];
+  }
+  __syncthreads();
+  // this wave's columns of every row; lambda = column norms (a reduction over
+  // this wave's lanes only), A = Ahat / lambda
+  double a[RPL][CPW];
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      a[p][q] = sA[lane + 64 * p][c0 + q];
+    });
+  });
+  {
+    double cn[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cn[v] = 0.0;
+    static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p = decltype(pc)::value;
+      static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        cn[q] = fma(a[p][q], a[p][q], cn[q]);
+      });
+    });
+    wave_transpose_reduce<NV>(cn);
+    gdouble* __restrict__ gA = (gdouble*)f.A;
+    static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      const int c = c0 + q;
+      const double lam = sqrt(lane_read(cn[0], G * q));
+      const double inv = (c < R && lam != 0.0) ? 1.0 / lam : 0.0;
+      if (lane == 0 && c < R) {
+        slam[c] = lam;
+        ((gdouble*)f.lambda)[c] = lam;
+      }
+      static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        const int row = lane + 64 * p;
+        a[p][q] *= inv;
+        if (row < I && c < R) gA[row + (int64_t)I * c] = a[p][q];
+      });
+    });
+  }
+  // Householder QR of A (rows beyond I are zero)
+  col_qr<RMAX, RPL, FC_NW, false>(a, R, [&](int) { return I; }, xb, sm);
+  // R_n = D R (D = sign(diag R)) and the reflectors for form_qn
+  gdouble* __restrict__ qv = (gdouble*)f.qn;
+  static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+    constexpr int q = decltype(qc)::value;
+    const int c = c0 + q;
+    const double sc_c = sm.scale[c < R ? c : 0];
+    if (lane < RMAX) {
+      const int j = lane;
+      const double sg = (j < R && sm.beta[j] < 0.0) ? -1.0 : 1.0;
+      const bool in = (j < R) && (c < R);
+      const double rr = (c > j) ? a[0][q] : ((c == j) ? sm.beta[j] : 0.0);
+      if (in) ((gdouble*)f.Rn)[j + R * c] = sg * rr;
+      const double v1 = (j > c) ? a[0][q] * sc_c : ((j == c) ? 1.0 : 0.0);
+      qv[QN_V1 + j * RMAX + c] = in ? v1 : 0.0;
+      if (c == 0) qv[QN_SGN + j] = sg;
+    }
+    static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p = decltype(pc)::value;
+      const int row = lane + 64 * p;
+      const double v = (row > c) ? a[p][q] * sc_c : ((row == c) ? 1.0 : 0.0);
+      if (row < I && c < R) qv[row + (int64_t)I * c] = v;
+    });
+  });
+  for (int e = tid; e < RMAX * RMAX; e += NT) qv[QN_T + e] = sm.T[e / RMAX][e % RMAX];
+  if (tid == 0) {
+    int bad = 0;
+    if (rank_deficient(R, [&](int c) { return sR0[c][c]; })) bad |= FLAG_RANKDEF;
+    if (rank_deficient(R, [&](int c) { return slam[c]; })) bad |= FLAG_RANKDEF;
+    for (int c = 0; c < R; ++c)
+      if (!isfinite(slam[c])) bad |= FLAG_NONFINITE;
+    // a mode smaller than the rank has min(I, R) reflectors; |R_n[c][c]| = |beta_c|
+    if (rank_deficient(R < I ? R : I, [&](int c) { return sm.beta[c]; })) bad |= FLAG_RANKDEF;
+    finish_state_tail(f, st, sc, bad);
+  }
+}
+
+// Explicit Q_n = (E - V M) diag(sgn), M = T V1^T, from the reflectors that
+// finish_col leaves in f.qn (one row per thread, the WY product of
+// block_qr_wy_product and the row arithmetic of wy_q_row).
+template <int RMAX>
+__global__ __launch_bounds__(256) void form_qn(FinishArgs f0, const FinishArgs* __restrict__ batch) {
+  const FinishArgs f = kernel_args(f0, batch, blockIdx.x);
+  __shared__ QrSmem<RMAX> sm;
+  __shared__ QrWySmem<RMAX> wy;
+  const int tid = threadIdx.x;
+  const int I = f.I, R = f.R;
+  const gdouble* __restrict__ qv = (const gdouble*)f.qn;
+  gdouble* __restrict__ gq64 = (gdouble*)f.q64;
+  gfloat* __restrict__ gq32 = (gfloat*)f.q32;
+  for (int e = tid; e < RMAX * RMAX; e += 256) {
+    const int k = e / RMAX, c = e % RMAX;
+    wy.V1[k][c] = qv[QN_V1 + e];
+    sm.T[k][c] = qv[QN_T + e];
+  }
+  if (tid < RMAX) sm.sgn[tid] = qv[QN_SGN + tid];
+  __syncthreads();
+  block_qr_wy_product<RMAX, 256>(sm, wy, R, nullptr, 0);
+  const int r = tid;
+  if (r < I) {
+    double v[RMAX];
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m) v[m] = (m < R) ? qv[r + (int64_t)I * (m < R ? m : 0)] : 0.0;
+    wy_q_row<RMAX, RMAX, 0>(v, r, R, sm, wy, [&](int c, double val) {
+      if (gq64) gq64[r + (int64_t)I * c] = val;
+      if (gq32) gq32[r + (int64_t)I * c] = (float)val;
+    });
+  }
+}
+
 // ------------------------------------------------------------ tall factors
 // A mode with more rows than the single-workgroup factor QR holds in
 // registers: this kernel streams the rows in chunks of its 256 threads for
@@ -921,22 +1125,49 @@ static hipError_t finish_launch(int rm, int rp, unsigned blocks, const FinishArg
   return hipGetLastError();
 }
 
+// Rows per lane of finish_col for a factor of I rows (0: beyond its 256 rows).
+static int col_rpl(int I) { return I <= 64 ? 1 : (I <= 128 ? 2 : (I <= 256 ? 4 : 0)); }
+
+static hipError_t finish_col_launch(int rm, int rpl, unsigned blocks, const FinishArgs& f,
+                                    const FinishArgs* batch, hipStream_t st) {
+#define CPQR_FC(RM, RP) \
+  hipLaunchKernelGGL((finish_col<RM, RP>), dim3(blocks), dim3(FC_NT), 0, st, f, batch)
+#define CPQR_FC_RPL(RM) \
+  if (rpl == 1) CPQR_FC(RM, 1); else if (rpl == 2) CPQR_FC(RM, 2); else if (rpl == 4) CPQR_FC(RM, 4); \
+  else return hipErrorInvalidValue;
+  if (rm == 8) { CPQR_FC_RPL(8) }
+  else if (rm == 16) { CPQR_FC_RPL(16) }
+  else if (rm == 32) { CPQR_FC_RPL(32) }
+  else return hipErrorInvalidValue;
+#undef CPQR_FC_RPL
+#undef CPQR_FC
+  return hipGetLastError();
+}
+
+static hipError_t form_qn_launch(int rm, unsigned blocks, const FinishArgs& f, const FinishArgs* batch,
+                                 hipStream_t st) {
+  if (rm == 8) hipLaunchKernelGGL((form_qn<8>), dim3(blocks), dim3(256), 0, st, f, batch);
+  else if (rm == 16) hipLaunchKernelGGL((form_qn<16>), dim3(blocks), dim3(256), 0, st, f, batch);
+  else if (rm == 32) hipLaunchKernelGGL((form_qn<32>), dim3(blocks), dim3(256), 0, st, f, batch);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_finish_head(const FinishArgs& f, hipStream_t st, bool* tail) {
   *tail = false;
   if (f.I > CPQR_MAX_FACTOR_ROWS) return hipErrorInvalidValue;
-  if (qr_rmax(f.R) == 32 && f.I <= 256 && f.qn != nullptr) {
-    // half-row layout: 512 threads, rows r < 256; Q_n in form_qn_h
-    hipLaunchKernelGGL(finish_update_h, dim3(1), dim3(FH_NT), 0, st, f);
+  const int rm = qr_rmax(f.R), rpl = col_rpl(f.I);
+  if (rpl > 0 && f.qn != nullptr) {
+    // column-distributed layout: 512 threads, rows r < 256; Q_n in form_qn
     *tail = true;
-    return hipGetLastError();
+    return finish_col_launch(rm, rpl, 1, f, nullptr, st);
   }
-  return finish_launch(qr_rmax(f.R), factor_rpt(f.I), 1, f, nullptr, st);
+  return finish_launch(rm, factor_rpt(f.I), 1, f, nullptr, st);
 }
 
 hipError_t launch_finish_tail(const FinishArgs& f, hipStream_t st) {
   if (f.I > 256 || f.R > 32 || f.qn == nullptr) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(form_qn_h, dim3(1), dim3(256), 0, st, f);
-  return hipGetLastError();
+  return form_qn_launch(qr_rmax(f.R), 1, f, nullptr, st);
 }
 
 hipError_t launch_finish(const FinishArgs& f, hipStream_t st) {
