@@ -102,6 +102,7 @@ __device__ __forceinline__ void col_qr(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)]
             d[q] = fma(x[p], a[p][q], d[q]);
           });
           d[CPW] = fma(x[p], x[p], d[CPW]);
+          if constexpr (NCH > 4) __builtin_amdgcn_sched_barrier(0);
         });
         wave_transpose_reduce<NV>(d);
         const double st = lane_read(d[0], G * CPW);
@@ -179,6 +180,133 @@ __device__ __forceinline__ void col_qr(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)]
   }
   // U entries were stored without the scale of their earlier column
   for (int e = tid; e < RMAX * RMAX; e += ColCfg<RMAX, NW>::NT) {
+    const int m = e / RMAX, jc = e % RMAX;
+    if (m < jc && jc < R) sm.U[m][jc] *= sm.scale[m];
+  }
+  __syncthreads();
+  block_qr_build_t<RMAX>(R, sm);
+}
+
+
+// ---------------------------------------------------------------------------
+// The same factorisation for Z_n with its rows in staircase order, where
+// column c is nonzero only on its profile, the first (c+1)^K rows.  Columns
+// go to the waves round-robin (column c = NW q + w is local column q of wave
+// w), so that local column q of every wave stays below (NW (q+1))^K rows and
+// needs only L(q) of the RPL row chunks in registers: at rank 32 and K = 2
+// that is 1 + 4 + 9 + 16 = 30 chunks for 4 local columns instead of 64.  The
+// owner of column j is wave j mod NW, and it publishes all of its columns
+// (their live chunks) into the broadcast buffer, local column q at offset
+// 64 RPL q; the readers take column j at local column j / NW.
+template <int RMAX, int RPL, int NW, int K>
+struct StairCfg {
+  static constexpr int CPW = RMAX / NW;
+  static constexpr int MR = 64 * RPL;
+  static constexpr int L(int q) {
+    long long c = (long long)NW * (q + 1), pw = 1;
+    for (int k = 0; k < K; ++k) pw *= c;
+    const long long ch = (pw + 63) / 64;
+    return ch < RPL ? (int)ch : RPL;
+  }
+  static constexpr int OFF(int q) {
+    int o = 0;
+    for (int i = 0; i < q; ++i) o += L(i);
+    return o;
+  }
+  static constexpr int TOT = OFF(CPW);
+};
+
+template <int RMAX, int RPL, int NW, int K, typename Prof>
+__device__ __forceinline__ void col_qr_stair(double (&a)[(StairCfg<RMAX, RPL, NW, K>::TOT)], int R, Prof&& prof,
+                                             double (*xb)[(StairCfg<RMAX, RPL, NW, K>::CPW) * 64 * RPL],
+                                             QrSmem<RMAX>& sm) {
+  using SC = StairCfg<RMAX, RPL, NW, K>;
+  constexpr int CPW = SC::CPW, MR = SC::MR;
+  constexpr int NV = ColCfg<RMAX, NW>::NV, G = 64 / NV;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto chunks = [&](int j) __attribute__((always_inline)) { return (prof(j) + 63) >> 6; };
+  // every column of this wave into the buffer (live chunks only)
+  auto publish = [&](double* __restrict__ dst) __attribute__((always_inline)) {
+    static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      static_for<0, SC::L(q)>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        dst[q * MR + lane + 64 * p] = a[SC::OFF(q) + p];
+      });
+    });
+  };
+  if (wave == 0) publish(xb[0]);
+  __syncthreads();
+  for (int jb = 0; jb * NW < R; ++jb) {
+    static_for<0, NW>([&](auto jjc) __attribute__((always_inline)) {
+      constexpr int jj = decltype(jjc)::value;   // owner wave of column j
+      const int j = jb * NW + jj;
+      if (j >= R) return;
+      const int buf = j & 1;
+      const double* __restrict__ xj = xb[buf] + jb * MR;
+      const int nch = chunks(j);
+      auto step = [&](auto nchc) __attribute__((always_inline)) {
+        constexpr int NCH = decltype(nchc)::value;   // active chunks, rounded up
+        const double x0 = xj[j];
+        // chunks at or beyond nch of the buffer may hold an earlier column
+        // (the bucket rounds nch up), so they read as zero
+        double x[NCH];
+        static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          const double v = xj[lane + 64 * p];
+          x[p] = (p < nch && (p > 0 || lane > j)) ? v : 0.0;
+        });
+        double d[NV];
+        static_for<0, NV>([&](auto vc) __attribute__((always_inline)) { d[decltype(vc)::value] = 0.0; });
+        static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            if constexpr (p < SC::L(q)) d[q] = fma(x[p], a[SC::OFF(q) + p], d[q]);
+          });
+          d[CPW] = fma(x[p], x[p], d[CPW]);
+        });
+        wave_transpose_reduce<NV>(d);
+        const double st = lane_read(d[0], G * CPW);
+        double tau, beta, scale;
+        qr_reflector_scalars(x0, st, &tau, &beta, &scale);
+        const double ts = tau * scale;
+        double coef[NCH];
+        static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          coef[p] = (p > 0 || lane > j) ? ts * x[p] : ((lane == j) ? tau : 0.0);
+        });
+        static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          // w_c = v^T a_c for c = NW q + wave (wave-uniform)
+          const double w = fma(scale, lane_read(d[0], G * q), lane_read(a[SC::OFF(q)], j));
+          const bool after = (q > jb) || (q == jb && wave > jj);
+          const bool before = (q < jb) || (q == jb && wave < jj);
+          const double wu = after ? w : 0.0;
+          static_for<0, (NCH < SC::L(q) ? NCH : SC::L(q))>([&](auto pc) __attribute__((always_inline)) {
+            constexpr int p = decltype(pc)::value;
+            a[SC::OFF(q) + p] = fma(-coef[p], wu, a[SC::OFF(q) + p]);
+          });
+          // U[c][j] = v_c^T v_j without the scale_c factor (applied below)
+          if (lane == 0 && before) sm.U[NW * q + wave][j] = w;
+        });
+        if (tid == 0) {
+          sm.tau[j] = tau;
+          sm.beta[j] = beta;
+          sm.scale[j] = scale;
+        }
+      };
+      if (nch <= 1) step(std::integral_constant<int, 1>{});
+      else if (nch <= 2 || RPL <= 2) step(std::integral_constant<int, (RPL < 2 ? RPL : 2)>{});
+      else if (nch <= 4 || RPL <= 4) step(std::integral_constant<int, (RPL < 4 ? RPL : 4)>{});
+      else if (nch <= 8 || RPL <= 8) step(std::integral_constant<int, (RPL < 8 ? RPL : 8)>{});
+      else step(std::integral_constant<int, RPL>{});
+      // the owner of column j + 1 publishes its columns for the next step
+      if (j + 1 < R && wave == (jj + 1) % NW) publish(xb[buf ^ 1]);
+      __syncthreads();
+    });
+  }
+  for (int e = tid; e < RMAX * RMAX; e += 64 * NW) {
     const int m = e / RMAX, jc = e % RMAX;
     if (m < jc && jc < R) sm.U[m][jc] *= sm.scale[m];
   }

@@ -156,6 +156,31 @@ struct StairArgs {
 };
 hipError_t launch_zqr_stair(const StairPlan& pl, const StairArgs& a, hipStream_t st);
 hipError_t launch_zqr_stair_batched(const StairPlan& pl, int count, const StairArgs* args, hipStream_t st);
+// Khatri-Rao QR of Z_n (at most 1024 rows) in the column-distributed layout,
+// written in the compact form Q0 = (E - V T V1^T) D: V (M x R, Kolda rows),
+// R0 (R x R, diag >= 0) and meta = [Md = T V1^T D (R x R), D (R), piv (R)].
+struct ZcolPlan {
+  bool ok;
+  int rmax;     // column class
+  int rpl;      // rows per lane (64-row chunks of the staircase)
+  int nw;       // waves (4 or 8)
+  int k;        // other modes (N - 1)
+};
+ZcolPlan zcol_plan(int N, int R);
+struct ZcolArgs {
+  int N, n, R;          // order, skipped mode, rank
+  int64_t M;            // R^(N-1) rows of Z_n
+  const double* rf;     // N x R x R column-major R factors
+  const int* smap;      // M x 2 ints: Kolda row and packed digits of staircase row s
+  double* R0;           // R x R out
+  double* V;            // M x R out (Kolda row order)
+  double* meta;         // R^2 + 2R doubles out
+  int active;           // 0: nothing to do (batched entries of other plans)
+};
+// Staircase row table (host): out[2s] = Kolda row, out[2s+1] = digits (5 bits each).
+void stair_table(int R, int K, int64_t M, int* out);
+hipError_t launch_zqr_col(const ZcolPlan& pl, const ZcolArgs& a, hipStream_t st);
+hipError_t launch_zqr_col_batched(const ZcolPlan& pl, int count, const ZcolArgs* args, hipStream_t st);
 hipError_t launch_factor_qr(int I, int R, const double* A, double* Rn, double* q64, float* q32,
                             hipStream_t st);
 
@@ -173,6 +198,10 @@ struct ApplyArgs {
   double* V;            // 2 x I x R reduced [Vp | Vq]
   int nchunks;
   const DevState* state;
+  // compact Q0 (zqr_col): Q0 / Q0prev hold the reflectors V and these the
+  // R^2 + 2R words [Md, D, piv] of each; null: Q0 / Q0prev are explicit
+  const double* meta_p = nullptr;
+  const double* meta_q = nullptr;
 };
 int apply_num_chunks(int64_t M, int I);
 hipError_t launch_apply(const ApplyArgs& a, hipStream_t st);
@@ -187,6 +216,9 @@ struct ApplyDev {
   double* partial;
   double* V;
   const DevState* state;
+  const double* meta_p;
+  const double* meta_q;
+  int y_f64;
 };
 ApplyDev apply_dev(const ApplyArgs& a);
 unsigned apply_iblocks(int I);

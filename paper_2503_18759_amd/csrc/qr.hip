@@ -15,6 +15,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "qr_device.h"
+#include "colqr_device.h"
 
 namespace cpqr {
 
@@ -469,6 +470,210 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_stair(StairArgs a0, const StairArgs* __
       }
     }
   }
+}
+
+// ------------------------------------------------- column-distributed Z QR
+// Householder QR of Z_n (at most 1024 rows, rows in staircase order) in the
+// column-distributed layout of col_qr (colqr_device.h); the staircase bounds
+// every column step to the rows of its column's profile, (j+1)^K.  The
+// output is the compact form of Q0 rather than Q0 itself: with the sign fix
+// D = sign(diag R), Q0 = (E - V T V1^T) D, where V holds the reflectors
+// (unit lower trapezoidal, rows scattered back to the Kolda order), V1 its
+// first R rows and E the first R columns of the identity in staircase order,
+// i.e. the unit vectors of the Kolda rows piv_0 .. piv_{R-1} of the first R
+// staircase rows.  Then Y_(n) Q0 = (Y_E - (Y_(n) V) Md) D... with Md = T V1^T D
+// and Y_E = Y_(n)[:, piv] the product needs only Y_(n) V, which has the
+// shape of Y_(n) Q0, and an R x R correction (apply_partial, apply_reduce).
+// meta (R^2 + 2R doubles): Md (R x R column-major), the signs D, piv.
+template <int RMAX, int RPL, int NW, int K>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
+  const ZcolArgs args = kernel_args(a0, batch, blockIdx.x);
+  if (!args.active) return;
+  using SC = StairCfg<RMAX, RPL, NW, K>;
+  constexpr int CPW = SC::CPW, NT = 64 * NW, MR = SC::MR;
+  const int n = args.n, R = args.R;
+  const int M = (int)args.M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ QrSmem<RMAX> sm;
+  __shared__ double xb[2][CPW * MR];
+  __shared__ union ZcolLds {
+    double srf[K * RMAX * RMAX];   // R factors of the other modes (Z build)
+    double v1[RMAX][RMAX + 1];     // first R rows of V (epilogue)
+  } u;
+  {
+    // R factors of the other modes (ascending mode order), zero-padded to
+    // RMAX x RMAX so that columns c >= R of every product vanish
+    const gdouble* __restrict__ rf = (const gdouble*)args.rf;
+    for (int e = tid; e < K * RMAX * RMAX; e += NT) {
+      const int q = e / (RMAX * RMAX), rem = e % (RMAX * RMAX);
+      const int i = rem % RMAX, c = rem / RMAX;
+      const int mode = (q < n) ? q : q + 1;
+      const bool in = i < R && c < R;
+      const double x = rf[in ? (int64_t)mode * R * R + i + (int64_t)R * c : 0];
+      u.srf[e] = in ? x : 0.0;
+    }
+  }
+  __syncthreads();
+  // Z[s][c] = prod_k R_k[d_k(s)][c] for this wave's columns c = NW q + wave,
+  // rows s = lane + 64 p < 64 L(q) in staircase order (digits from the
+  // staircase table, 5 bits each)
+  typedef __attribute__((address_space(1))) const int2 gint2;
+  const gint2* __restrict__ smap = (const gint2*)args.smap;
+  double a[SC::TOT];
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    const int s = lane + 64 * p;
+    const bool in = s < M;
+    const int dig = in ? smap[s].y : 0;
+    static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      if constexpr (p < SC::L(q)) {
+        const int c = NW * q + wave;
+        double v = in ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) v *= u.srf[k * RMAX * RMAX + ((dig >> (5 * k)) & 31) + RMAX * c];
+        a[SC::OFF(q) + p] = v;
+      }
+    });
+  });
+  __syncthreads();   // the R factors in LDS are dead from here on
+  // rows in the profile of column j: min(M, (j+1)^K)
+  auto prof = [&](int j) __attribute__((always_inline)) {
+    int pw = 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) pw *= (j + 1);
+    return pw < M ? pw : M;
+  };
+  col_qr_stair<RMAX, RPL, NW, K>(a, R, prof, xb, sm);
+  // R0 = D R, V rows (Kolda order; rows beyond a column's live chunks are
+  // zero in the buffer from its set-up), V1 into LDS
+  gdouble* __restrict__ gR0 = (gdouble*)args.R0;
+  gdouble* __restrict__ gV = (gdouble*)args.V;
+  static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+    constexpr int q = decltype(qc)::value;
+    const int c = NW * q + wave;
+    const double sc_c = sm.scale[c < R ? c : 0];
+    if (lane < RMAX) {
+      const int j = lane;
+      const double sg = (j < R && sm.beta[j] < 0.0) ? -1.0 : 1.0;
+      const double x = a[SC::OFF(q)];
+      const double rr = (c > j) ? x : ((c == j) ? sm.beta[j] : 0.0);
+      if (j < R && c < R) gR0[j + R * c] = sg * rr;
+      const double v1 = (j > c) ? x * sc_c : ((j == c) ? 1.0 : 0.0);
+      u.v1[j][c] = (j < R && c < R) ? v1 : 0.0;
+      if (c == 0) sm.sgn[j] = sg;
+    }
+    static_for<0, SC::L(q)>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p = decltype(pc)::value;
+      const int s = lane + 64 * p;
+      const double v = (s > c) ? a[SC::OFF(q) + p] * sc_c : ((s == c) ? 1.0 : 0.0);
+      if (s < M && c < R) gV[smap[s].x + (int64_t)M * c] = v;
+    });
+  });
+  gdouble* __restrict__ meta = (gdouble*)args.meta;
+  if (wave == 0 && lane < R) meta[R * R + R + lane] = (double)smap[lane].x;
+  __syncthreads();
+  if (tid < R) meta[R * R + tid] = sm.sgn[tid];
+  // Md = T V1^T D: Md[m][c] = sgn_c sum_k T[m][k] V1[c][k]
+  for (int e = tid; e < R * R; e += NT) {
+    const int m = e % R, c = e / R;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < RMAX; ++k) acc = fma(sm.T[m][k], u.v1[c][k], acc);
+    meta[e] = acc * sm.sgn[c];
+  }
+}
+
+// Staircase order of the rows of Z_n (the row order of zqr_stair): entry s
+// holds the Kolda row of staircase position s and its K digits, 5 bits each
+// (digit k = index into the k-th remaining mode).
+void stair_table(int R, int K, int64_t M, int* out) {
+  for (int64_t s = 0; s < M; ++s) {
+    auto ipw = [](int64_t b, int e) { int64_t p = 1; for (int k = 0; k < e; ++k) p *= b; return p; };
+    int m = 0;
+    while (ipw(m + 1, K) <= s) ++m;
+    int64_t o = s - ipw(m, K);
+    int h = K - 1;
+    int64_t lo = 1;
+    for (; h >= 0; --h) {
+      lo = ipw(m + 1, h);
+      const int64_t cnt = lo * ipw(m, K - 1 - h);
+      if (o < cnt) break;
+      o -= cnt;
+    }
+    int64_t l = o % lo, up = o / lo;
+    int64_t kr = 0, w = 1;
+    int packed = 0;
+    for (int k = 0; k < K; ++k) {
+      int dk;
+      if (k < h) { dk = (int)(l % (m + 1)); l /= (m + 1); }
+      else if (k == h) dk = m;
+      else { dk = (int)(up % m); up /= m; }
+      kr += dk * w;
+      w *= R;
+      packed |= dk << (5 * k);
+    }
+    out[2 * s] = (int)kr;
+    out[2 * s + 1] = packed;
+  }
+}
+
+ZcolPlan zcol_plan(int N, int R) {
+  ZcolPlan pl{};
+  const int rm = qr_rmax(R);
+  const int K = N - 1;
+  if (rm == 0 || (K != 2 && K != 3)) return pl;
+  int64_t M = 1;
+  for (int k = 0; k < K; ++k) M *= R;
+  if (M > 1024 || (K == 3 && rm == 32)) return pl;
+  pl.ok = true;
+  pl.rmax = rm;
+  pl.k = K;
+  pl.rpl = M <= 64 ? 1 : (M <= 128 ? 2 : (M <= 256 ? 4 : (M <= 512 ? 8 : 16)));
+  pl.nw = pl.rpl <= 4 ? 4 : 8;
+  // each wave needs at least one column of every rank class
+  if (pl.rmax / pl.nw < 1) pl.nw = pl.rmax;
+  return pl;
+}
+
+static hipError_t zcol_launch(const ZcolPlan& pl, unsigned blocks, const ZcolArgs& a, const ZcolArgs* batch,
+                              hipStream_t st) {
+#define CPQR_ZC(RM, RP, NWV, KV) \
+  hipLaunchKernelGGL((zqr_col<RM, RP, NWV, KV>), dim3(blocks), dim3(64 * NWV), 0, st, a, batch)
+#define CPQR_ZC_RPL(RM, KV)                                                  \
+  if (pl.rpl == 1) CPQR_ZC(RM, 1, (RM < 4 ? RM : 4), KV);                    \
+  else if (pl.rpl == 2) CPQR_ZC(RM, 2, (RM < 4 ? RM : 4), KV);               \
+  else if (pl.rpl == 4) CPQR_ZC(RM, 4, (RM < 4 ? RM : 4), KV);               \
+  else if (pl.rpl == 8) CPQR_ZC(RM, 8, 8, KV);                               \
+  else if (pl.rpl == 16) CPQR_ZC(RM, 16, 8, KV);                             \
+  else return hipErrorInvalidValue;
+  if (!pl.ok) return hipErrorInvalidValue;
+  if (pl.k == 2) {
+    if (pl.rmax == 8) { CPQR_ZC_RPL(8, 2) }
+    else if (pl.rmax == 16) { CPQR_ZC_RPL(16, 2) }
+    else if (pl.rmax == 32) { CPQR_ZC_RPL(32, 2) }
+    else return hipErrorInvalidValue;
+  } else if (pl.k == 3) {
+    if (pl.rmax == 8) { CPQR_ZC_RPL(8, 3) }
+    else if (pl.rmax == 16) { CPQR_ZC_RPL(16, 3) }
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef CPQR_ZC_RPL
+#undef CPQR_ZC
+  return hipGetLastError();
+}
+
+hipError_t launch_zqr_col(const ZcolPlan& pl, const ZcolArgs& a, hipStream_t st) {
+  if (!pl.ok || a.M > 64 * pl.rpl || a.R > pl.rmax) return hipErrorInvalidValue;
+  return zcol_launch(pl, 1, a, nullptr, st);
+}
+
+hipError_t launch_zqr_col_batched(const ZcolPlan& pl, int count, const ZcolArgs* args, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  return zcol_launch(pl, (unsigned)count, ZcolArgs{}, args, st);
 }
 
 // ------------------------------------------------------------- factor QR

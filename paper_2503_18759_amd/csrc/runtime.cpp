@@ -162,6 +162,8 @@ struct Problem {
   int P = 0;              // TSQR leaves
   int64_t leaf_rows = 0;
   StairPlan stair{};      // staircase Z_n QR (ok == false: dense TSQR)
+  ZcolPlan zcol{};        // column-distributed staircase Z_n QR, compact Q0 (preferred)
+  int* smap = nullptr;    // staircase row table of zqr_col (M x 2 ints)
   std::map<uint32_t, int> ttm_ks;    // TTM step (src | mode << 16) -> K split (0: default)
   int nchunks_max = 0;
   int Imax = 0;
@@ -170,7 +172,8 @@ struct Problem {
   std::vector<void*> Q;        // explicit Q_n in the TTM precision
   double* rf = nullptr;        // N x R x R R factors
   double* lambda = nullptr;
-  std::vector<double*> q0buf;  // per mode: 2 x M x R (ping-pong)
+  std::vector<double*> q0buf;  // per mode: 2 x M x R (ping-pong): Q0, or V of the compact Q0
+  std::vector<double*> q0meta; // per mode: 2 x (R^2 + 2R): [Md, D, piv] of the compact Q0
   double *tV = nullptr, *tT = nullptr, *tStack = nullptr, *tQtop = nullptr, *R0 = nullptr;
   // factor TSQR of modes with more than CPQR_MAX_FACTOR_ROWS rows (sized for
   // the largest such mode; fQ holds Q_n in float64 for the float32 chain)
@@ -256,6 +259,20 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   p.leaf_rows = pl.leaf_rows;
   p.P = pl.P;
   for (int k = 0; k < N; ++k) WS(h, p.prefix + "q0_" + std::to_string(k), (size_t)2 * p.M * R * 8, p.q0buf[k]);
+  p.q0meta.assign(N, nullptr);
+  if (p.zcol.ok) {
+    // staircase row table, and the reflector buffers cleared once: zqr_col
+    // writes only the rows of each column's live chunks, the rest stay zero
+    std::vector<int> tab((size_t)2 * p.M);
+    stair_table(R, N - 1, p.M, tab.data());
+    WS(h, p.prefix + "smap", tab.size() * sizeof(int), p.smap);
+    HIP_TRY(h, hipMemcpy(p.smap, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (int k = 0; k < N; ++k) {
+      WS(h, p.prefix + "q0meta_" + std::to_string(k), (size_t)2 * (R * R + 2 * R) * 8, p.q0meta[k]);
+      HIP_TRY(h, hipMemsetAsync(p.q0buf[k], 0, (size_t)2 * p.M * R * 8, h->stream));
+      HIP_TRY(h, hipMemsetAsync(p.q0meta[k], 0, (size_t)2 * (R * R + 2 * R) * 8, h->stream));
+    }
+  }
   WS(h, p.prefix + "tsqrV", (size_t)p.P * p.leaf_rows * R * 8, p.tV);
   WS(h, p.prefix + "tsqrT", (size_t)p.P * R * R * 8, p.tT);
   WS(h, p.prefix + "tsqrS", (size_t)p.P * R * R * 8, p.tStack);
@@ -293,6 +310,7 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
     p.carried.push_back({p.A[k], (size_t)p.dims[k] * R * 8});
     p.carried.push_back({p.Q[k], (size_t)p.dims[k] * R * p.elem});
     p.carried.push_back({p.q0buf[k], (size_t)2 * p.M * R * 8});
+    if (p.q0meta[k]) p.carried.push_back({p.q0meta[k], (size_t)2 * (R * R + 2 * R) * 8});
   }
   p.carried.push_back({p.rf, (size_t)N * R * R * 8});
   p.carried.push_back({p.lambda, (size_t)R * 8});
@@ -433,6 +451,11 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   a->V = p.Vbuf;
   a->nchunks = apply_num_chunks(p.M, a->I);
   a->state = p.state;
+  if (p.zcol.ok) {
+    const size_t mw = (size_t)R * R + 2 * R;
+    a->meta_p = p.q0meta[n] + (size_t)(sweep_k % 2) * mw;
+    a->meta_q = a->Q0prev ? p.q0meta[n] + (size_t)((sweep_k - 1) % 2) * mw : nullptr;
+  }
   f->I = (int)p.dims[n];
   f->R = R;
   f->V = p.Vbuf;
@@ -488,6 +511,16 @@ StairArgs stair_args(const TsqrArgs& t) {
   return StairArgs{t.N, t.n, t.R, t.M, t.rf, t.R0, t.Q0, 1};
 }
 
+// The Z QR of a mode update on the path its problem takes: the
+// column-distributed staircase kernel (compact Q0), the one-workgroup
+// staircase kernel, or the two-level TSQR.
+hipError_t launch_zqr_any(const Problem& p, const TsqrArgs& t, const ApplyArgs& a, hipStream_t s) {
+  if (p.zcol.ok)
+    return launch_zqr_col(p.zcol, ZcolArgs{t.N, t.n, t.R, t.M, t.rf, p.smap, t.R0, t.Q0,
+                                           const_cast<double*>(a.meta_p), 1}, s);
+  return p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
+}
+
 // The QR Z_n = Q0 R0 of a mode update.  It reads only the R factors, so it
 // may run beside the TTMs that produce the same update's Y_(n).
 hipError_t launch_zqr(const Problem& p, int n, int sweep_k, bool last, const cpqr_options* o, hipStream_t s) {
@@ -495,7 +528,7 @@ hipError_t launch_zqr(const Problem& p, int n, int sweep_k, bool last, const cpq
   ApplyArgs a;
   FinishArgs f;
   update_args(p, n, sweep_k, last, o, &t, &a, &f);
-  return p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
+  return launch_zqr_any(p, t, a, s);
 }
 
 // One mode update; with zqr_done the Z QR has been enqueued already (on a
@@ -518,7 +551,7 @@ hipError_t launch_update(const Problem& p, int n, int sweep_k, bool last, const 
   auto at = [&](int phase) { return mark ? (*mark)(phase) : hipSuccess; };
   if (!zqr_done) {
     if ((e = at(PH_OTHER)) != hipSuccess) return e;
-    e = p.stair.ok ? launch_zqr_stair(p.stair, stair_args(t), s) : launch_tsqr(t, s);
+    e = launch_zqr_any(p, t, a, s);
     if (e != hipSuccess) return e;
     if ((e = at(PH_Q0)) != hipSuccess) return e;
   }
@@ -775,7 +808,7 @@ namespace {
 // Creates the device state of one decomposition (workspace names prefixed by
 // `prefix`), computes ||X||^2 and the QRs of the initial factors.
 cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpqr_options* o,
-                                const std::string& prefix, cpqr_session** out) {
+                                const std::string& prefix, cpqr_session** out, bool batched = false) {
   *out = nullptr;
   {
     cpqr_status v = check_args(h, X, rank, o);
@@ -803,7 +836,12 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   p.X = X->data;
   p.f64 = (o->prec == CPQR_PREC_FP64);
   p.elem = p.f64 ? 8 : 4;
-  if (!(o->flags & CPQR_FLAG_DENSE_ZQR)) p.stair = stair_plan(N, rank);
+  if (!(o->flags & CPQR_FLAG_DENSE_ZQR)) {
+    p.stair = stair_plan(N, rank);
+    // the batched driver groups its Z QRs by the one-workgroup staircase
+    // kernel's shapes
+    if (!batched) p.zcol = zcol_plan(N, rank);
+  }
   cpqr_status stt = setup(h, p, o->iters, S.sched);
   if (stt != CPQR_OK) return stt;
   S.nelem = 1;
@@ -1665,7 +1703,7 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
   struct Unbusy { cpqr_handle* h; ~Unbusy() { h->busy = false; } } unbusy{h};
   for (int t = 0; t < count; ++t) {
     cpqr_session* S = nullptr;
-    cpqr_status st = session_create_impl(h, &Xs[t], ranks[t], &opts[t], "b" + std::to_string(t) + ":", &S);
+    cpqr_status st = session_create_impl(h, &Xs[t], ranks[t], &opts[t], "b" + std::to_string(t) + ":", &S, true);
     if (st != CPQR_OK) {
       const std::string m = h->err;
       return fail(h, st, "batched problem %d: %s", t, m.c_str());

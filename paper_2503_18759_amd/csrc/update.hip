@@ -12,9 +12,9 @@
 //    fit, back substitution of Ahat R0^T = Vu, lambda = column norms,
 //    A = Ahat / lambda, Householder QR of A -> Q_n, R_n; after the last update
 //    of a sweep the fit and the extrapolation activation rule.
-//    finish_update_h does the same for rank class 32 and up to 256 rows with
-//    each row split over the two halves of a wave, and leaves the explicit
-//    Q_n to form_qn_h.
+//    finish_col does the same for factors of at most 256 rows with the
+//    factor QR in the column-distributed layout (colqr_device.h), and leaves
+//    the explicit Q_n to form_qn.
 //  * finish_tall / tall_factor_tail: the same update for modes beyond the
 //    single-workgroup factor QR (the factor QR then goes through the TSQR).
 //  * sumsq / residual: ||X||^2 and ||X - K||^2 with float64 accumulation.
@@ -54,10 +54,25 @@ __global__ __launch_bounds__(AP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 2
   const gdouble* __restrict__ Q0prev = (const gdouble*)a.Q0prev;
   gdouble* __restrict__ partial = (gdouble*)a.partial;
   if ((int)blockIdx.x * AP_ROWS >= I || (int)blockIdx.y >= a.nchunks) return;
-  // rows padded by two so that each thread's pair of rows is one 16-byte read
-  __shared__ __attribute__((aligned(16))) double sY[AP_KT][AP_ROWS + 2];
-  __shared__ __attribute__((aligned(16))) double sQ[AP_KT][RMAX];
-  __shared__ __attribute__((aligned(16))) double sP[AP_KT][RMAX];
+  // k loop: Y tile (rows padded by two so that each thread's pair of rows is
+  // one 16-byte read) and the Q0 / Q0prev tiles; epilogue (compact Q0): the
+  // chunk's products and the two Md
+  __shared__ union __attribute__((aligned(16))) ApLds {
+    struct {
+      double y[AP_KT][AP_ROWS + 2];
+      double q[AP_KT][RMAX];
+      double p[AP_KT][RMAX];
+    } loop;
+    struct {
+      double pp[AP_ROWS][RMAX + 2];
+      double pq[AP_ROWS][RMAX + 2];
+      double mp[RMAX][RMAX];
+      double mq[RMAX][RMAX];
+    } epi;
+  } lds;
+  auto& sY = lds.loop.y;
+  auto& sQ = lds.loop.q;
+  auto& sP = lds.loop.p;
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * AP_ROWS;
   const int64_t M = L * S;
@@ -166,6 +181,51 @@ __global__ __launch_bounds__(AP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 2
     }
     __syncthreads();
   }
+  if (a.meta_p != nullptr) {
+    // compact Q0 = (E - V T V1^T) D: this chunk's share of Y_(n) Q0 is
+    // -(Y_(n) V)_chunk Md (the E D term is added once, in apply_reduce)
+    const gdouble* __restrict__ mp = (const gdouble*)a.meta_p;
+    const gdouble* __restrict__ mq = (const gdouble*)a.meta_q;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int m = 0; m < CW; ++m) {
+        lds.epi.pp[2 * ti + r][cg * CW + m] = ap[r][m];
+        lds.epi.pq[2 * ti + r][cg * CW + m] = aq[r][m];
+      }
+    for (int e = tid; e < RMAX * RMAX; e += AP_THREADS) {
+      const int i = e % RMAX, c = e / RMAX;
+      const bool in = i < R && c < R;
+      const double x = mp[in ? i + R * c : 0];
+      const double y = (mq != nullptr) ? mq[in ? i + R * c : 0] : 0.0;
+      lds.epi.mp[i][c] = in ? x : 0.0;
+      lds.epi.mq[i][c] = in ? y : 0.0;
+    }
+    __syncthreads();
+    double bp[2][CW], bq[2][CW];
+#pragma unroll
+    for (int m = 0; m < CW; ++m) bp[0][m] = bp[1][m] = bq[0][m] = bq[1][m] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < RMAX; ++k) {
+      const double p0 = lds.epi.pp[2 * ti][k], p1 = lds.epi.pp[2 * ti + 1][k];
+      const double q0 = lds.epi.pq[2 * ti][k], q1 = lds.epi.pq[2 * ti + 1][k];
+#pragma unroll
+      for (int m = 0; m < CW; ++m) {
+        const double x = lds.epi.mp[k][cg * CW + m], y = lds.epi.mq[k][cg * CW + m];
+        bp[0][m] = fma(p0, x, bp[0][m]);
+        bp[1][m] = fma(p1, x, bp[1][m]);
+        bq[0][m] = fma(q0, y, bq[0][m]);
+        bq[1][m] = fma(q1, y, bq[1][m]);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < CW; ++m) {
+      ap[0][m] = -bp[0][m];
+      ap[1][m] = -bp[1][m];
+      aq[0][m] = -bq[0][m];
+      aq[1][m] = -bq[1][m];
+    }
+  }
   gdouble* out = partial + (int64_t)blockIdx.y * 2 * I * R;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
@@ -216,6 +276,19 @@ __global__ __launch_bounds__(64 * AR_WAVES) void apply_reduce(ApplyDev a0, const
       double t = sp[0][lane];
 #pragma unroll
       for (int q = 1; q < AR_WAVES; ++q) t += sp[q][lane];
+      // compact Q0: add the E D term, D_c Y_(n)[i, piv_c]
+      const int h = (int)(o / ((int64_t)a.I * a.R));
+      const gdouble* __restrict__ meta = (const gdouble*)(h ? a.meta_q : a.meta_p);
+      if (meta != nullptr) {
+        const int64_t rem = o - (int64_t)h * a.I * a.R;
+        const int i = (int)(rem % a.I), c = (int)(rem / a.I);
+        const int R = a.R;
+        const int64_t k = (int64_t)meta[R * R + R + c];
+        const int64_t l = k % a.L, sidx = k / a.L;
+        const int64_t yi = l + a.L * (int64_t)i + a.L * (int64_t)a.I * sidx;
+        const double y = a.y_f64 ? (double)((const gdouble*)a.Y)[yi] : (double)((const gfloat*)a.Y)[yi];
+        t += meta[R * R + c] * y;
+      }
       V[o] = t;
     }
     __syncthreads();
@@ -238,7 +311,8 @@ ApplyDev apply_dev(const ApplyArgs& a) {
   const int64_t M = a.L * a.S;
   int64_t chunk = (M + a.nchunks - 1) / a.nchunks;
   chunk = ((chunk + AP_KT - 1) / AP_KT) * AP_KT;
-  return ApplyDev{a.Y, a.L, a.S, chunk, a.I, a.R, a.nchunks, a.Q0, a.Q0prev, a.partial, a.V, a.state};
+  return ApplyDev{a.Y, a.L, a.S, chunk, a.I, a.R, a.nchunks, a.Q0, a.Q0prev, a.partial, a.V, a.state,
+                  a.meta_p, a.meta_q, a.y_f64 ? 1 : 0};
 }
 
 static hipError_t apply_launch(int rm, bool y_f64, dim3 grid, dim3 rgrid, const ApplyDev& a,
@@ -467,313 +541,6 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
     // rows of R_n (c >= I) are zero by construction
     if (rank_deficient(R < I ? R : I, [&](int c) { return wy.Rm[c][c]; })) bad |= FLAG_RANKDEF;
     finish_state_tail(f, st, sc, bad);
-  }
-}
-
-// ------------------------------------------------------- half-row layout
-// finish_update for 32-column factors of at most 256 rows with 512 threads:
-// thread (wave w, lane l) holds columns 16 h .. 16 h + 15 (h = l >= 32) of
-// row 32 w + (l mod 32), so the two halves of a row sit in lanes l and l + 32
-// of one wave.  A Householder column step then updates 16 columns per lane,
-// reduces 16 values over the 32 lanes of a half-wave, and passes the next
-// column's entry between the halves with one cross-half swap; two waves per
-// SIMD hide each other's latencies.  The arithmetic per entry is that of
-// finish_update (same reflector convention, same T, WY product and explicit
-// Q); the back substitution runs row by row through LDS.
-static constexpr int FH_NT = 512;
-static constexpr int FH_NW = FH_NT / 64;
-
-// Transposed reduction of 16 doubles over each 32-lane half of the wave: on
-// exit a[0] of lane l holds the sum over the lane's half of value index
-// (l mod 32) >> 1.
-__device__ __forceinline__ void half_transpose_reduce16(double (&a)[16]) {
-  const int lane = threadIdx.x & 63;
-  static_for<0, 8>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    swap16_add(a[q], a[q + 8]);
-  });
-  static_for<0, 4>([&](auto bc) {
-    constexpr int bit = 3 - decltype(bc)::value;
-    constexpr int m = 1 << bit;
-    constexpr int ctrl = (bit == 3) ? 0x140 : (bit == 2) ? 0x141 : (bit == 1) ? 0x4E : 0xB1;
-    constexpr int half = 8 >> (4 - bit);
-    if constexpr (half >= 1) {
-      const bool upper = (lane & m) != 0;
-      static_for<0, half>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        const double keep = upper ? a[q + half] : a[q];
-        const double send = upper ? a[q] : a[q + half];
-        a[q] = keep + dpp_d<ctrl>(send);
-      });
-    } else {
-      a[0] += dpp_d<ctrl>(a[0]);
-    }
-  });
-}
-
-// The value of `v` in the partner lane of the other half (l xor 32).
-__device__ __forceinline__ double other_half(double v) { return shfl_xor_d(v, 32); }
-
-__global__ __launch_bounds__(FH_NT) void finish_update_h(FinishArgs f) {
-  constexpr int RMAX = 32, HW = 16;
-  __shared__ QrSmem<RMAX> sm;            // piv, tau, beta, scale, U, T, sgn
-  __shared__ QrWySmem<RMAX> wy;
-  __shared__ double sR0[RMAX][RMAX + 1];
-  __shared__ double hred[2][FH_NW][RMAX];
-  __shared__ double hw[FH_NW][RMAX];
-  __shared__ double sA[256][RMAX + 1];   // rows between the two layouts
-  __shared__ double sred2[FH_NW][2];
-  __shared__ double slam[RMAX], sinv[RMAX];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int h = lane >> 5, r = 32 * wave + (lane & 31), c0 = HW * h;
-  const int I = f.I, R = f.R;
-  DevState* st = f.state;
-  const gdouble* __restrict__ gV = (const gdouble*)f.V;
-  gdouble* __restrict__ gA = (gdouble*)f.A;
-  gdouble* __restrict__ gq64 = (gdouble*)f.q64;
-  gfloat* __restrict__ gq32 = (gfloat*)f.q32;
-  for (int e = tid; e < RMAX * RMAX; e += FH_NT) {
-    const int i = e / RMAX, c = e % RMAX;
-    sR0[i][c] = (i < R && c < R) ? ((const gdouble*)f.R0)[i + R * c] : 0.0;
-  }
-  const bool active = (f.extrap != 0) && st->active;
-  const double beta = active ? st->beta : 0.0;
-  const double cp = 1.0 + beta, cq = -f.alpha * beta;
-  // Vu = (1 + beta) Vp - alpha beta Vq for this half row, <Vp,Vu>, ||Vu||^2
-  double sc[2] = {0.0, 0.0};
-  {
-    double lp[HW], lq[HW];
-#pragma unroll
-    for (int u = 0; u < HW; ++u) {
-      const int c = c0 + u;
-      const int64_t e = (r < I && c < R) ? r + (int64_t)I * c : 0;
-      lp[u] = gV[e];
-      lq[u] = gV[(int64_t)I * R + e];
-    }
-#pragma unroll
-    for (int u = 0; u < HW; ++u) {
-      const int c = c0 + u;
-      const bool in = r < I && c < R;
-      const double vp = in ? lp[u] : 0.0, vq = in ? lq[u] : 0.0;
-      const double vu = active ? fma(cq, vq, cp * vp) : vp;
-      sc[0] = fma(vp, vu, sc[0]);
-      sc[1] = fma(vu, vu, sc[1]);
-      sA[r][c] = vu;
-    }
-  }
-  block_allreduce<2, FH_NW>(sc, sred2);   // its barriers also publish sR0 and sA
-  int bad = 0;
-  if (rank_deficient(R, [&](int c) { return sR0[c][c]; })) bad |= FLAG_RANKDEF;
-  // back substitution of R0 ahat = vu, one row per thread of the first four
-  // waves, in place in sA
-  if (tid < 256) {
-    double x[RMAX];
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) x[c] = sA[tid][c];
-    static_for<0, RMAX>([&](auto ic) {
-      constexpr int c = RMAX - 1 - decltype(ic)::value;
-      double s = x[c];
-      static_for<c + 1, RMAX>([&](auto dc) {
-        constexpr int d = decltype(dc)::value;
-        s = fma(-sR0[c][d], x[d], s);
-      });
-      x[c] = (c < R && tid < I && sR0[c][c] != 0.0) ? s / sR0[c][c] : 0.0;
-      __builtin_amdgcn_sched_barrier(0);
-    });
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) sA[tid][c] = x[c];
-  }
-  __syncthreads();
-  // lambda = column norms of Ahat; A = Ahat / lambda
-  // the half row in one register vector (a variable index into it is an
-  // indexed register move; into a plain array it would go to scratch)
-  f64x16 a;
-#pragma unroll
-  for (int u = 0; u < HW; ++u) a[u] = sA[r][c0 + u];
-  {
-    double cn[HW];
-#pragma unroll
-    for (int u = 0; u < HW; ++u) cn[u] = a[u] * a[u];
-    half_transpose_reduce16(cn);
-    if ((lane & 1) == 0) hred[0][wave][c0 + ((lane & 31) >> 1)] = cn[0];
-  }
-  __syncthreads();
-  if (tid < RMAX) {
-    double tot = 0.0;
-#pragma unroll
-    for (int w = 0; w < FH_NW; ++w) tot += hred[0][w][tid];
-    const double lam = sqrt(tot);
-    slam[tid] = lam;
-    sinv[tid] = (tid < R && lam != 0.0) ? 1.0 / lam : 0.0;
-    if (tid < R) ((gdouble*)f.lambda)[tid] = lam;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    if (rank_deficient(R, [&](int c) { return slam[c]; })) bad |= FLAG_RANKDEF;
-    for (int c = 0; c < R; ++c)
-      if (!isfinite(slam[c])) bad |= FLAG_NONFINITE;
-  }
-#pragma unroll
-  for (int u = 0; u < HW; ++u) {
-    const int c = c0 + u;
-    a[u] = a[u] * sinv[c];
-    if (r < I && c < R) gA[r + (int64_t)I * c] = a[u];
-  }
-  // Householder QR of A (rows beyond I are zero)
-  {
-    // column 0 lives in half 0.  The cross-lane read runs on every lane
-    // before the select: inside a branch only the reading half would be
-    // active, and a read from an inactive lane returns zero.
-    const double own0 = a[0];
-    const double oth0 = other_half(own0);
-    const double x0v = (h == 0) ? own0 : oth0;
-    double x = (r > 0) ? x0v : 0.0;
-    double part[HW];
-#pragma unroll
-    for (int u = 0; u < HW; ++u) part[u] = x * a[u];
-    if (r == 0) {
-#pragma unroll
-      for (int u = 0; u < HW; ++u) sm.piv[0][c0 + u] = a[u];
-    }
-    // (x of half 1 is its partner's column-0 entry, so every lane of a row
-    // holds the same x)
-    for (int j = 0; j < R; ++j) {
-      const int buf = j & 1;
-      half_transpose_reduce16(part);
-      if ((lane & 1) == 0) hred[buf][wave][c0 + ((lane & 31) >> 1)] = part[0];
-      __syncthreads();
-      double tot = 0.0, pc = 0.0, scl = 0.0;
-      const double xp = sm.piv[buf][j];
-      if (lane < RMAX) {
-        double rv[FH_NW];
-#pragma unroll
-        for (int w = 0; w < FH_NW; ++w) rv[w] = hred[buf][w][lane];
-        pc = sm.piv[buf][lane];
-        scl = sm.scale[lane];
-#pragma unroll
-        for (int w = 0; w < FH_NW; ++w) tot += rv[w];
-      }
-      const double stv = lane_read(tot, j);
-      double tau, bet, scale;
-      qr_reflector_scalars(xp, stv, &tau, &bet, &scale);
-      if (lane < RMAX) {
-        const double wu = fma(scale, tot, pc);
-        hw[wave][lane] = (lane > j) ? wu : 0.0;
-        if (wave == 0) sm.U[lane][j] = (lane < j) ? wu * scl : 0.0;
-      }
-      if (wave == 0 && lane == 0) {
-        sm.tau[j] = tau;
-        sm.beta[j] = bet;
-        sm.scale[j] = scale;
-      }
-      // this wave's own copy of w, read back in order (one wave's LDS
-      // operations complete in order)
-      double wv[HW];
-#pragma unroll
-      for (int u = 0; u < HW; ++u) wv[u] = hw[wave][c0 + u];
-      const int jn = j + 1;
-      const double coef = (r > j) ? tau * x * scale : ((r == j) ? tau : 0.0);
-      const int jc = jn < RMAX ? jn : 0;
-      const double wn = hw[wave][jc];
-      // the next column's entry of this row, updated, from the half that
-      // holds it
-      const double cand = fma(-coef, wn, a[jc & (HW - 1)]);
-      const double oth = other_half(cand);
-      const double an = (jn < RMAX) ? (((jc >> 4) == h) ? cand : oth) : 0.0;
-      const double xn = (r > jn) ? an : 0.0;
-#pragma unroll
-      for (int u = 0; u < HW; ++u) {
-        const double v = fma(-coef, wv[u], a[u]);
-        a[u] = v;
-        part[u] = xn * v;
-      }
-      x = xn;
-      if (r == jn && jn < R) {
-#pragma unroll
-        for (int u = 0; u < HW; ++u) sm.piv[buf ^ 1][c0 + u] = a[u];
-      }
-    }
-  }
-  __syncthreads();
-  block_qr_build_t<RMAX>(R, sm);
-  // publish V1 and R (rows 0..31: wave 0) with the sign fix
-  if (wave == 0) {
-    const int row = lane & 31;
-    const double sg = (row < R && sm.beta[row] < 0.0) ? -1.0 : 1.0;
-    if (h == 0) sm.sgn[row] = sg;
-#pragma unroll
-    for (int u = 0; u < HW; ++u) {
-      const int c = c0 + u;
-      const bool in = (row < R) && (c < R);
-      const double v = (row > c) ? a[u] * sm.scale[c] : ((row == c) ? 1.0 : 0.0);
-      const double rr = (c > row) ? a[u] : ((c == row) ? sm.beta[row] : 0.0);
-      wy.V1[row][c] = in ? v : 0.0;
-      wy.Rm[row][c] = in ? sg * rr : 0.0;
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < R * R; e += FH_NT) {
-    const int i = e % R, c = e / R;
-    ((gdouble*)f.Rn)[e] = wy.Rm[i][c];
-  }
-  // hand the reflectors to form_qn_h: rows r < I of V (I x R, column-major),
-  // the published V1 and T (RMAX x RMAX, row-major) and the signs
-  {
-    gdouble* __restrict__ qv = (gdouble*)f.qn;
-    gdouble* __restrict__ qv1 = qv + 256 * RMAX;
-    gdouble* __restrict__ qt = qv1 + RMAX * RMAX;
-    gdouble* __restrict__ qs = qt + RMAX * RMAX;
-#pragma unroll
-    for (int u = 0; u < HW; ++u) {
-      const int c = c0 + u;
-      const double v = (c < R) ? ((r > c) ? a[u] * sm.scale[c] : ((r == c) ? 1.0 : 0.0)) : 0.0;
-      if (r < I && c < R) qv[r + (int64_t)I * c] = v;
-    }
-    for (int e = tid; e < RMAX * RMAX; e += FH_NT) {
-      const int k = e / RMAX, c = e % RMAX;
-      qv1[e] = wy.V1[k][c];
-      qt[e] = sm.T[k][c];
-    }
-    if (tid < RMAX) qs[tid] = sm.sgn[tid];
-  }
-  if (tid == 0) {
-    if (rank_deficient(R < I ? R : I, [&](int c) { return wy.Rm[c][c]; })) bad |= FLAG_RANKDEF;
-    finish_state_tail(f, st, sc, bad);
-  }
-}
-
-// Explicit Q_n = (E - V M) diag(sgn), M = T V1^T, of the half-row factor QR
-// from what finish_update_h leaves in f.qn: the same WY product and the same
-// row arithmetic (wy_q_row) as the single-kernel path, one row per thread.
-__global__ __launch_bounds__(256) void form_qn_h(FinishArgs f) {
-  constexpr int RMAX = 32;
-  __shared__ QrSmem<RMAX> sm;
-  __shared__ QrWySmem<RMAX> wy;
-  const int tid = threadIdx.x;
-  const int I = f.I, R = f.R;
-  const gdouble* __restrict__ qv = (const gdouble*)f.qn;
-  const gdouble* __restrict__ qv1 = qv + 256 * RMAX;
-  const gdouble* __restrict__ qt = qv1 + RMAX * RMAX;
-  const gdouble* __restrict__ qs = qt + RMAX * RMAX;
-  gdouble* __restrict__ gq64 = (gdouble*)f.q64;
-  gfloat* __restrict__ gq32 = (gfloat*)f.q32;
-  for (int e = tid; e < RMAX * RMAX; e += 256) {
-    const int k = e / RMAX, c = e % RMAX;
-    wy.V1[k][c] = qv1[e];
-    sm.T[k][c] = qt[e];
-  }
-  if (tid < RMAX) sm.sgn[tid] = qs[tid];
-  __syncthreads();
-  block_qr_wy_product<RMAX, 256>(sm, wy, R, nullptr, 0);
-  const int r = tid;
-  if (r < I) {
-    double v[RMAX];
-#pragma unroll
-    for (int m = 0; m < RMAX; ++m) v[m] = (m < R) ? qv[r + (int64_t)I * (m < R ? m : 0)] : 0.0;
-    wy_q_row<RMAX, RMAX, 0>(v, r, R, sm, wy, [&](int c, double val) {
-      if (gq64) gq64[r + (int64_t)I * c] = val;
-      if (gq32) gq32[r + (int64_t)I * c] = (float)val;
-    });
   }
 }
 
