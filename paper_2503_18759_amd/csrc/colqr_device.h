@@ -65,7 +65,8 @@ __device__ __forceinline__ void col_publish(const double (&a)[RPL][(ColCfg<RMAX,
 // column j (wave j / CPW) and the local column of j are known when the body
 // is compiled: the owner updates only its columns after j, waves with
 // earlier columns only form the entries of U, and the next column is
-// published from a fixed register.
+// published from a fixed register.  On return tau, beta, scale and U are in
+// LDS; T (block_qr_build_t) is left to the caller.
 template <int RMAX, int RPL, int NW, bool STAIR, typename Prof>
 __device__ __forceinline__ void col_qr(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)], int R, Prof&& prof,
                                        double (*xb)[64 * RPL], QrSmem<RMAX>& sm) {
@@ -184,9 +185,32 @@ __device__ __forceinline__ void col_qr(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)]
     if (m < jc && jc < R) sm.U[m][jc] *= sm.scale[m];
   }
   __syncthreads();
-  block_qr_build_t<RMAX>(R, sm);
 }
 
+
+// T of the compact WY form from U and tau (block_qr_build_t) by the lanes of
+// wave 0 alone, without a workgroup barrier: the caller synchronises before
+// T is read.
+template <int RMAX>
+__device__ __forceinline__ void block_qr_build_t_wave0(int R, QrSmem<RMAX>& sm) {
+  const int k = threadIdx.x;
+  if (k < RMAX) {
+    double t[RMAX];
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+      double u[RMAX];
+#pragma unroll
+      for (int m = 0; m < j; ++m) u[m] = sm.U[m][j];
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m + 1 < j; ++m) acc = fma(t[m], u[m], acc);
+      if (j > 0) acc = fma(t[j - 1], u[j - 1], acc);
+      t[j] = (j < k || j >= R) ? 0.0 : ((j == k) ? sm.tau[j] : -sm.tau[j] * acc);
+    }
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) sm.T[k][j] = t[j];
+  }
+}
 
 // ---------------------------------------------------------------------------
 // The same factorisation for Z_n with its rows in staircase order, where
@@ -196,8 +220,11 @@ __device__ __forceinline__ void col_qr(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)]
 // needs only L(q) of the RPL row chunks in registers: at rank 32 and K = 2
 // that is 1 + 4 + 9 + 16 = 30 chunks for 4 local columns instead of 64.  The
 // owner of column j is wave j mod NW, and it publishes all of its columns
-// (their live chunks) into the broadcast buffer, local column q at offset
-// 64 RPL q; the readers take column j at local column j / NW.
+// (their live chunks) into the broadcast buffer, packed: local column q at
+// row offset 64 OFF(q); the readers take column j at local column j / NW.
+// The column loop is not unrolled (the owner and local column of a step are
+// runtime values), which keeps the kernel within the instruction cache: each
+// step runs one of the bodies compiled per chunk count.
 template <int RMAX, int RPL, int NW, int K>
 struct StairCfg {
   static constexpr int CPW = RMAX / NW;
@@ -218,7 +245,7 @@ struct StairCfg {
 
 template <int RMAX, int RPL, int NW, int K, typename Prof>
 __device__ __forceinline__ void col_qr_stair(double (&a)[(StairCfg<RMAX, RPL, NW, K>::TOT)], int R, Prof&& prof,
-                                             double (*xb)[(StairCfg<RMAX, RPL, NW, K>::CPW) * 64 * RPL],
+                                             double (*xb)[(StairCfg<RMAX, RPL, NW, K>::TOT) * 64],
                                              QrSmem<RMAX>& sm) {
   using SC = StairCfg<RMAX, RPL, NW, K>;
   constexpr int CPW = SC::CPW, MR = SC::MR;
@@ -231,19 +258,22 @@ __device__ __forceinline__ void col_qr_stair(double (&a)[(StairCfg<RMAX, RPL, NW
       constexpr int q = decltype(qc)::value;
       static_for<0, SC::L(q)>([&](auto pc) __attribute__((always_inline)) {
         constexpr int p = decltype(pc)::value;
-        dst[q * MR + lane + 64 * p] = a[SC::OFF(q) + p];
+        dst[64 * (SC::OFF(q) + p) + lane] = a[SC::OFF(q) + p];
       });
     });
   };
   if (wave == 0) publish(xb[0]);
   __syncthreads();
-  for (int jb = 0; jb * NW < R; ++jb) {
-    static_for<0, NW>([&](auto jjc) __attribute__((always_inline)) {
-      constexpr int jj = decltype(jjc)::value;   // owner wave of column j
-      const int j = jb * NW + jj;
-      if (j >= R) return;
+  for (int j = 0; j < R; ++j) {
+    {
+      const int jb = j / NW, jj = j % NW;   // local column and owner wave of column j
       const int buf = j & 1;
-      const double* __restrict__ xj = xb[buf] + jb * MR;
+      int off = 0;   // 64 OFF(jb): chunks of the local columns before jb
+      static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        off += (q < jb) ? SC::L(q) : 0;
+      });
+      const double* __restrict__ xj = xb[buf] + 64 * off;
       const int nch = chunks(j);
       auto step = [&](auto nchc) __attribute__((always_inline)) {
         constexpr int NCH = decltype(nchc)::value;   // active chunks, rounded up
@@ -304,14 +334,13 @@ __device__ __forceinline__ void col_qr_stair(double (&a)[(StairCfg<RMAX, RPL, NW
       // the owner of column j + 1 publishes its columns for the next step
       if (j + 1 < R && wave == (jj + 1) % NW) publish(xb[buf ^ 1]);
       __syncthreads();
-    });
+    }
   }
   for (int e = tid; e < RMAX * RMAX; e += 64 * NW) {
     const int m = e / RMAX, jc = e % RMAX;
     if (m < jc && jc < R) sm.U[m][jc] *= sm.scale[m];
   }
   __syncthreads();
-  block_qr_build_t<RMAX>(R, sm);
 }
 
 }  // namespace cpqr

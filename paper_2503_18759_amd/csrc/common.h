@@ -194,6 +194,16 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// rank_deficient evaluated by one wave: lane c < n passes d(c) in v (other
+// lanes' v is ignored); the same answer on every lane.
+__device__ __forceinline__ bool wave_rank_deficient(int n, double v) {
+  const int lane = threadIdx.x & 63;
+  const double a = (lane < n) ? fabs(v) : 0.0;
+  const double mx = wave_max(a);
+  const bool bad = (lane < n) && !(a > kRankRel * mx);
+  return __ballot(bad) != 0;
+}
+
 // Round-to-nearest-even split of a float into bf16 hi + bf16 lo.
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;

@@ -251,10 +251,10 @@ struct FinishArgs {
   int last_in_sweep;
   const double* beta_sched;  // device, sched_len values or null: beta of sweep k+1 = beta_sched[k]
   int sched_len;
-  double* qn;           // workspace of CPQR_QN_WORDS doubles: reflectors, T and signs
+  double* qn;           // workspace of CPQR_QN_WORDS doubles: reflectors, U, tau and signs
                         // handed from the factor QR to the Q_n kernel (half-row path)
 };
-static constexpr int CPQR_QN_WORDS = 256 * 32 + 2 * 32 * 32 + 32;
+static constexpr int CPQR_QN_WORDS = 256 * 32 + 2 * 32 * 32 + 2 * 32;
 hipError_t launch_finish(const FinishArgs& f, hipStream_t st);
 // launch_finish in two parts: the head (solve, lambda, factor QR, R_n, fit)
 // and, when *tail is set, the explicit Q_n kernel, which only the TTMs of the

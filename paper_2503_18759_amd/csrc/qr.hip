@@ -496,7 +496,7 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
   const int M = (int)args.M;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ QrSmem<RMAX> sm;
-  __shared__ double xb[2][CPW * MR];
+  __shared__ double xb[2][SC::TOT * 64];
   __shared__ union ZcolLds {
     double srf[K * RMAX * RMAX];   // R factors of the other modes (Z build)
     double v1[RMAX][RMAX + 1];     // first R rows of V (epilogue)
@@ -520,12 +520,22 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
   // staircase table, 5 bits each)
   typedef __attribute__((address_space(1))) const int2 gint2;
   const gint2* __restrict__ smap = (const gint2*)args.smap;
-  double a[SC::TOT];
+  int2 tab[RPL];   // Kolda row and digits of this lane's rows (all loads in flight together)
   static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
     constexpr int p = decltype(pc)::value;
     const int s = lane + 64 * p;
-    const bool in = s < M;
-    const int dig = in ? smap[s].y : 0;
+    int2 t = make_int2(-1, 0);
+    if (s < M) {
+      t.x = smap[s].x;
+      t.y = smap[s].y;
+    }
+    tab[p] = t;
+  });
+  double a[SC::TOT];
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    const bool in = tab[p].x >= 0;
+    const int dig = tab[p].y;
     static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
       constexpr int q = decltype(qc)::value;
       if constexpr (p < SC::L(q)) {
@@ -546,8 +556,7 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
     return pw < M ? pw : M;
   };
   col_qr_stair<RMAX, RPL, NW, K>(a, R, prof, xb, sm);
-  // R0 = D R, V rows (Kolda order; rows beyond a column's live chunks are
-  // zero in the buffer from its set-up), V1 into LDS
+  // R0 = D R and V1 into LDS (the first R rows are lanes 0..R-1 of chunk 0)
   gdouble* __restrict__ gR0 = (gdouble*)args.R0;
   gdouble* __restrict__ gV = (gdouble*)args.V;
   static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
@@ -562,26 +571,36 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
       if (j < R && c < R) gR0[j + R * c] = sg * rr;
       const double v1 = (j > c) ? x * sc_c : ((j == c) ? 1.0 : 0.0);
       u.v1[j][c] = (j < R && c < R) ? v1 : 0.0;
-      if (c == 0) sm.sgn[j] = sg;
     }
+  });
+  // wave 0 builds T while the other waves write their rows of V
+  if (wave == 0) block_qr_build_t_wave0<RMAX>(R, sm);
+  // V rows (Kolda order; rows beyond a column's live chunks stay zero in the
+  // buffer from its set-up)
+  static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+    constexpr int q = decltype(qc)::value;
+    const int c = NW * q + wave;
+    const double sc_c = sm.scale[c < R ? c : 0];
     static_for<0, SC::L(q)>([&](auto pc) __attribute__((always_inline)) {
       constexpr int p = decltype(pc)::value;
       const int s = lane + 64 * p;
       const double v = (s > c) ? a[SC::OFF(q) + p] * sc_c : ((s == c) ? 1.0 : 0.0);
-      if (s < M && c < R) gV[smap[s].x + (int64_t)M * c] = v;
+      if (tab[p].x >= 0 && c < R) gV[tab[p].x + (int64_t)M * c] = v;
     });
   });
   gdouble* __restrict__ meta = (gdouble*)args.meta;
-  if (wave == 0 && lane < R) meta[R * R + R + lane] = (double)smap[lane].x;
+  if (tid < R) {
+    meta[R * R + R + tid] = (double)tab[0].x;
+    meta[R * R + tid] = (sm.beta[tid] < 0.0) ? -1.0 : 1.0;
+  }
   __syncthreads();
-  if (tid < R) meta[R * R + tid] = sm.sgn[tid];
   // Md = T V1^T D: Md[m][c] = sgn_c sum_k T[m][k] V1[c][k]
   for (int e = tid; e < R * R; e += NT) {
     const int m = e % R, c = e / R;
     double acc = 0.0;
 #pragma unroll 8
     for (int k = 0; k < RMAX; ++k) acc = fma(sm.T[m][k], u.v1[c][k], acc);
-    meta[e] = acc * sm.sgn[c];
+    meta[e] = acc * ((sm.beta[c] < 0.0) ? -1.0 : 1.0);
   }
 }
 
@@ -631,9 +650,10 @@ ZcolPlan zcol_plan(int N, int R) {
   pl.rmax = rm;
   pl.k = K;
   pl.rpl = M <= 64 ? 1 : (M <= 128 ? 2 : (M <= 256 ? 4 : (M <= 512 ? 8 : 16)));
-  pl.nw = pl.rpl <= 4 ? 4 : 8;
-  // each wave needs at least one column of every rank class
-  if (pl.rmax / pl.nw < 1) pl.nw = pl.rmax;
+  // four waves (one per SIMD) up to 256 rows; eight (two per SIMD, half the
+  // columns each) beyond, where the column steps are bound by instruction
+  // issue
+  pl.nw = pl.rpl >= 8 ? 8 : 4;
   return pl;
 }
 

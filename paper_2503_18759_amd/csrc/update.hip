@@ -552,10 +552,11 @@ __global__ CPQR_QR_KERNEL(RMAX) void finish_update(FinishArgs f0, const FinishAr
 // inside one wave.  The arithmetic per entry is that of finish_update (same
 // Vu, solve, lambda, reflector convention and T) except that the solve
 // multiplies by the reciprocals of R0's diagonal; the reflectors go to
-// form_qn for the explicit Q_n, off the next update's Z QR path.  Layout of
-// f.qn: V rows (I x R column-major) at 0, V1 and T (RMAX x RMAX row-major)
-// at QN_V1 and QN_T, the signs of diag(R) at QN_SGN.
-static constexpr int QN_V1 = 256 * 32, QN_T = QN_V1 + 32 * 32, QN_SGN = QN_T + 32 * 32;
+// form_qn for the explicit Q_n, off the next update's Z QR path, and so does
+// T of the compact WY form.  Layout of f.qn: V rows (I x R column-major) at
+// 0, V1 and U (RMAX x RMAX row-major) at QN_V1 and QN_U, the signs of
+// diag(R) at QN_SGN and tau at QN_TAU.
+static constexpr int QN_V1 = 256 * 32, QN_U = QN_V1 + 32 * 32, QN_SGN = QN_U + 32 * 32, QN_TAU = QN_SGN + 32;
 static constexpr int FC_NW = 4, FC_NT = 64 * FC_NW;
 
 template <int RMAX, int RPL>
@@ -701,16 +702,20 @@ void finish_col(FinishArgs f0, const FinishArgs* __restrict__ batch) {
       if (row < I && c < R) qv[row + (int64_t)I * c] = v;
     });
   });
-  for (int e = tid; e < RMAX * RMAX; e += NT) qv[QN_T + e] = sm.T[e / RMAX][e % RMAX];
-  if (tid == 0) {
+  for (int e = tid; e < RMAX * RMAX; e += NT) qv[QN_U + e] = sm.U[e / RMAX][e % RMAX];
+  if (tid < RMAX) qv[QN_TAU + tid] = (tid < R) ? sm.tau[tid] : 0.0;
+  if (wave == 0) {
+    // rank tests of R0, lambda and R_n (|R_n[c][c]| = |beta_c|; a mode
+    // smaller than the rank has min(I, R) reflectors), one value per lane
+    const bool in = lane < R;
+    const double r0 = in ? sR0[lane][lane] : 0.0, lam = in ? slam[lane] : 0.0;
+    const double bt = in ? sm.beta[lane] : 0.0;
     int bad = 0;
-    if (rank_deficient(R, [&](int c) { return sR0[c][c]; })) bad |= FLAG_RANKDEF;
-    if (rank_deficient(R, [&](int c) { return slam[c]; })) bad |= FLAG_RANKDEF;
-    for (int c = 0; c < R; ++c)
-      if (!isfinite(slam[c])) bad |= FLAG_NONFINITE;
-    // a mode smaller than the rank has min(I, R) reflectors; |R_n[c][c]| = |beta_c|
-    if (rank_deficient(R < I ? R : I, [&](int c) { return sm.beta[c]; })) bad |= FLAG_RANKDEF;
-    finish_state_tail(f, st, sc, bad);
+    if (wave_rank_deficient(R, r0)) bad |= FLAG_RANKDEF;
+    if (wave_rank_deficient(R, lam)) bad |= FLAG_RANKDEF;
+    if (__ballot(in && !isfinite(lam)) != 0) bad |= FLAG_NONFINITE;
+    if (wave_rank_deficient(R < I ? R : I, bt)) bad |= FLAG_RANKDEF;
+    if (lane == 0) finish_state_tail(f, st, sc, bad);
   }
 }
 
@@ -730,10 +735,14 @@ __global__ __launch_bounds__(256) void form_qn(FinishArgs f0, const FinishArgs* 
   for (int e = tid; e < RMAX * RMAX; e += 256) {
     const int k = e / RMAX, c = e % RMAX;
     wy.V1[k][c] = qv[QN_V1 + e];
-    sm.T[k][c] = qv[QN_T + e];
+    sm.U[k][c] = qv[QN_U + e];
   }
-  if (tid < RMAX) sm.sgn[tid] = qv[QN_SGN + tid];
+  if (tid < RMAX) {
+    sm.sgn[tid] = qv[QN_SGN + tid];
+    sm.tau[tid] = qv[QN_TAU + tid];
+  }
   __syncthreads();
+  block_qr_build_t<RMAX>(R, sm);
   block_qr_wy_product<RMAX, 256>(sm, wy, R, nullptr, 0);
   const int r = tid;
   if (r < I) {
