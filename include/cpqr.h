@@ -54,14 +54,22 @@ typedef enum { CPQR_TREE_NONE = 0, CPQR_TREE_STANDARD = 1, CPQR_TREE_RESTRUCTURE
  * switch_delta and picks it from the fit level (Section 4.3).  LEARNED (a
  * feature of this library, not of the paper) takes beta from the MLP in
  * cpqr_options.mlp_weights after sweep 2 and applies it from sweep 3 through
- * the same eq. (19) update; every such sweep is accepted only if its fit
- * exceeds the previous sweep's fit, otherwise the sweep-start state is
- * restored, beta becomes the paper's table value for the previous fit, and
- * the sweep is redone (the MLP is not consulted again). */
+ * the same eq. (19) update.  The state after sweep 2 is the checkpoint, with
+ * its explicit fit 1 - ||X - K|| / ||X|| (float64).  Checks follow after 4
+ * sweeps, then after gaps that double (8, 16, ...), at the last sweep of the
+ * run and at a tolerance stop: the explicit fit, with lambda divided by
+ * 1 + (1 - alpha) beta (the factor by which eq. (19) scales an update at a
+ * fixed point), must exceed the checkpoint's, and the state becomes the new
+ * checkpoint; otherwise the checkpoint is restored (factors, Q0 of its sweep,
+ * the intermediates live across it), beta becomes the paper's table value
+ * for the checkpoint's fit, and the sweeps since the checkpoint run again
+ * with it, with no further checks (the MLP is not consulted again). */
 typedef enum { CPQR_EXTRAP_OFF = 0, CPQR_EXTRAP_PAPER = 1, CPQR_EXTRAP_LEARNED = 2 } cpqr_extrap;
 
 /* Learned-extrapolation MLP: CPQR_MLP_FEATURES inputs -> CPQR_MLP_HIDDEN tanh
- * units -> one linear output y, with beta = clamp(10^y - 1e-6, 0, 0.05).
+ * units -> one linear output y = u, the momentum share u = g beta / (1 + g beta)
+ * with g = 0.9: beta = u / (g (1 - u)) for u clamped to [0, 27/28]
+ * (beta in [0, 30]).
  * Parameters (float32, CPQR_MLP_PARAMS): W1 (HIDDEN x FEATURES, row-major),
  * b1 (HIDDEN), w2 (HIDDEN), b2 (1).  Features after sweep 2 (fits f1, f2 of
  * sweeps 1 and 2, order N, rank R, mode sizes I_n):
@@ -92,6 +100,10 @@ typedef enum { CPQR_DTYPE_F64 = 0, CPQR_DTYPE_F32 = 1 } cpqr_dtype;
 #define CPQR_FLAG_TIME_PHASES  0x10u /* fill cpqr_result.phase_seconds: kernels launch one by one
                                         (no graphs) with HIP events between kernel groups, and the
                                         host waits after every sweep; excludes TIME_KERNELS */
+#define CPQR_FLAG_CLOSING_PLAIN 0x20u /* the last sweep (sweep `iters`) runs without extrapolation
+                                        (beta = 0): at a fixed point eq. (19) scales every update
+                                        by 1 + (1 - alpha) beta, which lambda carries; a plain
+                                        sweep gives the extrapolated factors their own lambda */
 
 typedef struct cpqr_handle cpqr_handle;
 

@@ -64,6 +64,10 @@ F64 = np.float64
 # factor's diagonal, or the set of column norms lambda, is rank-deficient when
 # one entry is at most RANK_REL times the largest (zero included).
 RANK_REL = 1e-13
+# Learned extrapolation (a library feature): sweeps from the start of the
+# learned beta (after sweep 2) to its first acceptance check; the gap doubles
+# after every passed check.
+LEARNED_FIRST_CHECK = 4
 
 
 class RankDeficient(FloatingPointError):
@@ -353,16 +357,27 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
               tree: str = "none", extrap: str = "off", alpha: float = 0.1,
               delta: float = 0.03, tol: float = 0.0, fix_beta: Optional[float] = None,
               explicit_every_sweep: bool = False, explicit_final: bool = True,
-              sweep_callback=None, mlp_weights=None, beta_schedule=None, seed: int = 0) -> Dict:
+              sweep_callback=None, mlp_weights=None, beta_schedule=None, seed: int = 0,
+              closing_plain: bool = False) -> Dict:
     """CP-ALS-QR (Algorithm 2) / ALS-QR-BR(E) (Algorithm 3) in FP64 with
     direct multi-TTMs from X.  ``tree`` only selects the update order.
 
     ``extrap``: "off" (beta = 0), "paper" (eq. 19 with the activation rule)
     or "learned" (a library feature, not the paper's: after sweep 2 beta is
     the MLP output for the fits of sweeps 1-2 (``mlp_weights``, see
-    mlp_oracle); every later sweep is kept only if its fit exceeds the
-    previous one, otherwise the sweep-start state is restored, beta becomes
-    the paper's table value for the previous fit and the sweep is redone).
+    mlp_oracle) and the state after sweep 2 is the checkpoint, with its
+    explicit fit.  Checks come after LEARNED_FIRST_CHECK sweeps, then after
+    gaps that double, and at the last sweep (and at a tolerance stop): the
+    explicit fit, taken with lambda divided by 1 + (1 - alpha) beta, must
+    exceed the checkpoint's, and then the state becomes the new checkpoint;
+    otherwise the checkpoint is restored, beta becomes the paper's table
+    value for the checkpoint's fit, and the sweeps since the checkpoint are
+    run again with it, with no further checks).  The division undoes the
+    growth of lambda under eq. (19): at a fixed point Q0 of the sweep equals
+    Q0 of the previous one and the extrapolated R0 is (1 + beta - alpha beta)
+    times the plain one.  ``closing_plain``: the last of ``iters`` sweeps
+    runs with beta = 0, so lambda carries no extrapolation factor (its check
+    needs no correction).
     ``fix_beta`` (test hook): apply this beta from sweep 2 onward instead of
     the rule.  ``beta_schedule`` (with "paper"): sweep k >= 2 uses
     beta_schedule[k - 1] instead of the rule.  ``sweep_callback(k, fit)``
@@ -391,6 +406,9 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
     beta, active, beta_sweep = 0.0, False, 0
     learned = extrap == "learned"
     learned_on, fallback, fallback_sweep, beta_learned = False, False, 0, 0.0
+    fit_accept = 0.0
+    ckpt_k = next_check = check_gap = 0
+    ckpt = None
     fits: List[float] = []
     fitxs: List[float] = []
     orders: List[List[int]] = []
@@ -415,16 +433,10 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
             b = fix_beta if k >= 2 else 0.0
         else:
             b = beta if (extrap in ("paper", "learned") and active) else 0.0
-        if learned and learned_on and not fallback:
-            saved = copy.deepcopy((A, Qs, Rfs, lam, Q0prev))
-            fit = sweep(order, b)
-            if not fit > fits[-1]:
-                A, Qs, Rfs, lam, Q0prev = saved
-                beta, beta_sweep = beta_from_fit(fits[-1]), k - 1
-                fallback, fallback_sweep = True, k
-                fit = sweep(order, beta)
-        else:
-            fit = sweep(order, b)
+        closing = closing_plain and k == iters
+        if closing:
+            b = 0.0
+        fit = sweep(order, b)
         fits.append(fit)
         if explicit_every_sweep:
             fitxs.append(explicit_fit(X, lam, A))
@@ -436,9 +448,34 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
             x = M.features(fits[0], fits[1], N, R, X.shape)
             beta = M.beta_from_output(M.forward(mlp_weights, x)[0])
             beta_learned, active, beta_sweep, learned_on = beta, True, 2, True
+            fit_accept = explicit_fit(X, lam, A)
+            ckpt_k, check_gap = 2, LEARNED_FIRST_CHECK
+            next_check = 2 + check_gap
+            ckpt = copy.deepcopy((A, Qs, Rfs, lam, Q0prev))
+        tol_stop = tol > 0.0 and k >= 2 and abs(fits[-1] - fits[-2]) < tol
+        if learned and learned_on and not fallback and k > 2 and \
+                (k == next_check or k == iters or tol_stop):
+            scale = 1.0 if closing else 1.0 / (1.0 + (1.0 - alpha) * beta_learned)
+            fx = explicit_fit(X, lam * scale, A)
+            if fx > fit_accept:
+                fit_accept, ckpt_k = fx, k
+                check_gap *= 2
+                next_check = k + check_gap
+                ckpt = copy.deepcopy((A, Qs, Rfs, lam, Q0prev))
+            else:
+                A, Qs, Rfs, lam, Q0prev = copy.deepcopy(ckpt)
+                beta, beta_sweep = beta_from_fit(fit_accept), ckpt_k
+                fallback, fallback_sweep = True, ckpt_k + 1
+                del fits[ckpt_k:]
+                del fitxs[ckpt_k:]
+                for j in range(ckpt_k + 1, k + 1):
+                    fits.append(sweep(orders[j - 1], 0.0 if closing_plain and j == iters else beta))
+                    if explicit_every_sweep:
+                        fitxs.append(explicit_fit(X, lam, A))
+                tol_stop = tol > 0.0 and abs(fits[-1] - fits[-2]) < tol
         if sweep_callback is not None:
-            sweep_callback(k, fit)
-        if tol > 0.0 and k >= 2 and abs(fit - fits[-2]) < tol:
+            sweep_callback(k, fits[-1])
+        if tol_stop:
             break
     return {
         "factors": A, "lam": lam, "Q": Qs, "R": Rfs, "fits": np.array(fits),
@@ -446,7 +483,7 @@ def cp_als_qr(X: np.ndarray, rank: int, init: Sequence[np.ndarray], iters: int,
         "fitxs": np.array(fitxs),
         "orders": orders, "beta": beta if fix_beta is None else fix_beta,
         "beta_sweep": beta_sweep, "sweeps": len(fits), "nx2": nx2,
-        "beta_learned": beta_learned, "fallback_sweep": fallback_sweep,
+        "beta_learned": beta_learned, "fallback_sweep": fallback_sweep, "fit_accept": fit_accept,
     }
 
 

@@ -24,8 +24,13 @@ import numpy as np
 FEATURES = 8
 HIDDEN = 64
 PARAMS = HIDDEN * FEATURES + 2 * HIDDEN + 1
-BETA_MAX = 0.05
-BETA_SHIFT = 1e-6
+BETA_MAX = 30.0
+# The output is u = g beta / (1 + g beta) with g = 1 - alpha, alpha = 0.1 (the
+# value of the training runs): eq. (19) equals
+# (1 + g beta) (Q0^k + (alpha / g) u (Q0^k - Q0^{k-1})), so u is the momentum
+# of the normalised update up to the constant alpha / g, and lies in [0, 1).
+SHARE_G = 0.9
+U_MAX = SHARE_G * BETA_MAX / (1.0 + SHARE_G * BETA_MAX)
 
 
 def unpack(w: np.ndarray):
@@ -87,13 +92,18 @@ def features(f1: float, f2: float, N: int, R: int, dims: Sequence[int]) -> np.nd
 
 
 def beta_from_output(y: float) -> float:
-    """beta = 10^y - 1e-6, clamped to [0, 0.05]."""
-    b = 10.0 ** float(y) - BETA_SHIFT
-    return min(max(b, 0.0), BETA_MAX)
+    """u = clamp(y, 0, U_MAX); beta = u / (g (1 - u)), at most BETA_MAX."""
+    u = min(max(float(y), 0.0), U_MAX)
+    return min(u / (SHARE_G * (1.0 - u)), BETA_MAX)
+
+
+def share_of_beta(beta: float) -> float:
+    """The output u that maps to ``beta``."""
+    return SHARE_G * beta / (1.0 + SHARE_G * beta)
 
 
 def constant_weights(beta: float) -> np.ndarray:
-    """Weights whose output is the constant log10(beta + 1e-6)."""
+    """Weights whose output is the constant share_of_beta(beta)."""
     w = np.zeros(PARAMS)
-    w[-1] = math.log10(beta + BETA_SHIFT)
+    w[-1] = share_of_beta(beta)
     return w

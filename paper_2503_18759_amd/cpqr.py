@@ -29,6 +29,7 @@ MLP_PARAMS = MLP_HIDDEN * MLP_FEATURES + 2 * MLP_HIDDEN + 1
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 FLAG_EXPLICIT_FIT, FLAG_TIME_KERNELS, FLAG_NO_GRAPH, FLAG_DENSE_ZQR = 0x1, 0x2, 0x4, 0x8
 FLAG_TIME_PHASES = 0x10
+FLAG_CLOSING_PLAIN = 0x20
 PHASES = ("ttm", "qr", "q0", "apply_q0", "other")
 ZQR = ("stair", "dense")
 
@@ -219,7 +220,7 @@ def to_device(X: np.ndarray, dtype=None, device: int = 0):
 
 def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, switch_delta,
              fixed_beta, explicit_fit, time_kernels, use_graph, mlp_weights=None,
-             beta_schedule=None, zqr="stair", seed=0, time_phases=False):
+             beta_schedule=None, zqr="stair", seed=0, time_phases=False, closing_plain=False):
     if zqr not in ZQR:
         raise ValueError(f"zqr must be one of {ZQR}")
     dims, dt, ptr = _dims_and_ptr(x, dims)
@@ -241,7 +242,7 @@ def _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha, sw
             *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in inits])
     flags = (FLAG_EXPLICIT_FIT if explicit_fit else 0) | (FLAG_TIME_KERNELS if time_kernels else 0) \
         | (0 if use_graph else FLAG_NO_GRAPH) | (FLAG_DENSE_ZQR if zqr == "dense" else 0) \
-        | (FLAG_TIME_PHASES if time_phases else 0)
+        | (FLAG_TIME_PHASES if time_phases else 0) | (FLAG_CLOSING_PLAIN if closing_plain else 0)
     wptr = None
     if mlp_weights is not None:
         w = np.ascontiguousarray(np.asarray(mlp_weights, dtype=np.float32).reshape(-1))
@@ -301,7 +302,8 @@ def cp_als_qr(x, rank: int, init: Optional[Sequence[np.ndarray]], iters: int = 1
               alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
               explicit_fit: bool = False, time_kernels: bool = False, use_graph: bool = True,
               mlp_weights=None, beta_schedule=None, zqr: str = "stair", seed: int = 0,
-              time_phases: bool = False, handle: Optional[Handle] = None) -> Dict:
+              time_phases: bool = False, closing_plain: bool = False,
+              handle: Optional[Handle] = None) -> Dict:
     """CP-ALS-QR / ALS-QR-BR(E) on the GPU (Algorithms 2 and 3).
 
     ``zqr="dense"`` factors Z_n by the two-level TSQR even where the
@@ -309,6 +311,7 @@ def cp_als_qr(x, rank: int, init: Optional[Sequence[np.ndarray]], iters: int = 1
     the library draw seeded N(0,1) initial factors from ``seed``.
     ``time_phases`` fills ``phase_seconds`` (TTM, QR, computation and
     application of Q0, other) with kernels launched one by one.
+    ``closing_plain`` runs the last sweep without extrapolation.
 
     Returns a dict with factors (list of I_n x R float64 arrays), lam, fits
     (per-sweep fit history), fit, fit_explicit, orders, beta, beta_sweep,
@@ -317,7 +320,7 @@ def cp_als_qr(x, rank: int, init: Optional[Sequence[np.ndarray]], iters: int = 1
     L = load_library()
     dims, keep = _prepare(x, rank, init, iters, dims, tree, extrapolate, prec, tol, alpha,
                           switch_delta, fixed_beta, explicit_fit, time_kernels, use_graph,
-                          mlp_weights, beta_schedule, zqr, seed, time_phases)
+                          mlp_weights, beta_schedule, zqr, seed, time_phases, closing_plain)
     h = handle or default_handle(x.device.index or 0)
     res, bufs = _result_buffers(dims, rank, iters)
     st = L.cpqr_als_qr(h._h, ctypes.byref(keep["ten"]), int(rank), ctypes.byref(keep["opts"]),
@@ -376,14 +379,15 @@ class Session:
                  alpha: float = 0.1, switch_delta: float = 0.03, fixed_beta: float = 0.0,
                  explicit_fit: bool = False, time_kernels: bool = False,
                  use_graph: bool = True, mlp_weights=None, zqr: str = "stair",
-                 handle: Optional[Handle] = None):
+                 closing_plain: bool = False, handle: Optional[Handle] = None):
         L = load_library()
         self._x = x
         self.rank = rank
         self.max_sweeps = max_sweeps
         self.dims, self._keep = _prepare(x, rank, init, max_sweeps, dims, tree, extrapolate, prec,
                                          tol, alpha, switch_delta, fixed_beta, explicit_fit,
-                                         time_kernels, use_graph, mlp_weights, None, zqr)
+                                         time_kernels, use_graph, mlp_weights, None, zqr,
+                                         closing_plain=closing_plain)
         self.h = handle or default_handle(x.device.index or 0)
         self._s = ctypes.c_void_p()
         self.h.check(L.cpqr_session_create(self.h._h, ctypes.byref(self._keep["ten"]), int(rank),

@@ -282,8 +282,20 @@ hipError_t launch_state_init(DevState* s, const double* part, int nparts, hipStr
 // min(dims[n], R) entries.
 hipError_t launch_init_rank_check(const double* rf, int N, int R, const int64_t* dims, DevState* st,
                                   hipStream_t s);
+// ||X - K||^2 partial sums (sumsq_blocks(n) of them) with the weights
+// lambda multiplied by lambda_scale.
 hipError_t launch_residual(const void* x, bool f64, int N, const int64_t* dims_host,
                            double* const* factors, const double* lambda, int R, double* part,
-                           hipStream_t st);
+                           hipStream_t st, double lambda_scale = 1.0);
+
+// Copies of device buffers in one launch per COPY_LIST_MAX of them (sizes in
+// bytes, multiples of 4; buffers must not overlap).
+constexpr int COPY_LIST_MAX = 32;
+struct CopySeg {
+  const void* src;
+  void* dst;
+  int64_t bytes;
+};
+hipError_t launch_copy_list(const CopySeg* segs, int n, hipStream_t st);
 
 }  // namespace cpqr

@@ -573,6 +573,13 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
       u.v1[j][c] = (j < R && c < R) ? v1 : 0.0;
     }
   });
+  // the Kolda rows again (not held through the factorisation)
+  int krow[RPL];
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    const int s = lane + 64 * p;
+    krow[p] = (s < M) ? smap[s].x : -1;
+  });
   // wave 0 builds T while the other waves write their rows of V
   if (wave == 0) block_qr_build_t_wave0<RMAX>(R, sm);
   // V rows (Kolda order; rows beyond a column's live chunks stay zero in the
@@ -585,12 +592,12 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
       constexpr int p = decltype(pc)::value;
       const int s = lane + 64 * p;
       const double v = (s > c) ? a[SC::OFF(q) + p] * sc_c : ((s == c) ? 1.0 : 0.0);
-      if (tab[p].x >= 0 && c < R) gV[tab[p].x + (int64_t)M * c] = v;
+      if (krow[p] >= 0 && c < R) gV[krow[p] + (int64_t)M * c] = v;
     });
   });
   gdouble* __restrict__ meta = (gdouble*)args.meta;
   if (tid < R) {
-    meta[R * R + R + tid] = (double)tab[0].x;
+    meta[R * R + R + tid] = (double)smap[tid].x;
     meta[R * R + tid] = (sm.beta[tid] < 0.0) ? -1.0 : 1.0;
   }
   __syncthreads();

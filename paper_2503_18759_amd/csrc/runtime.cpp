@@ -183,10 +183,11 @@ struct Problem {
   double* fit_hist = nullptr;
   double* norm_part = nullptr;
   std::map<uint32_t, void*> inter;   // intermediates by free-mode mask
-  // buffers that carry state from one sweep to the next (restored when a
-  // learned-beta sweep is rejected), with their shadow copies
+  // buffers that carry state from one sweep to the next besides the Q0
+  // halves and the intermediates (part of the learned extrapolation's
+  // checkpoint), and the checkpoint copies by live buffer
   std::vector<std::pair<void*, size_t>> carried;
-  std::vector<void*> shadow;
+  std::map<const void*, void*> shadow;
   double* beta_sched = nullptr;   // device copy of cpqr_options.beta_schedule (iters values) or null
   int sched_len = 0;
 };
@@ -224,8 +225,12 @@ struct cpqr_session {
   float* mlp_w = nullptr;        // device weights
   float* mlp_io = nullptr;       // device features (CPQR_MLP_FEATURES) + output (1)
   bool learned_on = false;       // beta from the MLP in force
-  bool fallback = false;         // a learned sweep was rejected: paper beta from then on
+  bool fallback = false;         // a check failed: paper beta from then on
   double beta_learned = 0.0;
+  double fit_accept = 0.0;       // explicit fit at the checkpoint
+  int ckpt_k = 0;                // sweep of the checkpoint
+  int next_check = 0;            // sweep of the next check
+  int check_gap = 0;             // sweeps from the checkpoint to the next check
   int fallback_sweep = 0;
   ~cpqr_session() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -305,12 +310,12 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   WS(h, p.prefix + "V", (size_t)2 * p.Imax * R * 8, p.Vbuf);
   WS(h, p.prefix + "qn", (size_t)CPQR_QN_WORDS * 8, p.qnbuf);
   WS(h, p.prefix + "state", sizeof(DevState), p.state);
+  // State that sweeps hand on besides the Q0 halves and the intermediates:
+  // factors, Q_n, R factors, lambda and the device state.
   p.carried.clear();
   for (int k = 0; k < N; ++k) {
     p.carried.push_back({p.A[k], (size_t)p.dims[k] * R * 8});
     p.carried.push_back({p.Q[k], (size_t)p.dims[k] * R * p.elem});
-    p.carried.push_back({p.q0buf[k], (size_t)2 * p.M * R * 8});
-    if (p.q0meta[k]) p.carried.push_back({p.q0meta[k], (size_t)2 * (R * R + 2 * R) * 8});
   }
   p.carried.push_back({p.rf, (size_t)N * R * R * 8});
   p.carried.push_back({p.lambda, (size_t)R * 8});
@@ -327,7 +332,6 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
           void* ptr = nullptr;
           WS(h, p.prefix + "Y" + std::to_string(dst), (size_t)inter_elems(p, dst) * p.elem, ptr);
           p.inter[dst] = ptr;
-          p.carried.push_back({ptr, (size_t)inter_elems(p, dst) * p.elem});
         }
       }
   (void)full;
@@ -418,6 +422,11 @@ cpqr_status tune_ttm_steps(cpqr_handle* h, Problem& p, const std::vector<std::ve
   return CPQR_OK;
 }
 
+// The closing plain sweep of CPQR_FLAG_CLOSING_PLAIN (1-based sweep k).
+bool closing_sweep(const cpqr_options* o, int k) {
+  return (o->flags & CPQR_FLAG_CLOSING_PLAIN) && k == o->iters;
+}
+
 // Arguments of the mode-n update of sweep k (Z QR, Y*Q0, finish).  Q0 of
 // the sweep and of the previous sweep are the two halves of the mode's
 // ping-pong buffer.
@@ -472,7 +481,7 @@ void update_args(const Problem& p, int n, int sweep_k, bool last, const cpqr_opt
   f->delta = o->switch_delta;
   f->fixed_beta = o->fixed_beta;
   // the learned mode drives the same device-side beta state as the paper's rule
-  f->extrap = (o->extrapolate != CPQR_EXTRAP_OFF) ? 1 : 0;
+  f->extrap = (o->extrapolate != CPQR_EXTRAP_OFF && !closing_sweep(o, sweep_k)) ? 1 : 0;
   f->last_in_sweep = last ? 1 : 0;
   f->beta_sched = p.beta_sched;
   f->sched_len = p.sched_len;
@@ -914,7 +923,9 @@ cpqr_status cpqr_session_create(cpqr_handle* h, const cpqr_tensor* X, int rank,
 namespace {
 
 // Enqueues sweep k (graph replay, or kernel by kernel) and counts its TTM work.
-cpqr_status run_sweep(cpqr_session* S, int k) {
+// Runs sweep k (1-based).  capture_only: only capture (and keep) the sweep's
+// graph if it is not there yet, without running it.
+cpqr_status run_sweep(cpqr_session* S, int k, bool capture_only = false) {
   cpqr_handle* h = S->h;
   hipStream_t s = h->stream;
   const cpqr_options* o = &S->opts;
@@ -925,6 +936,7 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
   const bool use_graph = !timing && !phases && !(o->flags & CPQR_FLAG_NO_GRAPH);
   const uint32_t full = (1u << N) - 1u;
   const auto& sw = S->sched[k - 1];
+  if (capture_only && !use_graph) return CPQR_OK;
   // phase timing: an event at every kernel-group boundary, kernel by kernel
   size_t ph_n = 0;
   const PhaseMark mark = [&](int phase) -> hipError_t {
@@ -939,7 +951,7 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
     return hipEventRecord(S->ph_ev[ph_n++], s);
   };
   for (const Step& st : sw)
-    if (st.kind == STEP_TTM) {
+    if (st.kind == STEP_TTM && !capture_only) {
       const int64_t in = inter_elems(p, st.src);
       const int64_t outn = in / p.dims[st.mode] * p.R;
       S->ttm_flops += 2.0 * in * p.R;
@@ -1068,7 +1080,7 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
   };
   if (use_graph) {
     // sweeps with the same step list and Q0 ping-pong parity share a graph
-    const std::string key = sweep_key(sw, k == 1 ? 2 : (k % 2), o->extrapolate != 0);
+    const std::string key = sweep_key(sw, k == 1 ? 2 : (k % 2), o->extrapolate != 0 && !closing_sweep(o, k));
     auto itg = S->graphs.find(key);
     if (itg == S->graphs.end()) {
       hipGraph_t g;
@@ -1084,6 +1096,7 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
       if (e3 != hipSuccess) return fail(h, CPQR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e3));
       itg = S->graphs.emplace(key, ge).first;
     }
+    if (capture_only) return CPQR_OK;
     HIP_TRY(h, hipGraphLaunch(itg->second, s));
   } else {
     hipError_t e = enqueue(s);
@@ -1101,23 +1114,40 @@ cpqr_status run_sweep(cpqr_session* S, int k) {
   return CPQR_OK;
 }
 
-// Copies every buffer that carries state between sweeps into (to_shadow) or
-// back from its shadow copy.
-cpqr_status copy_carried(cpqr_session* S, bool to_shadow) {
+// Checkpoint of the state after sweep c (1-based) for the learned
+// extrapolation: everything sweeps c+1, c+2, ... read before they write it,
+// that is the carried buffers, the Q0 half of sweep c of every mode (Q0^{k-1}
+// of sweep c+1) with its compact-form metadata, and the intermediates live
+// across the boundary.  save: live -> copy; otherwise copy -> live.  One
+// launch per COPY_LIST_MAX buffers, on the library's stream.
+cpqr_status checkpoint(cpqr_session* S, int c, bool save) {
   cpqr_handle* h = S->h;
   Problem& p = S->p;
-  if (p.shadow.size() != p.carried.size()) {
-    p.shadow.resize(p.carried.size());
-    for (size_t i = 0; i < p.carried.size(); ++i)
-      WS(h, p.prefix + "shadow" + std::to_string(i), p.carried[i].second, p.shadow[i]);
+  std::vector<std::pair<void*, size_t>> bufs(p.carried);
+  const size_t mw = (size_t)p.R * p.R + 2 * p.R;
+  for (int n = 0; n < p.N; ++n) {
+    bufs.push_back({p.q0buf[n] + (size_t)(c % 2) * p.M * p.R, (size_t)p.M * p.R * 8});
+    if (p.q0meta[n]) bufs.push_back({p.q0meta[n] + (size_t)(c % 2) * mw, mw * 8});
   }
-  for (size_t i = 0; i < p.carried.size(); ++i) {
-    void* live = p.carried[i].first;
-    if (to_shadow)
-      HIP_TRY(h, hipMemcpyAsync(p.shadow[i], live, p.carried[i].second, hipMemcpyDeviceToDevice, h->stream));
+  for (uint32_t m : live_intermediates(p.N, S->sched, c)) {
+    auto it = p.inter.find(m);
+    if (it == p.inter.end()) return fail(h, CPQR_EINVAL, "checkpoint: intermediate %u not allocated", m);
+    bufs.push_back({it->second, (size_t)inter_elems(p, m) * p.elem});
+  }
+  std::vector<CopySeg> segs;
+  for (const auto& b : bufs) {
+    auto it = p.shadow.find(b.first);
+    if (it == p.shadow.end()) {
+      void* sh = nullptr;
+      WS(h, p.prefix + "ckpt" + std::to_string(p.shadow.size()), b.second, sh);
+      it = p.shadow.emplace(b.first, sh).first;
+    }
+    if (save)
+      segs.push_back(CopySeg{b.first, it->second, (int64_t)b.second});
     else
-      HIP_TRY(h, hipMemcpyAsync(live, p.shadow[i], p.carried[i].second, hipMemcpyDeviceToDevice, h->stream));
+      segs.push_back(CopySeg{it->second, b.first, (int64_t)b.second});
   }
+  HIP_TRY(h, launch_copy_list(segs.data(), (int)segs.size(), h->stream));
   return CPQR_OK;
 }
 
@@ -1126,6 +1156,24 @@ cpqr_status read_fits(cpqr_session* S, int k, double* f) {
   cpqr_handle* h = S->h;
   HIP_TRY(h, hipMemcpyAsync(f, S->p.fit_hist + (k - 2), 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return CPQR_OK;
+}
+
+// Explicit fit 1 - ||X - K|| / ||X|| of the current factors, with lambda
+// multiplied by lambda_scale (float64 accumulation).
+cpqr_status explicit_fit(cpqr_session* S, double lambda_scale, double* fit) {
+  cpqr_handle* h = S->h;
+  Problem& p = S->p;
+  std::vector<double*> fac(p.A.begin(), p.A.end());
+  HIP_TRY(h, launch_residual(p.X, p.f64, p.N, p.dims.data(), fac.data(), p.lambda, p.R, p.norm_part, h->stream,
+                             lambda_scale));
+  const int nb = sumsq_blocks(S->nelem);
+  std::vector<double> part(nb);
+  HIP_TRY(h, hipMemcpyAsync(part.data(), p.norm_part, nb * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  double r2 = 0.0;
+  for (double v : part) r2 += v;
+  *fit = 1.0 - std::sqrt(r2) / std::sqrt(S->nx2);
   return CPQR_OK;
 }
 
@@ -1151,6 +1199,12 @@ double paper_beta(double fit) {
   return 1.0 / 250.0;
 }
 
+// Upper end of the training grid of the learned beta.
+constexpr double kMaxLearnedBeta = 30.0;
+// Sweeps from the learned beta's start (after sweep 2) to its first check;
+// the gap between checks doubles after every passed check.
+constexpr int kLearnedFirstCheck = 4;
+
 // Learned beta after sweep 2 from the fits of sweeps 1 and 2 (features as in
 // cpqr.h), evaluated by the MLP kernel.
 cpqr_status learned_beta(cpqr_session* S, double f1, double f2, double* beta) {
@@ -1170,10 +1224,14 @@ cpqr_status learned_beta(cpqr_session* S, double f1, double f2, double* beta) {
   float y = 0.f;
   HIP_TRY(h, hipMemcpyAsync(&y, S->mlp_io + CPQR_MLP_FEATURES, sizeof(float), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  double b = std::pow(10.0, (double)y) - 1e-6;
-  if (!(b > 0.0)) b = 0.0;
-  if (b > 0.05) b = 0.05;
-  *beta = b;
+  // y is u = g beta / (1 + g beta), g = 1 - 0.1 (the alpha of the training
+  // runs): the momentum of the normalised eq. (19) update up to alpha / g
+  constexpr double g = 0.9;
+  constexpr double u_max = g * kMaxLearnedBeta / (1.0 + g * kMaxLearnedBeta);
+  double u = (double)y;
+  if (!(u > 0.0)) u = 0.0;
+  if (u > u_max) u = u_max;
+  *beta = std::min(u / (g * (1.0 - u)), kMaxLearnedBeta);
   return CPQR_OK;
 }
 
@@ -1202,41 +1260,73 @@ cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
   for (int it = 0; it < nsweeps; ++it) {
     const int k = S->k + 1;
     cpqr_status st;
-    if (learned && S->learned_on && !S->fallback) {
-      // acceptance test: keep the sweep only if the fit improves
-      if ((st = copy_carried(S, true)) != CPQR_OK) return st;
-      if ((st = run_sweep(S, k)) != CPQR_OK) return st;
-      double f[2];
-      if ((st = read_fits(S, k, f)) != CPQR_OK) return st;
-      if (!(f[1] > f[0])) {
-        if ((st = copy_carried(S, false)) != CPQR_OK) return st;
-        if ((st = set_beta(S, paper_beta(f[0]), k - 1)) != CPQR_OK) return st;
-        S->fallback = true;
-        S->fallback_sweep = k;
-        if ((st = run_sweep(S, k)) != CPQR_OK) return st;
-      }
-    } else {
-      if ((st = run_sweep(S, k)) != CPQR_OK) return st;
-    }
+    if ((st = run_sweep(S, k)) != CPQR_OK) return st;
     S->k = k;
+    // the closing plain sweep's graph (another key when extrapolation is on)
+    // is captured with the first sweep's, so that no later sweep pays for it
+    if (k == 1 && closing_sweep(o, o->iters) && o->iters > 1 && (st = run_sweep(S, o->iters, true)) != CPQR_OK)
+      return st;
     if (learned && k == 2 && !S->learned_on) {
       double f[2], b = 0.0;
       if ((st = read_fits(S, 2, f)) != CPQR_OK) return st;
+      if ((st = explicit_fit(S, 1.0, &S->fit_accept)) != CPQR_OK) return st;
       if ((st = learned_beta(S, f[0], f[1], &b)) != CPQR_OK) return st;
       if ((st = set_beta(S, b, 2)) != CPQR_OK) return st;
       S->beta_learned = b;
       S->learned_on = true;
+      S->ckpt_k = 2;
+      S->check_gap = kLearnedFirstCheck;
+      S->next_check = 2 + kLearnedFirstCheck;
+      if (o->iters > 2 && (st = checkpoint(S, 2, true)) != CPQR_OK) return st;
     }
+    bool tol_stop = false;
     if (o->tol > 0.0 && k >= 2) {
       DevState hs;
       HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
       double fk[2];
       HIP_TRY(h, hipMemcpyAsync(fk, p.fit_hist + (k - 2), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(h, hipStreamSynchronize(s));
-      if (hs.flags || std::fabs(fk[1] - fk[0]) < o->tol) {
-        S->stopped = true;
-        break;
+      tol_stop = hs.flags || std::fabs(fk[1] - fk[0]) < o->tol;
+    }
+    if (learned && S->learned_on && !S->fallback && k > 2 &&
+        (k == S->next_check || k == o->iters || tol_stop)) {
+      // acceptance test on the explicit fit.  While beta is on, eq. (19)
+      // scales each update by about 1 + (1 - alpha) beta (exactly at a fixed
+      // point), which lambda carries and the factors' directions do not; the
+      // fit is taken with lambda divided by that factor, so that it compares
+      // with the checkpoint's.  The closing plain sweep needs no correction.
+      double fx = 0.0;
+      const double scale = closing_sweep(o, k) ? 1.0 : 1.0 / (1.0 + (1.0 - o->alpha) * S->beta_learned);
+      if ((st = explicit_fit(S, scale, &fx)) != CPQR_OK) return st;
+      if (fx > S->fit_accept) {
+        S->fit_accept = fx;
+        S->ckpt_k = k;
+        S->check_gap *= 2;
+        S->next_check = k + S->check_gap;
+        if (k < o->iters && !tol_stop && (st = checkpoint(S, k, true)) != CPQR_OK) return st;
+      } else {
+        // back to the checkpoint; sweeps ckpt_k + 1 .. k again with the
+        // paper's beta for the checkpoint's fit
+        if ((st = checkpoint(S, S->ckpt_k, false)) != CPQR_OK) return st;
+        if ((st = set_beta(S, paper_beta(S->fit_accept), S->ckpt_k)) != CPQR_OK) return st;
+        S->fallback = true;
+        S->fallback_sweep = S->ckpt_k + 1;
+        for (int j = S->ckpt_k + 1; j <= k; ++j)
+          if ((st = run_sweep(S, j)) != CPQR_OK) return st;
+        tol_stop = false;
+        if (o->tol > 0.0) {
+          DevState hs;
+          HIP_TRY(h, hipMemcpyAsync(&hs, p.state, sizeof(DevState), hipMemcpyDeviceToHost, s));
+          double fk[2];
+          HIP_TRY(h, hipMemcpyAsync(fk, p.fit_hist + (k - 2), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIP_TRY(h, hipStreamSynchronize(s));
+          tol_stop = hs.flags || std::fabs(fk[1] - fk[0]) < o->tol;
+        }
       }
+    }
+    if (tol_stop) {
+      S->stopped = true;
+      break;
     }
   }
   return CPQR_OK;

@@ -212,4 +212,23 @@ bool validate_schedule(int N, const std::vector<std::vector<Step>>& sched) {
   return true;
 }
 
+std::vector<uint32_t> live_intermediates(int N, const std::vector<std::vector<Step>>& sched, int from) {
+  const uint32_t full = (1u << N) - 1u;
+  std::vector<char> first(1u << N, 0);   // 0: not accessed yet, 'r' or 'w'
+  std::vector<uint32_t> live;
+  for (size_t k = from < 0 ? 0 : (size_t)from; k < sched.size(); ++k)
+    for (const Step& st : sched[k]) {
+      const uint32_t rd = st.kind == STEP_TTM ? st.src : (1u << st.mode);
+      if (rd != full && !first[rd]) {
+        first[rd] = 'r';
+        live.push_back(rd);
+      }
+      if (st.kind == STEP_TTM) {
+        const uint32_t d = st.src & ~(1u << st.mode);
+        if (!first[d]) first[d] = 'w';
+      }
+    }
+  return live;
+}
+
 }  // namespace cpqr

@@ -23,4 +23,10 @@ bool build_schedule(int N, int tree, int sweeps, std::vector<std::vector<Step>>&
 // and every leaf only contains contractions with the current Q's.
 bool validate_schedule(int N, const std::vector<std::vector<Step>>& sched);
 
+// Intermediates (free-mode masks, X excluded) live across the boundary
+// before sweep index `from` (0-based): those whose first access in sweeps
+// from, from + 1, ... is a read, so that running those sweeps again needs
+// their contents as they were at the boundary.
+std::vector<uint32_t> live_intermediates(int N, const std::vector<std::vector<Step>>& sched, int from);
+
 }  // namespace cpqr

@@ -1085,9 +1085,131 @@ __global__ __launch_bounds__(NORM_THREADS) void residual_kernel(const T* __restr
   }
 }
 
+// ||X - K||^2 by mode-1 fibres: a wave takes one fibre (i_2 .. i_N) at a
+// time, forms w_r = s lambda_r prod_{k >= 2} A_k[i_k][r] in lanes r < R
+// (shared through the wave's LDS row), and its lanes run along mode 1
+// (contiguous in X) with K[i] = sum_r A_1[i][r] w_r from A_1 in LDS.
+// float64 throughout, as residual_kernel; R <= 64 and I_1 R <= RF_A1.
+static constexpr int RF_A1 = 8192;
+
+template <typename T>
+__global__ __launch_bounds__(NORM_THREADS) void residual_fiber_kernel(const T* __restrict__ x, int N,
+                                                                      FactorPtrs fp, const double* __restrict__ lam,
+                                                                      double lscale, int R, int64_t nfib,
+                                                                      double* __restrict__ part) {
+  __shared__ double a1s[RF_A1];
+  __shared__ double wv[NORM_THREADS / 64][64];
+  __shared__ double red[NORM_THREADS / 64];
+  const int I1 = (int)fp.dims[0];
+  for (int e = threadIdx.x; e < I1 * R; e += NORM_THREADS) {
+    const int i = e / R, r = e % R;
+    a1s[e] = fp.a[0][i + (int64_t)I1 * r];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * (NORM_THREADS / 64);
+  double s = 0.0;
+  for (int64_t f = (int64_t)blockIdx.x * (NORM_THREADS / 64) + wave; f < nfib; f += nwaves) {
+    if (lane < R) {
+      double prod = lam[lane] * lscale;
+      int64_t rem = f;
+      for (int k = 1; k < N; ++k) {
+        const int64_t ik = rem % fp.dims[k];
+        rem /= fp.dims[k];
+        prod *= fp.a[k][ik + fp.dims[k] * lane];
+      }
+      wv[wave][lane] = prod;
+    }
+    // one wave's LDS operations complete in order: the row is written
+    // before any lane reads it
+    const T* __restrict__ xf = x + f * I1;
+    for (int i = lane; i < I1; i += 64) {
+      double kv = 0.0;
+      for (int r = 0; r < R; ++r) kv = fma(a1s[i * R + r], wv[wave][r], kv);
+      const double d = (double)xf[i] - kv;
+      s = fma(d, d, s);
+    }
+  }
+  s = wave_sum(s);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NORM_THREADS / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+// ||X - K||^2 with one mode-1 fibre (i_2 .. i_N) per thread, for short
+// fibres (I_1 < 64, where a wave per fibre would leave lanes idle and pay
+// the fibre's index arithmetic and factor loads for few entries): the thread
+// forms w_r = s lambda_r prod_{k >= 2} A_k[i_k][r] in registers and runs
+// along the fibre with K[i] = sum_r A_1[i][r] w_r, reading A_1 from LDS
+// (every lane reads the same row: broadcast).  A_1 is held as I_1 rows of
+// RM doubles, zero beyond R.  float64 throughout.
+template <typename T, int RM>
+__global__ __launch_bounds__(NORM_THREADS) void residual_thread_fiber_kernel(
+    const T* __restrict__ x, int N, FactorPtrs fp, const double* __restrict__ lam, double lscale, int R,
+    int64_t nfib, double* __restrict__ part) {
+  extern __shared__ double a1t[];
+  __shared__ double red[NORM_THREADS / 64];
+  const int I1 = (int)fp.dims[0];
+  for (int e = threadIdx.x; e < I1 * RM; e += NORM_THREADS) {
+    const int i = e / RM, r = e % RM;
+    a1t[e] = r < R ? fp.a[0][i + (int64_t)I1 * r] : 0.0;
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int64_t f = (int64_t)blockIdx.x * NORM_THREADS + threadIdx.x; f < nfib;
+       f += (int64_t)gridDim.x * NORM_THREADS) {
+    double w[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) w[r] = r < R ? lam[r] * lscale : 0.0;
+    int64_t rem = f;
+    for (int k = 1; k < N; ++k) {
+      const int64_t dk = fp.dims[k];
+      const int64_t ik = rem % dk;
+      rem /= dk;
+      const double* __restrict__ ak = fp.a[k] + ik;
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+        if (r < R) w[r] *= ak[dk * r];
+    }
+    const T* __restrict__ xf = x + f * I1;
+    for (int i = 0; i < I1; ++i) {
+      const double* __restrict__ row = a1t + i * RM;
+      double kv = 0.0;
+#pragma unroll
+      for (int r = 0; r < RM; ++r) kv = fma(row[r], w[r], kv);
+      const double d = (double)xf[i] - kv;
+      s = fma(d, d, s);
+    }
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NORM_THREADS / 64; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+template <int RM>
+void launch_residual_thread_fiber(const void* x, bool f64, int N, const FactorPtrs& fp, const double* lambda,
+                                  double lscale, int R, int64_t nfib, int b, double* part, hipStream_t st) {
+  const size_t lds = (size_t)fp.dims[0] * RM * sizeof(double);
+  if (f64)
+    hipLaunchKernelGGL((residual_thread_fiber_kernel<double, RM>), dim3(b), dim3(NORM_THREADS), lds, st,
+                       (const double*)x, N, fp, lambda, lscale, R, nfib, part);
+  else
+    hipLaunchKernelGGL((residual_thread_fiber_kernel<float, RM>), dim3(b), dim3(NORM_THREADS), lds, st,
+                       (const float*)x, N, fp, lambda, lscale, R, nfib, part);
+}
+
 hipError_t launch_residual(const void* x, bool f64, int N, const int64_t* dims_host,
                            double* const* factors, const double* lambda, int R, double* part,
-                           hipStream_t st) {
+                           hipStream_t st, double lambda_scale) {
   FactorPtrs fp;
   int64_t n = 1;
   for (int k = 0; k < N; ++k) {
@@ -1096,9 +1218,92 @@ hipError_t launch_residual(const void* x, bool f64, int N, const int64_t* dims_h
     n *= dims_host[k];
   }
   const int b = sumsq_blocks(n);
+  if (R <= 64 && dims_host[0] < 64 && N >= 2) {
+    const int64_t nfib = n / dims_host[0];
+    if (R <= 8) launch_residual_thread_fiber<8>(x, f64, N, fp, lambda, lambda_scale, R, nfib, b, part, st);
+    else if (R <= 16) launch_residual_thread_fiber<16>(x, f64, N, fp, lambda, lambda_scale, R, nfib, b, part, st);
+    else if (R <= 24) launch_residual_thread_fiber<24>(x, f64, N, fp, lambda, lambda_scale, R, nfib, b, part, st);
+    else if (R <= 32) launch_residual_thread_fiber<32>(x, f64, N, fp, lambda, lambda_scale, R, nfib, b, part, st);
+    else if (R <= 48) launch_residual_thread_fiber<48>(x, f64, N, fp, lambda, lambda_scale, R, nfib, b, part, st);
+    else launch_residual_thread_fiber<64>(x, f64, N, fp, lambda, lambda_scale, R, nfib, b, part, st);
+    return hipGetLastError();
+  }
+  if (R <= 64 && dims_host[0] * R <= RF_A1) {
+    const int64_t nfib = n / dims_host[0];
+    if (f64)
+      hipLaunchKernelGGL(residual_fiber_kernel<double>, dim3(b), dim3(NORM_THREADS), 0, st, (const double*)x, N, fp,
+                         lambda, lambda_scale, R, nfib, part);
+    else
+      hipLaunchKernelGGL(residual_fiber_kernel<float>, dim3(b), dim3(NORM_THREADS), 0, st, (const float*)x, N, fp,
+                         lambda, lambda_scale, R, nfib, part);
+    return hipGetLastError();
+  }
+  if (lambda_scale != 1.0) return hipErrorInvalidValue;
   if (f64) hipLaunchKernelGGL(residual_kernel<double>, dim3(b), dim3(NORM_THREADS), 0, st, (const double*)x, N, fp, lambda, R, n, part);
   else     hipLaunchKernelGGL(residual_kernel<float>, dim3(b), dim3(NORM_THREADS), 0, st, (const float*)x, N, fp, lambda, R, n, part);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- copy list
+// One launch copies up to COPY_LIST_MAX device buffers (the checkpoint of
+// the learned extrapolation: factors, Q0 halves, live intermediates).  Work
+// goes in chunks of COPY_CHUNK bytes; block b finds its buffer from the
+// chunk prefix sums.  16-byte accesses where both addresses are 16-byte
+// aligned, 4-byte ones otherwise and for the tail (sizes are multiples of 4).
+static constexpr int COPY_THREADS = 256;
+static constexpr int64_t COPY_CHUNK = 16384;
+
+struct CopyListArgs {
+  CopySeg seg[COPY_LIST_MAX];
+  int64_t chunk0[COPY_LIST_MAX + 1];   // first chunk of each buffer; chunk0[n] = total
+  int n;
+};
+
+__global__ __launch_bounds__(COPY_THREADS) void copy_list_kernel(CopyListArgs a) {
+  const int64_t c = blockIdx.x;
+  int s = 0;
+  while (s + 1 < a.n && a.chunk0[s + 1] <= c) ++s;
+  const CopySeg g = a.seg[s];
+  const int64_t off = (c - a.chunk0[s]) * COPY_CHUNK;
+  const int64_t rest = g.bytes - off;
+  const int64_t len = rest < COPY_CHUNK ? rest : COPY_CHUNK;
+  const char* __restrict__ src = static_cast<const char*>(g.src) + off;
+  char* __restrict__ dst = static_cast<char*>(g.dst) + off;
+  int64_t done = 0;
+  if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+    const int64_t n16 = len / 16;
+    const uint4* __restrict__ s4 = reinterpret_cast<const uint4*>(src);
+    uint4* __restrict__ d4 = reinterpret_cast<uint4*>(dst);
+    for (int64_t i = threadIdx.x; i < n16; i += COPY_THREADS) d4[i] = s4[i];
+    done = n16 * 16;
+  }
+  const int64_t n4 = (len - done) / 4;
+  const uint32_t* __restrict__ s1 = reinterpret_cast<const uint32_t*>(src + done);
+  uint32_t* __restrict__ d1 = reinterpret_cast<uint32_t*>(dst + done);
+  for (int64_t i = threadIdx.x; i < n4; i += COPY_THREADS) d1[i] = s1[i];
+}
+
+hipError_t launch_copy_list(const CopySeg* segs, int n, hipStream_t st) {
+  int i = 0;
+  while (i < n) {
+    CopyListArgs a{};
+    a.n = 0;
+    int64_t chunks = 0;
+    for (; i < n && a.n < COPY_LIST_MAX; ++i) {
+      if (segs[i].bytes <= 0) continue;
+      if (segs[i].bytes % 4 != 0) return hipErrorInvalidValue;
+      a.seg[a.n] = segs[i];
+      a.chunk0[a.n] = chunks;
+      chunks += (segs[i].bytes + COPY_CHUNK - 1) / COPY_CHUNK;
+      ++a.n;
+    }
+    a.chunk0[a.n] = chunks;
+    if (chunks == 0) continue;
+    hipLaunchKernelGGL(copy_list_kernel, dim3((unsigned)chunks), dim3(COPY_THREADS), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace cpqr

@@ -14,8 +14,14 @@ carry, so a fit read while beta is still on mixes the acceleration with that
 offset; two plain sweeps remove it.  The label is the beta whose explicit fit
 after HORIZON sweeps is highest (ties: the smallest beta).  The features are those of the
 learned mode (include/cpqr.h), computed from the fits of sweeps 1 and 2 of
-the beta = 0 run.  The MLP (8 -> 64 tanh -> 1) regresses log10(beta + 1e-6)
-and is trained with the library's Adam kernels.
+the beta = 0 run.  The MLP (8 -> 64 tanh -> 1) regresses the momentum share
+u = g beta / (1 + g beta), g = 1 - alpha = 0.9 (include/cpqr.h): eq. (19)
+equals (1 + g beta) (Q0^k + (alpha / g) u (Q0^k - Q0^{k-1})), so u is the
+momentum of the normalised update up to a constant, and where problems with
+alike features have different labels the regression averages momenta, not
+orders of magnitude of beta.  It is trained with the library's Adam kernels.
+The labelled set (features, labels and the explicit fit of every grid value)
+is written beside the weights.
 
 Run on a GPU host from the repository root:
     python -m paper_2503_18759_amd.learned_beta [--count 2000]
@@ -34,10 +40,25 @@ import numpy as np
 
 from . import cpqr as C
 
-GRID = [0.0, 5e-5, 2e-4, 5e-4, 1e-3, 2e-3, 4e-3, 1e-2, 2e-2, 3.5e-2, 5e-2]
+# Beta enters eq. (19) as (1 + beta) Q0^k - alpha beta Q0^{k-1}: the part that
+# moves the factors is the difference term, alpha beta (Q0^k - Q0^{k-1})
+# against (1 + (1 - alpha) beta) Q0^k, whose weight grows towards
+# alpha / (1 - alpha) only for beta of order one and more, so the grid
+# reaches well past the paper's table (at most 1/250).
+GRID = [0.0, 1e-3, 1e-2, 5e-2, 0.1, 0.3, 1.0, 3.0, 10.0, 30.0]
 HORIZON = 30
 BASE_SEED = 10000
 WEIGHTS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "learned_beta_mlp.json")
+DATASET_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "learned_beta_dataset.npz")
+
+
+SHARE_G = 0.9
+BETA_MAX = 30.0
+
+
+def share_of_beta(beta: float) -> float:
+    """The network output u for ``beta`` (the library maps u back)."""
+    return SHARE_G * beta / (1.0 + SHARE_G * beta)
 
 
 def features(f1: float, f2: float, N: int, R: int, dims: Sequence[int]) -> np.ndarray:
@@ -99,7 +120,7 @@ def build_dataset(count: int, group: int = 5, log=print):
             probs = [problem(t) for t in ids[g0:g0 + group]]
             for f, beta, fx in label_group(probs):
                 X.append(f)
-                y.append(math.log10(beta + 1e-6))
+                y.append(share_of_beta(beta))
                 fits.append(fx)
             log(f"labelled {len(y)}/{count} ({time.time() - t0:.0f} s)")
     return np.array(X, np.float32), np.array(y, np.float32), np.array(fits)
@@ -124,15 +145,31 @@ def main():
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--out", default=WEIGHTS_PATH)
+    ap.add_argument("--dataset", default=DATASET_PATH,
+                    help="labelled set: read if it exists and --relabel is not given, else written")
+    ap.add_argument("--relabel", action="store_true")
     args = ap.parse_args()
     C.load_library()
-    X, y, fits = build_dataset(args.count, log=lambda m: print(m, flush=True))
+    if os.path.exists(args.dataset) and not args.relabel:
+        d = np.load(args.dataset)
+        X, betas, fits = d["features"], d["labels"], d["fits"]
+        if len(betas) != args.count or list(d["grid"]) != GRID:
+            raise SystemExit(f"{args.dataset} holds another set: run with --relabel")
+        y = np.array([share_of_beta(b) for b in betas], np.float32)
+        print(f"read {len(y)} labelled problems from {args.dataset}", flush=True)
+    else:
+        X, y, fits = build_dataset(args.count, log=lambda m: print(m, flush=True))
+        betas = np.array([GRID[int(np.argmax(f))] for f in fits])
+        os.makedirs(os.path.dirname(args.dataset), exist_ok=True)
+        np.savez_compressed(args.dataset, features=X, labels=betas, fits=fits, grid=np.array(GRID))
+        print("wrote", args.dataset, flush=True)
     w, hist, val_loss, const_loss = train(X, y, epochs=args.epochs)
     print(f"train loss {hist[0]:.4f} -> {hist[-1]:.4f}; validation {val_loss:.4f} "
           f"(constant predictor {const_loss:.4f})", flush=True)
-    labels = {f"{b:g}": int(np.sum(np.isclose(y, math.log10(b + 1e-6)))) for b in GRID}
+    labels = {f"{b:g}": int(np.sum(betas == b)) for b in GRID}
     doc = {
-        "what": "weights of the learned extrapolation MLP (8 -> 64 tanh -> 1, output log10(beta + 1e-6))",
+        "what": "weights of the learned extrapolation MLP (8 -> 64 tanh -> 1, output the momentum "
+                "share u = 0.9 beta / (1 + 0.9 beta))",
         "layout": "W1 (64 x 8 row-major), b1 (64), w2 (64), b2 (1)",
         "training_set": {"count": args.count, "seeds": [BASE_SEED, BASE_SEED + args.count - 1],
                          "orders": "3 (even index), 4 (odd index)", "dims": "U{24..64}",

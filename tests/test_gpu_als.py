@@ -215,6 +215,29 @@ def test_fp64_beta_schedule(P):
         assert np.max(np.abs(a - b)) <= 1e-8
 
 
+def test_fp64_closing_plain_sweep(P):
+    """The closing plain sweep: sweep ``iters`` runs with beta = 0 whatever
+    the schedule or the activation rule says, so the final lambda carries no
+    extrapolation factor.  Large betas (10) make the factor visible."""
+    prob = G.workload("small_o4", dtype=np.float64)
+    sched = [0.0] + [10.0] * 9
+    x, dims = P.to_device(prob.X)
+    g = P.cp_als_qr(x, prob.rank, prob.init, len(sched), dims=dims, tree="restructured",
+                    extrapolate="paper", prec="fp64", beta_schedule=sched, closing_plain=True,
+                    explicit_fit=True)
+    o = O.cp_als_qr(prob.X, prob.rank, prob.init, len(sched), tree="restructured", extrap="paper",
+                    beta_schedule=sched, closing_plain=True)
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-10
+    assert np.max(np.abs(g["lam"] - o["lam"])) <= 1e-8 * np.max(np.abs(o["lam"]))
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+    # the same run without the closing sweep ends with lambda inflated
+    n = O.cp_als_qr(prob.X, prob.rank, prob.init, len(sched), tree="restructured", extrap="paper",
+                    beta_schedule=sched)
+    assert n["fitx"] < o["fitx"] - 0.5
+
+
 def test_fp32_paper_extrapolation(P):
     prob = G.make_problem([30, 26, 34], 5, seed=22, congruence=0.7, rho=0.02, dtype=np.float32)
     g, o = _run(P, prob, 40, prec="fp32", tree="restructured", extrap="paper")

@@ -78,13 +78,15 @@ def test_training_fits_a_teacher(P):
     assert abs(hist[-1] - rl) <= 1e-4 * max(1.0, rl)
 
 
-def _learned(P, prob, iters, w, prec):
+def _learned(P, prob, iters, w, prec, closing_plain=False):
     dt = np.float64 if prec == "fp64" else np.float32
     x, dims = P.to_device(prob.X.astype(dt))
     g = P.cp_als_qr(x, prob.rank, prob.init, iters, dims=dims, tree="restructured",
-                    extrapolate="learned", prec=prec, mlp_weights=w, explicit_fit=True)
+                    extrapolate="learned", prec=prec, mlp_weights=w, explicit_fit=True,
+                    closing_plain=closing_plain)
     o = O.cp_als_qr(np.asarray(prob.X, dtype=dt).astype(np.float64), prob.rank, prob.init, iters,
-                    tree="restructured", extrap="learned", mlp_weights=np.asarray(w, np.float64))
+                    tree="restructured", extrap="learned", mlp_weights=np.asarray(w, np.float64),
+                    closing_plain=closing_plain)
     return g, o
 
 
@@ -100,10 +102,13 @@ def test_learned_constant_beta_fp64(P):
 
 
 def test_learned_rejection_and_fallback_fp64(P):
-    prob = G.make_problem([10, 9, 11], 3, seed=42, congruence=0.8, rho=0.01, dtype=np.float64)
+    # collinear components (congruence 0.95), noise-free: with the largest
+    # beta the lambda-corrected explicit fit at the first check (sweep 6)
+    # stays below that of sweep 2 (0.9774 against 0.9787)
+    prob = G.make_problem([5, 10, 9], 4, seed=77, congruence=0.95, rho=0.0, dtype=np.float64)
     w = M.constant_weights(M.BETA_MAX).astype(np.float32)
     g, o = _learned(P, prob, 10, w, "fp64")
-    assert o["fallback_sweep"] >= 3
+    assert o["fallback_sweep"] == 3
     assert g["learned_fallback_sweep"] == o["fallback_sweep"]
     assert g["beta"] == o["beta"] and g["beta_sweep"] == o["beta_sweep"]
     assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
@@ -114,7 +119,8 @@ def test_learned_random_mlp_fp32(P):
     float32 problem: same beta to float32 accuracy, fits to float32 parity."""
     rng = np.random.default_rng(13)
     w = (rng.standard_normal(M.PARAMS) * 0.2).astype(np.float32)
-    w[-1] = -2.8      # beta around 1.6e-3
+    w[M.HIDDEN * M.FEATURES + M.HIDDEN:-1] *= 0.01
+    w[-1] = 0.008     # beta around 9e-3
     prob = G.make_problem([30, 26, 34], 5, seed=22, congruence=0.7, rho=0.02, dtype=np.float32)
     g, o = _learned(P, prob, 25, w, "fp32")
     assert abs(g["beta_learned"] - o["beta_learned"]) <= 1e-5 * o["beta_learned"] + 1e-9
@@ -122,3 +128,34 @@ def test_learned_random_mlp_fp32(P):
     for fg, fo in zip(g["fits"], o["fits"]):
         assert abs(fg - fo) <= 1e-6 + 5e-7 / (1 - fo)
     assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-6
+
+
+def test_learned_large_beta_closing_plain_fp64(P):
+    """A large learned beta (3) accepted on the lambda-corrected explicit fit,
+    then the closing plain sweep: same decisions, fits and factors as the
+    oracle."""
+    prob = G.workload("small_o4", dtype=np.float64)
+    w = M.constant_weights(3.0).astype(np.float32)
+    g, o = _learned(P, prob, 14, w, "fp64", closing_plain=True)
+    assert o["fallback_sweep"] == g["learned_fallback_sweep"]
+    assert abs(g["beta_learned"] - o["beta_learned"]) <= 1e-6 * o["beta_learned"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-9
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-9
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-7
+
+
+def test_learned_late_rejection_order4_fp64(P):
+    """Checks at sweeps 6 and 14 pass, the one at the last sweep (16) fails:
+    the checkpoint of sweep 14 (factors, the Q0 halves of sweep 14 and the
+    intermediates live across that boundary of the restructured order-4
+    tree) is restored and sweeps 15-16 run again with the paper's beta."""
+    prob = G.make_problem([7, 8, 5, 5], 4, seed=10, congruence=0.98, rho=0.01, dtype=np.float64)
+    w = M.constant_weights(M.BETA_MAX).astype(np.float32)
+    g, o = _learned(P, prob, 16, w, "fp64")
+    assert o["fallback_sweep"] == 15 and o["beta_sweep"] == 14
+    assert g["learned_fallback_sweep"] == 15
+    assert g["beta"] == o["beta"] and g["beta_sweep"] == o["beta_sweep"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-9
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-7

@@ -59,11 +59,24 @@ def test_adam_first_two_steps_closed_form():
 
 
 def test_constant_weights_round_trip():
-    for beta in [0.0, 5e-5, 2e-3, 0.04]:
+    for beta in [0.0, 5e-5, 2e-3, 0.04, 3.0, 29.0]:
         w = M.constant_weights(beta)
         y = M.forward(w, np.zeros(M.FEATURES))[0]
         assert abs(M.beta_from_output(y) - beta) <= 1e-15 + 1e-12 * beta
-    assert M.beta_from_output(5.0) == M.BETA_MAX
+    assert M.beta_from_output(5.0) == M.BETA_MAX == 30.0
+    assert M.beta_from_output(M.U_MAX) == M.BETA_MAX
+
+
+def test_output_share_is_the_momentum_of_eq19():
+    """The output u maps to beta such that eq. (19), divided by its
+    rescaling 1 + (1 - alpha) beta, is Q0^k + (alpha / (1 - alpha)) u
+    (Q0^k - Q0^{k-1}) at alpha = 0.1."""
+    rng = np.random.default_rng(3)
+    q, qp = rng.standard_normal((6, 3)), rng.standard_normal((6, 3))
+    for u in [0.0, 0.01, 0.3, 0.8, 0.95]:
+        b = M.beta_from_output(u)
+        eq19 = (1 + b) * q - 0.1 * b * qp
+        assert np.allclose(eq19 / (1 + 0.9 * b), q + (0.1 / 0.9) * u * (q - qp), rtol=0, atol=1e-13)
     assert M.beta_from_output(-20.0) == 0.0
 
 
@@ -85,16 +98,22 @@ def test_learned_beta_zero_equals_plain_br():
 
 
 def test_learned_rejection_falls_back_to_paper_beta():
-    """A beta far too large lowers the fit; the sweep is redone with the
-    paper's table value for the previous fit, after which the fit keeps
-    rising."""
-    prob = G.make_problem([10, 9, 11], 3, seed=42, congruence=0.8, rho=0.01, dtype=np.float64)
-    r = O.cp_als_qr(prob.X, 3, prob.init, 10, tree="restructured", extrap="learned",
+    """A beta far too large lowers the fit at the first check; the sweeps
+    since the checkpoint (sweep 2) run again with the paper's table value
+    for the checkpoint's fit, exactly as a run with that beta from sweep 3."""
+    # collinear components (congruence 0.95), noise-free: with the largest
+    # beta the lambda-corrected explicit fit at the first check (sweep 6)
+    # stays below that of sweep 2 (0.9774 against 0.9787)
+    prob = G.make_problem([5, 10, 9], 4, seed=77, congruence=0.95, rho=0.0, dtype=np.float64)
+    r = O.cp_als_qr(prob.X, 4, prob.init, 10, tree="restructured", extrap="learned",
                     mlp_weights=M.constant_weights(M.BETA_MAX))
-    assert r["fallback_sweep"] >= 3
-    k = r["fallback_sweep"]
-    assert r["beta"] == O.beta_from_fit(r["fits"][k - 2])
-    assert np.all(np.diff(r["fits"][k - 2:]) > -1e-12)
+    assert r["fallback_sweep"] == 3 and r["beta_sweep"] == 2
+    assert r["beta"] == O.beta_from_fit(r["fit_accept"])
+    # sweeps 3..10 ran again with the paper's beta: the fit rises throughout
+    assert np.all(np.diff(r["fits"][1:]) > -1e-12)
+    p = O.cp_als_qr(prob.X, 4, prob.init, 10, tree="restructured", extrap="paper",
+                    beta_schedule=[0.0, 0.0] + [r["beta"]] * 8)
+    assert np.array_equal(p["fits"], r["fits"])
 
 
 def test_zero_schedule_equals_plain_br():
@@ -120,3 +139,49 @@ def test_committed_weights_load_and_give_a_beta():
     x = M.features(0.8553, 0.8961, 5, 16, [40] * 5)
     b = M.beta_from_output(M.forward(w, x)[0])
     assert 0.0 <= b <= M.BETA_MAX
+
+
+def test_extrapolation_scales_lambda_at_a_fixed_point():
+    """Eq. (19) at a fixed point: when Q0 of the sweep equals Q0 of the
+    previous sweep, the extrapolated Q0 is (1 + beta - alpha beta) Q0, so
+    lambda grows by that factor while the normalised factors stay put.  This
+    is the factor the learned mode divides out of lambda before it compares
+    fits.  Start from the planted factors of a noise-free tensor (a fixed
+    point of ALS) and apply beta from sweep 2."""
+    prob = G.make_problem([8, 9, 7], 3, seed=5, congruence=0.3, rho=0.0, dtype=np.float64)
+    a = O.cp_als_qr(prob.X, 3, prob.truth, 1, tree="restructured", extrap="off")
+    for beta in [0.5, 3.0, 30.0]:
+        b = O.cp_als_qr(prob.X, 3, prob.truth, 2, tree="restructured", extrap="paper",
+                        fix_beta=beta)
+        assert np.allclose(b["lam"], (1.0 + (1.0 - 0.1) * beta) * a["lam"], rtol=1e-9, atol=0)
+        for u, v in zip(a["factors"], b["factors"]):
+            un = u / np.linalg.norm(u, axis=0)
+            vn = v / np.linalg.norm(v, axis=0)
+            assert np.max(np.abs(un - vn)) <= 1e-9
+
+
+def test_closing_plain_sweep_removes_the_lambda_factor():
+    """With the closing plain sweep the last lambda carries no extrapolation
+    factor: at a fixed point the final explicit fit is the exact one (1 for
+    a noise-free tensor) although every earlier sweep applied beta."""
+    prob = G.make_problem([8, 9, 7], 3, seed=5, congruence=0.3, rho=0.0, dtype=np.float64)
+    r = O.cp_als_qr(prob.X, 3, prob.truth, 6, tree="restructured", extrap="paper",
+                    fix_beta=10.0, closing_plain=True)
+    assert r["fitx"] > 1.0 - 1e-9
+    s = O.cp_als_qr(prob.X, 3, prob.truth, 6, tree="restructured", extrap="paper",
+                    fix_beta=10.0)
+    assert s["fitx"] < 0.0          # lambda 10 times too large
+
+
+def test_learned_checks_double_their_gap():
+    """Checks at sweeps 6 (gap 4), 14 (gap 8) and the last sweep: here the
+    first two pass and the last fails, so the run is the learned beta up to
+    sweep 14 followed by the paper's beta for the fit of sweep 14."""
+    prob = G.make_problem([7, 8, 5, 5], 4, seed=10, congruence=0.98, rho=0.01, dtype=np.float64)
+    r = O.cp_als_qr(prob.X, 4, prob.init, 16, tree="restructured", extrap="learned",
+                    mlp_weights=M.constant_weights(M.BETA_MAX))
+    assert r["fallback_sweep"] == 15 and r["beta_sweep"] == 14
+    b = r["beta_learned"]
+    p = O.cp_als_qr(prob.X, 4, prob.init, 16, tree="restructured", extrap="paper",
+                    beta_schedule=[0.0, 0.0] + [b] * 12 + [r["beta"]] * 2)
+    assert np.array_equal(p["fits"], r["fits"])
