@@ -814,6 +814,9 @@ cpqr_status cpqr_check_args(const cpqr_tensor* X, int rank, const cpqr_options* 
 
 namespace {
 
+cpqr_status checkpoint_shadows(cpqr_session* S, int c, std::vector<CopySeg>* save,
+                               std::vector<CopySeg>* restore);
+
 // Creates the device state of one decomposition (workspace names prefixed by
 // `prefix`), computes ||X||^2 and the QRs of the initial factors.
 cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpqr_options* o,
@@ -895,6 +898,12 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
     WS(h, prefix + "mlp_w", CPQR_MLP_PARAMS * sizeof(float), S.mlp_w);
     WS(h, prefix + "mlp_io", (CPQR_MLP_FEATURES + 1) * sizeof(float), S.mlp_io);
     HIP_TRY(h, hipMemcpy(S.mlp_w, o->mlp_weights, CPQR_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+    // the checkpoint copies for every boundary the checks can fall on, so
+    // that no sweep allocates
+    for (int c = 2; c < o->iters; ++c) {
+      stt = checkpoint_shadows(&S, c, nullptr, nullptr);
+      if (stt != CPQR_OK) return stt;
+    }
   }
   HIP_TRY(h, hipEventCreate(&S.t0));
   HIP_TRY(h, hipEventCreate(&S.t1));
@@ -1118,23 +1127,31 @@ cpqr_status run_sweep(cpqr_session* S, int k, bool capture_only = false) {
 // extrapolation: everything sweeps c+1, c+2, ... read before they write it,
 // that is the carried buffers, the Q0 half of sweep c of every mode (Q0^{k-1}
 // of sweep c+1) with its compact-form metadata, and the intermediates live
-// across the boundary.  save: live -> copy; otherwise copy -> live.  One
-// launch per COPY_LIST_MAX buffers, on the library's stream.
-cpqr_status checkpoint(cpqr_session* S, int c, bool save) {
-  cpqr_handle* h = S->h;
+// across the boundary.
+cpqr_status checkpoint_bufs(cpqr_session* S, int c, std::vector<std::pair<void*, size_t>>* bufs) {
   Problem& p = S->p;
-  std::vector<std::pair<void*, size_t>> bufs(p.carried);
+  *bufs = p.carried;
   const size_t mw = (size_t)p.R * p.R + 2 * p.R;
   for (int n = 0; n < p.N; ++n) {
-    bufs.push_back({p.q0buf[n] + (size_t)(c % 2) * p.M * p.R, (size_t)p.M * p.R * 8});
-    if (p.q0meta[n]) bufs.push_back({p.q0meta[n] + (size_t)(c % 2) * mw, mw * 8});
+    bufs->push_back({p.q0buf[n] + (size_t)(c % 2) * p.M * p.R, (size_t)p.M * p.R * 8});
+    if (p.q0meta[n]) bufs->push_back({p.q0meta[n] + (size_t)(c % 2) * mw, mw * 8});
   }
   for (uint32_t m : live_intermediates(p.N, S->sched, c)) {
     auto it = p.inter.find(m);
-    if (it == p.inter.end()) return fail(h, CPQR_EINVAL, "checkpoint: intermediate %u not allocated", m);
-    bufs.push_back({it->second, (size_t)inter_elems(p, m) * p.elem});
+    if (it == p.inter.end()) return fail(S->h, CPQR_EINVAL, "checkpoint: intermediate %u not allocated", m);
+    bufs->push_back({it->second, (size_t)inter_elems(p, m) * p.elem});
   }
-  std::vector<CopySeg> segs;
+  return CPQR_OK;
+}
+
+// The copy of every buffer of the checkpoint after sweep c (allocated once).
+cpqr_status checkpoint_shadows(cpqr_session* S, int c, std::vector<CopySeg>* save,
+                               std::vector<CopySeg>* restore) {
+  cpqr_handle* h = S->h;
+  Problem& p = S->p;
+  std::vector<std::pair<void*, size_t>> bufs;
+  cpqr_status st = checkpoint_bufs(S, c, &bufs);
+  if (st != CPQR_OK) return st;
   for (const auto& b : bufs) {
     auto it = p.shadow.find(b.first);
     if (it == p.shadow.end()) {
@@ -1142,12 +1159,19 @@ cpqr_status checkpoint(cpqr_session* S, int c, bool save) {
       WS(h, p.prefix + "ckpt" + std::to_string(p.shadow.size()), b.second, sh);
       it = p.shadow.emplace(b.first, sh).first;
     }
-    if (save)
-      segs.push_back(CopySeg{b.first, it->second, (int64_t)b.second});
-    else
-      segs.push_back(CopySeg{it->second, b.first, (int64_t)b.second});
+    if (save) save->push_back(CopySeg{b.first, it->second, (int64_t)b.second});
+    if (restore) restore->push_back(CopySeg{it->second, b.first, (int64_t)b.second});
   }
-  HIP_TRY(h, launch_copy_list(segs.data(), (int)segs.size(), h->stream));
+  return CPQR_OK;
+}
+
+// Saves (save) or restores the checkpoint after sweep c: one launch per
+// COPY_LIST_MAX buffers, on the library's stream.
+cpqr_status checkpoint(cpqr_session* S, int c, bool save) {
+  std::vector<CopySeg> segs;
+  cpqr_status st = checkpoint_shadows(S, c, save ? &segs : nullptr, save ? nullptr : &segs);
+  if (st != CPQR_OK) return st;
+  HIP_TRY(S->h, launch_copy_list(segs.data(), (int)segs.size(), S->h->stream));
   return CPQR_OK;
 }
 
