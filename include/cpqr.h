@@ -312,6 +312,36 @@ cpqr_status cpqr_schedule(int order, int tree, int sweeps, int *orders_out,
                           double *flops_out);
 
 /*
+ * Tuned TTM launch shapes (not in the paper: an autotuner of this library).
+ * The first session or batch that meets a float32 TTM shape times its launch
+ * shapes (K split 1/2/4 waves per 64-row output tile, 1 or 2 workgroups per
+ * CU) and keeps the fastest in the handle and in a JSON file:
+ *   {"format": 1, "device": "<gcnArchName>:<CUs>",
+ *    "entries": {"<key>": [ks, wpc], ...}}
+ * at $CPQR_TUNE_CACHE, else $XDG_CACHE_HOME/cpqr/ttm_tune.json, else
+ * $HOME/.cache/cpqr/ttm_tune.json; CPQR_TUNE_CACHE=off keeps the results in
+ * memory.  Entries for another device signature are ignored.
+ *
+ * cpqr_tune_cache_check -- host-only: parses the text of such a file.
+ *  text    : host, NUL-terminated file contents.
+ *  device  : host, NUL-terminated device signature ("gfx950:256").
+ *  entries : host, receives the number of entries valid for `device` (0 when
+ *            the file was written for another device), or NULL.
+ * Returns CPQR_OK for a well-formed file, CPQR_EINVAL otherwise (null text or
+ * device, syntax errors, unknown fields, shapes outside the candidates).
+ */
+cpqr_status cpqr_tune_cache_check(const char *text, const char *device, int *entries);
+
+/*
+ * cpqr_tune_cache_path -- the file the handle's tuning results go to
+ * (empty when persistence is off) and the handle's device signature.
+ *  path, device : host buffers of `cap` bytes each (NUL-terminated, truncated
+ *                 to fit); either may be NULL.
+ * Returns CPQR_EINVAL for a null handle.
+ */
+cpqr_status cpqr_tune_cache_path(cpqr_handle *handle, char *path, char *device, int cap);
+
+/*
  * cpqr_ttm -- one mode-m product Y = X x_m Q^T (Section 2.1): the tensor
  * `in` (device, dims[0..order-1], column-major) is contracted on mode `mode`
  * (0-based) with Q (device, dims[mode] x R column-major, same precision as

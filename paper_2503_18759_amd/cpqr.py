@@ -75,7 +75,8 @@ EXPORTS = ["cpqr_create", "cpqr_destroy", "cpqr_last_error", "cpqr_status_string
            "cpqr_check_args", "cpqr_als_qr", "cpqr_session_create", "cpqr_session_sweeps",
            "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy",
            "cpqr_schedule", "cpqr_ttm", "cpqr_qr", "cpqr_als_qr_batched",
-           "cpqr_mlp_forward", "cpqr_mlp_grad", "cpqr_mlp_train", "cpqr_qr_noalloc"]
+           "cpqr_mlp_forward", "cpqr_mlp_grad", "cpqr_mlp_train", "cpqr_qr_noalloc",
+           "cpqr_tune_cache_check", "cpqr_tune_cache_path"]
 
 _lib = None
 
@@ -120,9 +121,12 @@ def load_library(path: str = LIB_PATH):
     L.cpqr_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
     L.cpqr_mlp_grad.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     L.cpqr_mlp_train.argtypes = [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, ctypes.c_uint64, vp]
+    L.cpqr_tune_cache_check.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(i32)]
+    L.cpqr_tune_cache_path.argtypes = [vp, ctypes.c_char_p, ctypes.c_char_p, i32]
     for f in ("cpqr_create", "cpqr_destroy", "cpqr_check_args", "cpqr_als_qr", "cpqr_schedule",
               "cpqr_ttm", "cpqr_qr", "cpqr_qr_noalloc", "cpqr_session_create", "cpqr_session_sweeps",
-              "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy"):
+              "cpqr_session_sync", "cpqr_session_result", "cpqr_session_destroy",
+              "cpqr_tune_cache_check", "cpqr_tune_cache_path"):
         getattr(L, f).restype = i32
     _lib = L
     return L
@@ -545,6 +549,28 @@ def schedule(order: int, tree: str, sweeps: int) -> Tuple[List[List[int]], List[
             modes = tuple(k for k in range(order) if mask >> k & 1)
             poly[(modes, order - len(modes) + 1)] = int(c)
     return ords, stp, poly
+
+
+# ------------------------------------------------------------------ tuning table
+def tune_cache_check(text: str, device: str) -> int:
+    """Host-only: number of entries for `device` in the text of a TTM tuning
+    file (include/cpqr.h); raises CpqrError for a malformed file."""
+    L = load_library()
+    n = ctypes.c_int(0)
+    st = L.cpqr_tune_cache_check(text.encode(), device.encode(), ctypes.byref(n))
+    if st != OK:
+        raise CpqrError(st, "malformed tuning file")
+    return n.value
+
+
+def tune_cache_path(handle: Optional[Handle] = None) -> Tuple[str, str]:
+    """(file the handle's TTM tuning results go to, '' when off; device signature)."""
+    L = load_library()
+    h = handle or default_handle()
+    path = ctypes.create_string_buffer(4096)
+    dev = ctypes.create_string_buffer(4096)
+    h.check(L.cpqr_tune_cache_path(h._h, path, dev, 4096))
+    return path.value.decode(), dev.value.decode()
 
 
 # ------------------------------------------------------------------ MLP

@@ -30,10 +30,11 @@ bool ttm_mfma_supported(int I, int R);
 // ev0/ev1 (optional): events stamped with the kernel's own start and end
 // (hipExtLaunchKernel), used to time single TTM launches.  ks: waves per
 // output tile (K split 1, 2 or 4); 0, or a split this shape cannot use,
-// takes the launcher's own choice.
+// takes the launcher's own choice.  wpc: workgroups per CU of the persistent
+// grid (1 or 2; 0: the default, 2).
 hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L, int I, int64_t S,
                           int R, bool bf16x3, hipStream_t st, hipEvent_t ev0 = nullptr,
-                          hipEvent_t ev1 = nullptr, int ks = 0);
+                          hipEvent_t ev1 = nullptr, int ks = 0, int wpc = 0);
 // K splits a float32 MFMA TTM of this shape can use (bit k set: split 1 << k).
 unsigned ttm_ks_options(int64_t L, int I, int64_t S, int R);
 hipError_t launch_ttm_f64(const double* in, const double* Q, double* out, int64_t L, int I,
@@ -64,8 +65,9 @@ struct TtmBatch {
 };
 // Host helper for building a TtmBatch: workgroups and LDS bytes for one
 // problem of `rows` output rows at K split `ks` (0: the launcher's own
-// choice, returned in *ks).  False if that split does not fit.
-bool ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds);
+// choice, returned in *ks) and `wpc` workgroups per CU (0: default).  False
+// if that split does not fit.
+bool ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds, int wpc = 0);
 hipError_t launch_ttm_f32_batched(const TtmBatch& b, hipStream_t st);
 bool ttm_vec_legal(const TtmArgs& a);   // 16-byte loads (and stores) legal for this problem
 bool ttm_buf_legal(const TtmArgs& a);   // input addressable through a buffer resource

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -25,6 +26,7 @@
 #include "kernels.h"
 #include "mlp.h"
 #include "schedule.h"
+#include "tune_cache.h"
 
 using namespace cpqr;
 
@@ -48,8 +50,9 @@ struct cpqr_handle {
   std::string err;
   std::map<std::string, DevBuf> bufs;
   bool busy = false;                  // a session is using the workspace
-  // tuned K split of float32 TTMs by shape (L, I, S, R, precision)
-  std::map<std::tuple<int64_t, int, int64_t, int, int>, int> ttm_ks;
+  // tuned launch shapes of float32 TTMs (in memory, and in the JSON file
+  // of tune_cache.h), created at the first tuning
+  std::unique_ptr<TuneCache> tune;
 };
 
 namespace {
@@ -164,7 +167,7 @@ struct Problem {
   StairPlan stair{};      // staircase Z_n QR (ok == false: dense TSQR)
   ZcolPlan zcol{};        // column-distributed staircase Z_n QR, compact Q0 (preferred)
   int* smap = nullptr;    // staircase row table of zqr_col (M x 2 ints)
-  std::map<uint32_t, int> ttm_ks;    // TTM step (src | mode << 16) -> K split (0: default)
+  std::map<uint32_t, TtmShape> ttm_ks;   // TTM step (src | mode << 16) -> launch shape
   int nchunks_max = 0;
   int Imax = 0;
   // device pointers
@@ -361,18 +364,29 @@ hipError_t launch_ttm_step(const Problem& p, const Step& st, hipStream_t s, hipE
     return launch_ttm_f64((const double*)a.in, (const double*)a.Q, (double*)a.out, a.L, a.I, a.S, a.R, s,
                           ev0, ev1);
   const auto k = p.ttm_ks.find(st.src | ((uint32_t)st.mode << 16));
-  return launch_ttm_f32(a.in, a.Q, a.out, a.L, a.I, a.S, a.R, p.prec == CPQR_PREC_BF16X3, s, ev0, ev1,
-                        k == p.ttm_ks.end() ? 0 : k->second);
+  const TtmShape sh = k == p.ttm_ks.end() ? TtmShape{} : k->second;
+  return launch_ttm_f32(a.in, a.Q, a.out, a.L, a.I, a.S, a.R, p.prec == CPQR_PREC_BF16X3, s, ev0, ev1, sh.ks,
+                        sh.wpc);
 }
 
-// K split (waves per output tile) of every float32 TTM step of the schedule:
-// each shape is timed once per handle (one warm-up and three launches per
-// candidate, output redirected to scratch so that no cached intermediate is
-// touched) and the fastest split is kept.  The best split depends on the
-// shape and on the memory system, so it is measured rather than assumed.
+// Launch shape of every float32 TTM step of the schedule: the K split
+// (waves per output tile: 1, 2 or 4, as the shape allows) and the
+// workgroups per CU of the persistent grid (1 or 2).  Each shape is timed once
+// (one warm-up and three launches per candidate, output redirected to scratch
+// so that no cached intermediate is touched) and the fastest is kept in the
+// handle's table, which tune_cache.h also keeps on disk, so that later
+// processes on the same kind of device skip the timing.  The best shape
+// depends on the shape and on the memory system, so it is measured rather
+// than assumed.
+TuneCache& handle_tune(cpqr_handle* h) {
+  if (!h->tune) h->tune.reset(new TuneCache(h->device));
+  return *h->tune;
+}
+
 cpqr_status tune_ttm_steps(cpqr_handle* h, Problem& p, const std::vector<std::vector<Step>>& sched) {
   if (p.f64) return CPQR_OK;
   hipStream_t s = h->stream;
+  TuneCache& tc = handle_tune(h);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   for (const auto& sw : sched)
     for (const Step& st : sw) {
@@ -380,45 +394,49 @@ cpqr_status tune_ttm_steps(cpqr_handle* h, Problem& p, const std::vector<std::ve
       const uint32_t key = st.src | ((uint32_t)st.mode << 16);
       if (p.ttm_ks.count(key)) continue;
       const TtmArgs a = ttm_step_args(p, st);
-      const auto shape = std::make_tuple(a.L, a.I, a.S, a.R, p.prec);
-      const auto known = h->ttm_ks.find(shape);
-      if (known != h->ttm_ks.end()) {
-        p.ttm_ks[key] = known->second;
+      const std::string name = ttm_key_single(p.prec, a.L, a.I, a.S, a.R);
+      TtmShape best;
+      if (tc.find(name, &best)) {
+        p.ttm_ks[key] = best;
         continue;
       }
       const unsigned opts = ttm_ks_options(a.L, a.I, a.S, a.R);
-      int best = 0;
-      if (opts & (opts - 1)) {   // more than one candidate
-        float* out = nullptr;
-        WS(h, "tune:ttm_out", (size_t)(a.L * a.S * a.R) * 4 + 256, out);
-        if (!e0) {
-          HIP_TRY(h, hipEventCreate(&e0));
-          HIP_TRY(h, hipEventCreate(&e1));
-        }
-        float best_ms = 1e30f;
-        for (int b = 0; b < 3; ++b) {
-          if (!(opts & (1u << b))) continue;
+      if (opts == 0) {   // not an MFMA shape: the launcher decides
+        p.ttm_ks[key] = TtmShape{};
+        continue;
+      }
+      float* out = nullptr;
+      WS(h, "tune:ttm_out", (size_t)(a.L * a.S * a.R) * 4 + 256, out);
+      if (!e0) {
+        HIP_TRY(h, hipEventCreate(&e0));
+        HIP_TRY(h, hipEventCreate(&e1));
+      }
+      float best_ms = 1e30f;
+      const bool bf = p.prec == CPQR_PREC_BF16X3;
+      for (int b = 0; b < 3; ++b) {
+        if (!(opts & (1u << b))) continue;
+        for (int wpc = 1; wpc <= 2; ++wpc) {
           const int ks = 1 << b;
-          const bool bf = p.prec == CPQR_PREC_BF16X3;
-          HIP_TRY(h, launch_ttm_f32(a.in, a.Q, out, a.L, a.I, a.S, a.R, bf, s, nullptr, nullptr, ks));
+          HIP_TRY(h, launch_ttm_f32(a.in, a.Q, out, a.L, a.I, a.S, a.R, bf, s, nullptr, nullptr, ks, wpc));
           HIP_TRY(h, hipEventRecord(e0, s));
           for (int r = 0; r < 3; ++r)
-            HIP_TRY(h, launch_ttm_f32(a.in, a.Q, out, a.L, a.I, a.S, a.R, bf, s, nullptr, nullptr, ks));
+            HIP_TRY(h, launch_ttm_f32(a.in, a.Q, out, a.L, a.I, a.S, a.R, bf, s, nullptr, nullptr, ks, wpc));
           HIP_TRY(h, hipEventRecord(e1, s));
           HIP_TRY(h, hipEventSynchronize(e1));
           float ms = 0.f;
           HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
           if (ms < best_ms) {
             best_ms = ms;
-            best = ks;
+            best = TtmShape{ks, wpc};
           }
         }
       }
-      h->ttm_ks[shape] = best;
+      tc.put(name, best);
       p.ttm_ks[key] = best;
     }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  tc.save();
   return CPQR_OK;
 }
 
@@ -1356,6 +1374,30 @@ cpqr_status cpqr_session_sweeps(cpqr_session* S, int nsweeps) {
   return CPQR_OK;
 }
 
+cpqr_status cpqr_tune_cache_check(const char* text, const char* device, int* entries) {
+  if (!text || !device) return CPQR_EINVAL;
+  std::map<std::string, TtmShape> e;
+  if (!tune_cache_parse(text, device, &e)) return CPQR_EINVAL;
+  if (entries) *entries = (int)e.size();
+  return CPQR_OK;
+}
+
+cpqr_status cpqr_tune_cache_path(cpqr_handle* h, char* path, char* device, int cap) {
+  if (!h) return CPQR_EINVAL;
+  if (cap <= 0) return CPQR_OK;
+  HIP_TRY(h, hipSetDevice(h->device));
+  TuneCache& tc = handle_tune(h);
+  auto put = [cap](char* dst, const std::string& v) {
+    if (!dst) return;
+    const size_t n = std::min(v.size(), (size_t)cap - 1);
+    std::memcpy(dst, v.data(), n);
+    dst[n] = '\0';
+  };
+  put(path, tc.path());
+  put(device, tc.device());
+  return CPQR_OK;
+}
+
 cpqr_status cpqr_session_sync(cpqr_session* S) {
   if (!S) return CPQR_EINVAL;
   cpqr_handle* h = S->h;
@@ -1521,7 +1563,6 @@ struct BatchRun {
   std::vector<cpqr_session*> S;
   std::map<std::string, hipGraphExec_t> graphs;
   std::vector<hipEvent_t> fork_evs;   // fork/join events of the captured sweeps
-  std::map<std::string, int> tuned_ks;
   ~BatchRun() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
     for (hipEvent_t e : fork_evs) (void)hipEventDestroy(e);
@@ -1537,15 +1578,16 @@ size_t blob_put(std::vector<char>& blob, const std::vector<T>& v) {
   return off;
 }
 
-// TTM launch shape of a group at K split ks; false if some member cannot use it.
-bool ttm_group_shape(const std::vector<TtmArgs>& args, int ks, unsigned* wgs, size_t* lds) {
+// TTM launch shape of a group at K split ks and wpc workgroups per CU; false
+// if some member cannot use it.
+bool ttm_group_shape(const std::vector<TtmArgs>& args, int ks, int wpc, unsigned* wgs, size_t* lds) {
   *wgs = 1;
   *lds = 0;
   for (const TtmArgs& a : args) {
     int k = ks;
     unsigned w = 0;
     size_t l = 0;
-    if (!ttm_batch_shape(a.L == 1 ? a.S : a.L * a.S, a.I, a.R, &k, &w, &l)) return false;
+    if (!ttm_batch_shape(a.L == 1 ? a.S : a.L * a.S, a.I, a.R, &k, &w, &l, wpc)) return false;
     if (w > *wgs) *wgs = w;
     if (l > *lds) *lds = l;
   }
@@ -1578,18 +1620,21 @@ void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpq
           vec = vec && ttm_vec_legal(args.back());
           buf = buf && ttm_buf_legal(args.back());
         }
-        it.tune_sig = std::to_string(st.src) + "/" + std::to_string(st.mode) + "/" + std::to_string(g.first);
+        std::vector<std::array<int64_t, 4>> shapes;
+        for (const TtmArgs& a : args) shapes.push_back({a.L, (int64_t)a.I, a.S, (int64_t)a.R});
+        it.tune_sig = ttm_key_batch(o->prec, g.first, args[0].L == 1, shapes);
         it.tb.count = (int)args.size();
         it.tb.kc = args[0].L == 1;
         it.tb.vec = vec;
         it.tb.bf16x3 = bf;
         it.tb.buf = buf;
         it.tb.nb = g.first;
-        auto tk = B.tuned_ks.find(it.tune_sig);
-        it.tb.ks = tk != B.tuned_ks.end() ? tk->second : 1;
-        if (!ttm_group_shape(args, it.tb.ks, &it.tb.wgs, &it.tb.lds)) {
+        TtmShape sh{1, 0};
+        (void)handle_tune(B.h).find(it.tune_sig, &sh);
+        it.tb.ks = sh.ks;
+        if (!ttm_group_shape(args, it.tb.ks, sh.wpc, &it.tb.wgs, &it.tb.lds)) {
           it.tb.ks = 1;
-          ttm_group_shape(args, 1, &it.tb.wgs, &it.tb.lds);
+          ttm_group_shape(args, 1, 0, &it.tb.wgs, &it.tb.lds);
         }
         it.off[0] = blob_put(*blob, args);
         ttm_host->push_back(args);
@@ -1721,18 +1766,28 @@ hipError_t launch_item(const BatchItem& it, const char* base, hipStream_t s) {
   }
 }
 
-// Autotuner: for every TTM group not tuned yet, times the K splits that fit
-// (1, 2, 4 waves per tile) with outputs redirected to scratch memory, so that
-// no cached intermediate is disturbed, and keeps the fastest.
+// Autotuner: for every TTM group not tuned yet, times the launch shapes that
+// fit (K split 1, 2 or 4 waves per tile; 1 or 2 workgroups per CU) with
+// outputs redirected to scratch memory, so that no cached intermediate is
+// disturbed, and keeps the fastest (in the handle's table and its file).
 cpqr_status tune_ttm(BatchRun& B, std::vector<BatchItem>& items,
                      const std::vector<std::vector<TtmArgs>>& ttm_host) {
   cpqr_handle* h = B.h;
   hipStream_t s = h->stream;
+  TuneCache& tc = handle_tune(h);
   size_t ti = 0;
   for (BatchItem& it : items) {
     if (it.kind != 0) continue;
     const std::vector<TtmArgs>& args = ttm_host[ti++];
-    if (B.tuned_ks.count(it.tune_sig)) continue;
+    TtmShape known;
+    if (tc.find(it.tune_sig, &known)) {
+      it.tb.ks = known.ks;
+      if (!ttm_group_shape(args, known.ks, known.wpc, &it.tb.wgs, &it.tb.lds)) {
+        it.tb.ks = 1;
+        ttm_group_shape(args, 1, 0, &it.tb.wgs, &it.tb.lds);
+      }
+      continue;
+    }
     std::vector<TtmArgs> scratch = args;
     size_t total = 0;
     for (const TtmArgs& a : args) total += (size_t)(a.L * a.S * a.R) * 4 + 256;
@@ -1749,31 +1804,33 @@ cpqr_status tune_ttm(BatchRun& B, std::vector<BatchItem>& items,
     hipEvent_t e0, e1;
     HIP_TRY(h, hipEventCreate(&e0));
     HIP_TRY(h, hipEventCreate(&e1));
-    int best = 1;
+    TtmShape best{1, 0};
     float best_ms = 1e30f;
-    for (int ks : {1, 2, 4}) {
-      TtmBatch b = it.tb;
-      b.ks = ks;
-      if (!ttm_group_shape(args, ks, &b.wgs, &b.lds)) continue;
-      b.args = dargs;
-      HIP_TRY(h, launch_ttm_f32_batched(b, s));
-      HIP_TRY(h, hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) HIP_TRY(h, launch_ttm_f32_batched(b, s));
-      HIP_TRY(h, hipEventRecord(e1, s));
-      HIP_TRY(h, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = ks;
+    for (int ks : {1, 2, 4})
+      for (int wpc = 1; wpc <= 2; ++wpc) {
+        TtmBatch b = it.tb;
+        b.ks = ks;
+        if (!ttm_group_shape(args, ks, wpc, &b.wgs, &b.lds)) continue;
+        b.args = dargs;
+        HIP_TRY(h, launch_ttm_f32_batched(b, s));
+        HIP_TRY(h, hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) HIP_TRY(h, launch_ttm_f32_batched(b, s));
+        HIP_TRY(h, hipEventRecord(e1, s));
+        HIP_TRY(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = TtmShape{ks, wpc};
+        }
       }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    B.tuned_ks[it.tune_sig] = best;
-    it.tb.ks = best;
-    ttm_group_shape(args, best, &it.tb.wgs, &it.tb.lds);
+    tc.put(it.tune_sig, best);
+    it.tb.ks = best.ks;
+    ttm_group_shape(args, best.ks, best.wpc, &it.tb.wgs, &it.tb.lds);
   }
+  tc.save();
   return CPQR_OK;
 }
 

@@ -828,10 +828,10 @@ static int ttm_pick_ks(int64_t tiles, int I, int NB) {
   return ks;
 }
 
-static dim3 ttm_grid(int64_t tiles, int ks) {
+static dim3 ttm_grid(int64_t tiles, int ks, int wpc) {
   const int tpw = 4 / ks;
   int64_t wgs = (tiles + tpw - 1) / tpw;
-  const int64_t cap = (int64_t)device_cu_count() * TTM_WG_PER_CU;
+  const int64_t cap = (int64_t)device_cu_count() * (wpc > 0 ? wpc : TTM_WG_PER_CU);
   if (wgs > cap) wgs = cap;
   return dim3((unsigned)(wgs > 0 ? wgs : 1));
 }
@@ -895,14 +895,14 @@ static bool ttm_vec_ok(const TtmArgs& a) {
 bool ttm_vec_legal(const TtmArgs& a) { return ttm_vec_ok(a); }
 bool ttm_buf_legal(const TtmArgs& a) { return a.L * (int64_t)a.I * a.S * 4 < TTM_BUF_LIMIT - 64; }
 
-bool ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds) {
+bool ttm_batch_shape(int64_t rows, int I, int R, int* ks, unsigned* wgs, size_t* lds, int wpc) {
   const int NB = (R + 15) / 16;
   const int64_t tiles = (rows + TTM_TILE - 1) / TTM_TILE;
   if (*ks <= 0) *ks = ttm_pick_ks(tiles, I, NB);
   if (*ks != 1 && *ks != 2 && *ks != 4) return false;
   *lds = ttm_q_lds(I, NB) + ttm_red_lds(*ks, NB);
   if (*lds > 64 * 1024 || (I + 31) / 32 < *ks) return false;
-  *wgs = ttm_grid(tiles, *ks).x;
+  *wgs = ttm_grid(tiles, *ks, wpc).x;
   return true;
 }
 
@@ -934,7 +934,8 @@ unsigned ttm_ks_options(int64_t L, int I, int64_t S, int R) {
 }
 
 hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L, int I, int64_t S,
-                          int R, bool bf16x3, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int ks_req) {
+                          int R, bool bf16x3, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, int ks_req,
+                          int wpc) {
   if (L * S == 0) return hipSuccess;
   if (!ttm_mfma_supported(I, R)) {
     if (bf16x3) return hipErrorInvalidValue;
@@ -958,7 +959,7 @@ hipError_t launch_ttm_f32(const float* in, const float* Q, float* out, int64_t L
     if (ttm_batch_shape(rows, I, R, &k, &wgs, &lds)) ks = ks_req;
   }
   const bool buf = ttm_buf_legal(a);
-  return launch_f32_any(NB, buf, L == 1, ttm_vec_ok(a), bf16x3, ttm_grid(tiles, ks),
+  return launch_f32_any(NB, buf, L == 1, ttm_vec_ok(a), bf16x3, ttm_grid(tiles, ks, wpc),
                         ttm_q_lds(I, NB) + ttm_red_lds(ks, NB), st, a, nullptr, ks, ev0, ev1);
 }
 

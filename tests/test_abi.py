@@ -125,3 +125,24 @@ def test_python_layer_fails_loudly_without_library(tmp_path):
             C.load_library(str(tmp_path / "missing.so"))
         finally:
             C._lib = C._lib_saved
+
+
+def test_tune_cache_file_format():
+    """The TTM tuning file (include/cpqr.h): entries for the matching device,
+    none for another, and malformed files rejected."""
+    import paper_2503_18759_amd as P
+    P.load_library()
+    good = ('{"format": 1, "device": "gfx950:256",\n "entries": {\n'
+            '  "ttm/p1/L1/I256/S65536/R32": [1, 2],\n  "ttmb/p1/nb1/kc/5/0123456789abcdef": [4, 1]\n }\n}\n')
+    assert P.tune_cache_check(good, "gfx950:256") == 2
+    assert P.tune_cache_check(good, "gfx942:304") == 0
+    assert P.tune_cache_check('{"format": 1, "device": "x", "entries": {}}', "x") == 0
+    bad = [good.replace("[1, 2]", "[3, 2]"),          # K split outside 1/2/4
+           good.replace("[1, 2]", "[1, 5]"),          # workgroups per CU outside 0..2
+           good.replace('"format": 1', '"format": 2'),
+           good.replace('"device": "gfx950:256",', ""),
+           good.replace("[4, 1]", "[4 1]"),
+           good[:-3], "", "[]", '{"format": 1, "device": "x", "other": 1}']
+    for b in bad:
+        with pytest.raises(P.CpqrError):
+            P.tune_cache_check(b, "gfx950:256")
