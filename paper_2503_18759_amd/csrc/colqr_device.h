@@ -188,6 +188,186 @@ __device__ __forceinline__ void col_qr(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)]
 }
 
 
+// col_qr for a dense block, two columns per step.  Columns j and j + 1 (j
+// even) belong to the same wave (CPW is even).  Before the step's barrier
+// that wave alone forms reflector j from its column j, applies it to column
+// j + 1, forms reflector j + 1 (two reductions over its own lanes) and
+// publishes both columns with their scalars and v_j^T v_{j+1}.  After the
+// barrier every wave applies H_{j+1} H_j to its later columns in the compact
+// WY form: with s1 = v_j^T a and s2 = v_{j+1}^T a (one reduction of 2 CPW
+// values), a -= v_j (tau_j s1) + v_{j+1} tau_{j+1} (s2 - (v_j^T v_{j+1}) tau_j s1);
+// waves with finished columns form their entries of U from the same dot
+// products.  Half as many barriers, broadcasts and reductions as col_qr;
+// the reflector convention, storage, tau, beta, scale and U on return are
+// those of col_qr (the reflectors are the same up to rounding).  xp holds
+// two double-buffered pairs of published columns.
+template <int RMAX, int RPL, int NW>
+__device__ __forceinline__ void col_qr_pair(double (&a)[RPL][(ColCfg<RMAX, NW>::CPW)], int R,
+                                            double (*xp)[2][64 * RPL], QrSmem<RMAX>& sm) {
+  constexpr int CPW = ColCfg<RMAX, NW>::CPW;
+  static_assert(CPW % 2 == 0, "pairs of columns must lie in one wave");
+  constexpr int NP = CPW / 2;
+  constexpr int NV2 = 2 * CPW <= 2 ? 2 : (2 * CPW <= 4 ? 4 : (2 * CPW <= 8 ? 8 : 16));
+  constexpr int G2 = 64 / NV2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the owner's work for pair (j, j + 1): local columns QA = 2 PP, QB = QA + 1
+  auto prework = [&](auto ppc, int j, int buf) __attribute__((always_inline)) {
+    constexpr int QA = 2 * decltype(ppc)::value, QB = QA + 1;
+    const int j1 = j + 1;
+    double d[2] = {0.0, 0.0};
+    static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p = decltype(pc)::value;
+      const double xv = (p > 0 || lane > j) ? a[p][QA] : 0.0;
+      d[0] = fma(xv, xv, d[0]);
+      d[1] = fma(xv, a[p][QB], d[1]);
+    });
+    wave_transpose_reduce<2>(d);
+    double tau1, beta1, scale1;
+    qr_reflector_scalars(lane_read(a[0][QA], j), lane_read(d[0], 0), &tau1, &beta1, &scale1);
+    // column j + 1 <- H_j column j + 1
+    const double w1y = fma(scale1, lane_read(d[0], 32), lane_read(a[0][QB], j));
+    const double ts1 = tau1 * scale1;
+    static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p = decltype(pc)::value;
+      const double coef = (p > 0 || lane > j) ? ts1 * a[p][QA] : ((lane == j) ? tau1 : 0.0);
+      a[p][QB] = fma(-coef, w1y, a[p][QB]);
+    });
+    double tau2 = 0.0, beta2 = 0.0, scale2 = 0.0, w12 = 0.0;
+    if (j1 < R) {
+      double e[2] = {0.0, 0.0};
+      static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        const bool below = p > 0 || lane > j1;
+        const double yv = below ? a[p][QB] : 0.0;
+        e[0] = fma(yv, yv, e[0]);
+        e[1] = fma(below ? a[p][QA] : 0.0, yv, e[1]);
+      });
+      wave_transpose_reduce<2>(e);
+      qr_reflector_scalars(lane_read(a[0][QB], j1), lane_read(e[0], 0), &tau2, &beta2, &scale2);
+      // v_j^T v_{j+1} without the scale of column j (applied with the other U entries)
+      w12 = fma(scale2, lane_read(e[0], 32), lane_read(a[0][QA], j1));
+    }
+    static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p = decltype(pc)::value;
+      xp[buf][0][lane + 64 * p] = a[p][QA];
+      xp[buf][1][lane + 64 * p] = a[p][QB];
+    });
+    if (lane == 0) {
+      sm.tau[j] = tau1;
+      sm.beta[j] = beta1;
+      sm.scale[j] = scale1;
+      if (j1 < R) {
+        sm.tau[j1] = tau2;
+        sm.beta[j1] = beta2;
+        sm.scale[j1] = scale2;
+        sm.U[j][j1] = w12;
+      }
+    }
+  };
+  if (wave == 0) prework(std::integral_constant<int, 0>{}, 0, 0);
+  __syncthreads();
+  for (int jb = 0; jb * CPW < R; ++jb) {
+    static_for<0, NP>([&](auto ppc) __attribute__((always_inline)) {
+      constexpr int PP = decltype(ppc)::value;
+      const int j = jb * CPW + 2 * PP;
+      if (j >= R) return;
+      const int j1 = j + 1;
+      const int buf = (j >> 1) & 1;
+      const bool two = j1 < R;
+      double x[RPL], y[RPL];
+      static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        const double xv = xp[buf][0][lane + 64 * p], yv = xp[buf][1][lane + 64 * p];
+        x[p] = (p > 0 || lane > j) ? xv : 0.0;
+        y[p] = (p > 0 || lane > j1) ? yv : 0.0;
+      });
+      const double tau1 = sm.tau[j], scale1 = sm.scale[j];
+      const double tau2 = two ? sm.tau[j1] : 0.0, scale2 = two ? sm.scale[j1] : 0.0;
+      const double u12 = two ? scale1 * sm.U[j][j1] : 0.0;
+      // d[2q] = x^T a_q (rows > j), d[2q + 1] = y^T a_q (rows > j + 1)
+      double d[NV2];
+      static_for<0, NV2>([&](auto vc) __attribute__((always_inline)) { d[decltype(vc)::value] = 0.0; });
+      static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          d[2 * q] = fma(x[p], a[p][q], d[2 * q]);
+          d[2 * q + 1] = fma(y[p], a[p][q], d[2 * q + 1]);
+        });
+      });
+      wave_transpose_reduce<NV2>(d);
+      auto s1 = [&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        return fma(scale1, lane_read(d[0], G2 * (2 * q)), lane_read(a[0][q], j));
+      };
+      auto s2 = [&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        return fma(scale2, lane_read(d[0], G2 * (2 * q + 1)), lane_read(a[0][q], j1));
+      };
+      // a -= v_j c1 + v_{j+1} c2 for local columns [Q0, CPW)
+      auto update = [&](auto q0c) __attribute__((always_inline)) {
+        constexpr int Q0 = decltype(q0c)::value;
+        double c1[CPW], c2[CPW];
+        static_for<Q0, CPW>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          c1[q] = tau1 * s1(qc);
+          c2[q] = tau2 * fma(-u12, c1[q], s2(qc));
+        });
+        static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          const double v1 = (p == 0 && lane == j) ? 1.0 : scale1 * x[p];
+          const double v2 = (p == 0 && lane == j1) ? 1.0 : scale2 * y[p];
+          static_for<Q0, CPW>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            a[p][q] = fma(-v2, c2[q], fma(-v1, c1[q], a[p][q]));
+          });
+        });
+      };
+      // U[c][j] and U[c][j + 1] of finished local columns [0, Q1) (without
+      // their scale_c, applied after the loop)
+      auto ustore = [&](auto q1c) __attribute__((always_inline)) {
+        constexpr int Q1 = decltype(q1c)::value;
+        double w1[CPW], w2[CPW];
+        static_for<0, Q1>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          w1[q] = s1(qc);
+          w2[q] = s2(qc);
+        });
+        if (lane == 0) {
+          static_for<0, Q1>([&](auto qc) __attribute__((always_inline)) {
+            constexpr int q = decltype(qc)::value;
+            sm.U[CPW * wave + q][j] = w1[q];
+            if (two) sm.U[CPW * wave + q][j1] = w2[q];
+          });
+        }
+      };
+      if (wave > jb) {
+        update(std::integral_constant<int, 0>{});
+      } else if (wave == jb) {
+        update(std::integral_constant<int, 2 * PP + 2>{});
+        ustore(std::integral_constant<int, 2 * PP>{});
+      } else {
+        ustore(std::integral_constant<int, CPW>{});
+      }
+      // the owner of the next pair forms and publishes it
+      const int jn = j + 2;
+      if (jn < R) {
+        if constexpr (PP + 1 < NP) {
+          if (wave == jb) prework(std::integral_constant<int, PP + 1>{}, jn, buf ^ 1);
+        } else {
+          if (wave == jb + 1) prework(std::integral_constant<int, 0>{}, jn, buf ^ 1);
+        }
+      }
+      __syncthreads();
+    });
+  }
+  for (int e = tid; e < RMAX * RMAX; e += ColCfg<RMAX, NW>::NT) {
+    const int m = e / RMAX, jc = e % RMAX;
+    if (m < jc && jc < R) sm.U[m][jc] *= sm.scale[m];
+  }
+  __syncthreads();
+}
+
 // T of the compact WY form from U and tau (block_qr_build_t) by the lanes of
 // wave 0 alone, without a workgroup barrier: the caller synchronises before
 // T is read.

@@ -575,6 +575,7 @@ void finish_col(FinishArgs f0, const FinishArgs* __restrict__ batch) {
   __shared__ double rinv[RMAX];
   __shared__ double sA[MR][RMAX + 1];
   __shared__ double xb[2][MR];
+  __shared__ double xp[2][2][MR];
   __shared__ double sred2[FC_NW][2];
   __shared__ double slam[RMAX];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -681,7 +682,10 @@ void finish_col(FinishArgs f0, const FinishArgs* __restrict__ batch) {
     });
   }
   // Householder QR of A (rows beyond I are zero)
-  col_qr<RMAX, RPL, FC_NW, false>(a, R, [&](int) { return I; }, xb, sm);
+  if constexpr (CPW % 2 == 0)
+    col_qr_pair<RMAX, RPL, FC_NW>(a, R, xp, sm);
+  else
+    col_qr<RMAX, RPL, FC_NW, false>(a, R, [&](int) { return I; }, xb, sm);
   // R_n = D R (D = sign(diag R)) and the reflectors for form_qn
   gdouble* __restrict__ qv = (gdouble*)f.qn;
   static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
