@@ -370,25 +370,28 @@ __device__ __forceinline__ void col_qr_pair(double (&a)[RPL][(ColCfg<RMAX, NW>::
 
 // T of the compact WY form from U and tau (block_qr_build_t) by the lanes of
 // wave 0 alone, without a workgroup barrier: the caller synchronises before
-// T is read.
+// T is read.  Lane k forms row k, T[k][j] = -tau_j sum_{k <= m < j} T[k][m]
+// U[m][j] (T[k][k] = tau_k): once T[k][m] is known its terms go into the
+// sums of every later column, one row of U at a time, so that the row of T
+// and the running sums share one register array (the caller's registers
+// stay live).  Each sum adds its terms in ascending m, as block_qr_build_t.
 template <int RMAX>
 __device__ __forceinline__ void block_qr_build_t_wave0(int R, QrSmem<RMAX>& sm) {
   const int k = threadIdx.x;
   if (k < RMAX) {
-    double t[RMAX];
+    double acc[RMAX];   // the sum of column j until T[k][j] is known, then T[k][j]
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) acc[j] = 0.0;
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
-      double u[RMAX];
+      const double tj = (j < k || j >= R) ? 0.0 : ((j == k) ? sm.tau[j] : -sm.tau[j] * acc[j]);
+      acc[j] = tj;
 #pragma unroll
-      for (int m = 0; m < j; ++m) u[m] = sm.U[m][j];
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m + 1 < j; ++m) acc = fma(t[m], u[m], acc);
-      if (j > 0) acc = fma(t[j - 1], u[j - 1], acc);
-      t[j] = (j < k || j >= R) ? 0.0 : ((j == k) ? sm.tau[j] : -sm.tau[j] * acc);
+      for (int jj = j + 1; jj < RMAX; ++jj) acc[jj] = fma(tj, sm.U[j][jj], acc[jj]);
+      __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j) sm.T[k][j] = t[j];
+    for (int j = 0; j < RMAX; ++j) sm.T[k][j] = acc[j];
   }
 }
 
@@ -405,15 +408,22 @@ __device__ __forceinline__ void block_qr_build_t_wave0(int R, QrSmem<RMAX>& sm) 
 // The column loop is not unrolled (the owner and local column of a step are
 // runtime values), which keeps the kernel within the instruction cache: each
 // step runs one of the bodies compiled per chunk count.
-template <int RMAX, int RPL, int NW, int K>
+// PAIRS: the columns go to the waves two at a time (columns 2 (NW r + w) and
+// 2 (NW r + w) + 1 are local columns 2 r and 2 r + 1 of wave w), for
+// col_qr_stair_pair, which factors two columns per step.
+template <int RMAX, int RPL, int NW, int K, bool PAIRS = false>
 struct StairCfg {
   static constexpr int CPW = RMAX / NW;
   static constexpr int MR = 64 * RPL;
   static constexpr int L(int q) {
-    long long c = (long long)NW * (q + 1), pw = 1;
+    long long c = PAIRS ? 2LL * NW * (q / 2 + 1) : (long long)NW * (q + 1), pw = 1;
     for (int k = 0; k < K; ++k) pw *= c;
     const long long ch = (pw + 63) / 64;
     return ch < RPL ? (int)ch : RPL;
+  }
+  // column index of local column q of wave w
+  static __device__ __forceinline__ int col(int q, int w) {
+    return PAIRS ? 2 * (NW * (q / 2) + w) + (q & 1) : NW * q + w;
   }
   static constexpr int OFF(int q) {
     int o = 0;
@@ -515,6 +525,160 @@ __device__ __forceinline__ void col_qr_stair(double (&a)[(StairCfg<RMAX, RPL, NW
       if (j + 1 < R && wave == (jj + 1) % NW) publish(xb[buf ^ 1]);
       __syncthreads();
     }
+  }
+  for (int e = tid; e < RMAX * RMAX; e += 64 * NW) {
+    const int m = e / RMAX, jc = e % RMAX;
+    if (m < jc && jc < R) sm.U[m][jc] *= sm.scale[m];
+  }
+  __syncthreads();
+}
+
+// col_qr_stair with two columns per step (the scheme of col_qr_pair) and
+// the paired column layout (StairCfg<..., true>): pair (j, j + 1), j even,
+// is local pair j / (2 NW) of wave (j / 2) mod NW.  The owner forms both
+// reflectors on the rows of column j + 1's profile and publishes the two
+// columns; the other waves' steps run the body compiled for that chunk
+// count.  Same outputs as col_qr_stair.
+template <int RMAX, int RPL, int NW, int K, typename Prof>
+__device__ __forceinline__ void col_qr_stair_pair(double (&a)[(StairCfg<RMAX, RPL, NW, K, true>::TOT)], int R,
+                                                  Prof&& prof, double (*xp)[2][64 * RPL], QrSmem<RMAX>& sm) {
+  using SC = StairCfg<RMAX, RPL, NW, K, true>;
+  constexpr int CPW = SC::CPW;
+  static_assert(CPW % 2 == 0, "pairs of columns must lie in one wave");
+  constexpr int NP = CPW / 2;
+  constexpr int NV2 = 2 * CPW <= 2 ? 2 : (2 * CPW <= 4 ? 4 : (2 * CPW <= 8 ? 8 : 16));
+  constexpr int G2 = 64 / NV2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto chunks = [&](int j) __attribute__((always_inline)) { return (prof(j) + 63) >> 6; };
+  // dispatch on the active chunk count of a step, rounded up to a power of two
+  auto by_chunks = [&](int nch, auto&& body) __attribute__((always_inline)) {
+    if (nch <= 1) body(std::integral_constant<int, 1>{});
+    else if (nch <= 2 || RPL <= 2) body(std::integral_constant<int, (RPL < 2 ? RPL : 2)>{});
+    else if (nch <= 4 || RPL <= 4) body(std::integral_constant<int, (RPL < 4 ? RPL : 4)>{});
+    else if (nch <= 8 || RPL <= 8) body(std::integral_constant<int, (RPL < 8 ? RPL : 8)>{});
+    else body(std::integral_constant<int, RPL>{});
+  };
+  // the owner's work for pair (j, j + 1) held in local pair LP
+  auto prework = [&](auto lpc, int j, int buf) __attribute__((always_inline)) {
+    constexpr int QA = 2 * decltype(lpc)::value, QB = QA + 1;
+    constexpr int LA = SC::L(QA);   // chunks held for both columns of the pair
+    const int j1 = j + 1;
+    by_chunks(chunks(j1), [&](auto nchc) __attribute__((always_inline)) {
+      constexpr int NC = decltype(nchc)::value < LA ? decltype(nchc)::value : LA;
+      double d[2] = {0.0, 0.0};
+      static_for<0, NC>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        const double xv = (p > 0 || lane > j) ? a[SC::OFF(QA) + p] : 0.0;
+        d[0] = fma(xv, xv, d[0]);
+        d[1] = fma(xv, a[SC::OFF(QB) + p], d[1]);
+      });
+      wave_transpose_reduce<2>(d);
+      double tau1, beta1, scale1;
+      qr_reflector_scalars(lane_read(a[SC::OFF(QA)], j), lane_read(d[0], 0), &tau1, &beta1, &scale1);
+      const double w1y = fma(scale1, lane_read(d[0], 32), lane_read(a[SC::OFF(QB)], j));
+      const double ts1 = tau1 * scale1;
+      static_for<0, NC>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        const double coef = (p > 0 || lane > j) ? ts1 * a[SC::OFF(QA) + p] : ((lane == j) ? tau1 : 0.0);
+        a[SC::OFF(QB) + p] = fma(-coef, w1y, a[SC::OFF(QB) + p]);
+      });
+      double tau2 = 0.0, beta2 = 0.0, scale2 = 0.0, w12 = 0.0;
+      if (j1 < R) {
+        double e[2] = {0.0, 0.0};
+        static_for<0, NC>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          const bool below = p > 0 || lane > j1;
+          const double yv = below ? a[SC::OFF(QB) + p] : 0.0;
+          e[0] = fma(yv, yv, e[0]);
+          e[1] = fma(below ? a[SC::OFF(QA) + p] : 0.0, yv, e[1]);
+        });
+        wave_transpose_reduce<2>(e);
+        qr_reflector_scalars(lane_read(a[SC::OFF(QB)], j1), lane_read(e[0], 0), &tau2, &beta2, &scale2);
+        w12 = fma(scale2, lane_read(e[0], 32), lane_read(a[SC::OFF(QA)], j1));
+      }
+      static_for<0, NC>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        xp[buf][0][lane + 64 * p] = a[SC::OFF(QA) + p];
+        xp[buf][1][lane + 64 * p] = a[SC::OFF(QB) + p];
+      });
+      if (lane == 0) {
+        sm.tau[j] = tau1;
+        sm.beta[j] = beta1;
+        sm.scale[j] = scale1;
+        if (j1 < R) {
+          sm.tau[j1] = tau2;
+          sm.beta[j1] = beta2;
+          sm.scale[j1] = scale2;
+          sm.U[j][j1] = w12;
+        }
+      }
+    });
+  };
+  auto prework_at = [&](int j, int buf) __attribute__((always_inline)) {
+    const int lp = (j >> 1) / NW;
+    static_for<0, NP>([&](auto lpc) __attribute__((always_inline)) {
+      if (lp == decltype(lpc)::value) prework(lpc, j, buf);
+    });
+  };
+  if (wave == 0) prework_at(0, 0);
+  __syncthreads();
+  for (int j = 0; j < R; j += 2) {
+    const int j1 = j + 1;
+    const int buf = (j >> 1) & 1;
+    const bool two = j1 < R;
+    by_chunks(chunks(two ? j1 : j), [&](auto nchc) __attribute__((always_inline)) {
+      constexpr int NCH = decltype(nchc)::value;
+      const int nch = chunks(two ? j1 : j);
+      // chunks at or beyond nch of the buffer may hold an earlier pair (the
+      // bucket rounds nch up), so they read as zero
+      double x[NCH], y[NCH];
+      static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        const double xv = xp[buf][0][lane + 64 * p], yv = xp[buf][1][lane + 64 * p];
+        x[p] = (p < nch && (p > 0 || lane > j)) ? xv : 0.0;
+        y[p] = (p < nch && (p > 0 || lane > j1)) ? yv : 0.0;
+      });
+      const double tau1 = sm.tau[j], scale1 = sm.scale[j];
+      const double tau2 = two ? sm.tau[j1] : 0.0, scale2 = two ? sm.scale[j1] : 0.0;
+      const double u12 = two ? scale1 * sm.U[j][j1] : 0.0;
+      double d[NV2];
+      static_for<0, NV2>([&](auto vc) __attribute__((always_inline)) { d[decltype(vc)::value] = 0.0; });
+      static_for<0, NCH>([&](auto pc) __attribute__((always_inline)) {
+        constexpr int p = decltype(pc)::value;
+        static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+          constexpr int q = decltype(qc)::value;
+          if constexpr (p < SC::L(q)) {
+            d[2 * q] = fma(x[p], a[SC::OFF(q) + p], d[2 * q]);
+            d[2 * q + 1] = fma(y[p], a[SC::OFF(q) + p], d[2 * q + 1]);
+          }
+        });
+      });
+      wave_transpose_reduce<NV2>(d);
+      static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+        constexpr int q = decltype(qc)::value;
+        const int c = SC::col(q, wave);
+        const double s1 = fma(scale1, lane_read(d[0], G2 * (2 * q)), lane_read(a[SC::OFF(q)], j));
+        const double s2 = fma(scale2, lane_read(d[0], G2 * (2 * q + 1)), lane_read(a[SC::OFF(q)], j1));
+        const bool after = c > j1, before = c < j;
+        const double c1 = after ? tau1 * s1 : 0.0;
+        const double c2 = after ? tau2 * fma(-u12, c1, s2) : 0.0;
+        static_for<0, (NCH < SC::L(q) ? NCH : SC::L(q))>([&](auto pc) __attribute__((always_inline)) {
+          constexpr int p = decltype(pc)::value;
+          const double v1 = (p == 0 && lane == j) ? 1.0 : scale1 * x[p];
+          const double v2 = (p == 0 && lane == j1) ? 1.0 : scale2 * y[p];
+          a[SC::OFF(q) + p] = fma(-v2, c2, fma(-v1, c1, a[SC::OFF(q) + p]));
+        });
+        // U[c][j], U[c][j + 1] without the scale_c factor (applied below)
+        if (lane == 0 && before) {
+          sm.U[c][j] = s1;
+          if (two) sm.U[c][j1] = s2;
+        }
+      });
+    });
+    // the owner of the next pair forms and publishes it
+    const int jn = j + 2;
+    if (jn < R && wave == (jn >> 1) % NW) prework_at(jn, buf ^ 1);
+    __syncthreads();
   }
   for (int e = tid; e < RMAX * RMAX; e += 64 * NW) {
     const int m = e / RMAX, jc = e % RMAX;

@@ -490,13 +490,17 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
 void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
   const ZcolArgs args = kernel_args(a0, batch, blockIdx.x);
   if (!args.active) return;
-  using SC = StairCfg<RMAX, RPL, NW, K>;
+  // two columns per step where the pairs fit the waves
+  constexpr bool PAIRS = ((RMAX / NW) % 2) == 0;
+  using SC = StairCfg<RMAX, RPL, NW, K, PAIRS>;
   constexpr int CPW = SC::CPW, NT = 64 * NW, MR = SC::MR;
   const int n = args.n, R = args.R;
   const int M = (int)args.M;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ QrSmem<RMAX> sm;
-  __shared__ double xb[2][SC::TOT * 64];
+  // broadcast buffer: two published columns per step, double-buffered
+  // (pairs), or the owner's columns packed, double-buffered
+  __shared__ double xbuf[PAIRS ? 2 * 2 * 64 * RPL : 2 * SC::TOT * 64];
   __shared__ union ZcolLds {
     double srf[K * RMAX * RMAX];   // R factors of the other modes (Z build)
     double v1[RMAX][RMAX + 1];     // first R rows of V (epilogue)
@@ -539,7 +543,7 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
     static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
       constexpr int q = decltype(qc)::value;
       if constexpr (p < SC::L(q)) {
-        const int c = NW * q + wave;
+        const int c = SC::col(q, wave);
         double v = in ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) v *= u.srf[k * RMAX * RMAX + ((dig >> (5 * k)) & 31) + RMAX * c];
@@ -555,13 +559,16 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
     for (int k = 0; k < K; ++k) pw *= (j + 1);
     return pw < M ? pw : M;
   };
-  col_qr_stair<RMAX, RPL, NW, K>(a, R, prof, xb, sm);
+  if constexpr (PAIRS)
+    col_qr_stair_pair<RMAX, RPL, NW, K>(a, R, prof, reinterpret_cast<double(*)[2][64 * RPL]>(xbuf), sm);
+  else
+    col_qr_stair<RMAX, RPL, NW, K>(a, R, prof, reinterpret_cast<double(*)[SC::TOT * 64]>(xbuf), sm);
   // R0 = D R and V1 into LDS (the first R rows are lanes 0..R-1 of chunk 0)
   gdouble* __restrict__ gR0 = (gdouble*)args.R0;
   gdouble* __restrict__ gV = (gdouble*)args.V;
   static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
     constexpr int q = decltype(qc)::value;
-    const int c = NW * q + wave;
+    const int c = SC::col(q, wave);
     const double sc_c = sm.scale[c < R ? c : 0];
     if (lane < RMAX) {
       const int j = lane;
@@ -586,7 +593,7 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
   // buffer from its set-up)
   static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
     constexpr int q = decltype(qc)::value;
-    const int c = NW * q + wave;
+    const int c = SC::col(q, wave);
     const double sc_c = sm.scale[c < R ? c : 0];
     static_for<0, SC::L(q)>([&](auto pc) __attribute__((always_inline)) {
       constexpr int p = decltype(pc)::value;
