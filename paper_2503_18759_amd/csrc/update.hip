@@ -599,13 +599,15 @@ void finish_col(FinishArgs f0, const FinishArgs* __restrict__ batch) {
   {
     constexpr int NE = MR * RMAX / NT;
     double vp[NE], vq[NE];
+    // without extrapolation in this sweep Vq is not read at all
+    const bool load_q = f.extrap != 0;
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = tid + NT * t;
       const int r = e % MR, c = e / MR;
       const int64_t g = (r < I && c < R) ? r + (int64_t)I * c : 0;
       vp[t] = gV[g];
-      vq[t] = gV[(int64_t)I * R + g];
+      vq[t] = load_q ? gV[(int64_t)I * R + g] : 0.0;
     }
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
