@@ -266,6 +266,12 @@ hipError_t launch_finish_tail(const FinishArgs& f, hipStream_t st);
 // One workgroup per problem; every problem of the batch has rank class rmax
 // and factor rows-per-thread rpt.
 hipError_t launch_finish_batched(int count, int rmax, int rpt, const FinishArgs* args, hipStream_t st);
+// The column-distributed finish (factors of at most 256 rows, finish_col_rpl
+// rows per lane: 1, 2 or 4; 0 beyond) for every problem of a batch, and the
+// explicit Q_n that follows it.
+int finish_col_rpl(int I);
+hipError_t launch_finish_col_batched(int count, int rmax, int rpl, const FinishArgs* args, hipStream_t st);
+hipError_t launch_form_qn_batched(int count, int rmax, const FinishArgs* args, hipStream_t st);
 // A factor with more than CPQR_MAX_FACTOR_ROWS rows: solve, lambda, A and the
 // fit in one streaming workgroup (f.Rn, f.q64, f.q32 unused); the factor QR is
 // then launch_tsqr on A (explicit source) followed by the tail, which writes

@@ -868,9 +868,7 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   p.elem = p.f64 ? 8 : 4;
   if (!(o->flags & CPQR_FLAG_DENSE_ZQR)) {
     p.stair = stair_plan(N, rank);
-    // the batched driver groups its Z QRs by the one-workgroup staircase
-    // kernel's shapes
-    if (!batched) p.zcol = zcol_plan(N, rank);
+    p.zcol = zcol_plan(N, rank);
   }
   cpqr_status stt = setup(h, p, o->iters, S.sched);
   if (stt != CPQR_OK) return stt;
@@ -1547,14 +1545,17 @@ void count_ttm(cpqr_session* S, const std::vector<Step>& sw) {
 // One batched launch of a sweep's step list, with the byte offsets of its
 // argument arrays inside the sweep's argument blob.
 struct BatchItem {
-  int kind = 0;                 // 0 TTM, 1 TSQR, 2 Y*Q0, 3 finish, 4 staircase Z QR
+  int kind = 0;                 // 0 TTM, 1 TSQR, 2 Y*Q0, 3 finish, 4 staircase Z QR,
+                                // 6 explicit Q_n after column-layout finishes, 7 zqr_col
   std::string tune_sig;         // TTM: identifies the step for the autotuner
   std::vector<int> members;     // problem indices
   TtmBatch tb{};
   TsqrBatch qb{};
   ApplyBatch ab{};
   int fin_rmax = 0, fin_rpt = 0;
+  bool fin_col = false;         // kind 3: finish_col (fin_rpt = its rows per lane)
   StairPlan sp{};
+  ZcolPlan zp{};
   size_t off[3] = {0, 0, 0};
 };
 
@@ -1649,10 +1650,17 @@ void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpq
       // shares only the tree, extrapolation mode, precision and sweep count)
       for (int t = 0; t < count; ++t)
         update_args(B.S[t]->p, st.mode, k, last, &B.S[t]->opts, &ts[t], &as[t], &fs[t]);
-      // staircase Z QR groups: kernel shape; TSQR groups: rank class and plan
+      // column-distributed Z QR groups: its plan; staircase Z QR groups:
+      // kernel shape; TSQR groups: rank class and plan
+      std::map<std::pair<int, int>, std::vector<int>> zg;
       std::map<std::pair<int, int>, std::vector<int>> sg;
       std::map<std::tuple<int, int, int>, std::vector<int>> tg;
       for (int t = 0; t < count; ++t) {
+        const ZcolPlan& zp = B.S[t]->p.zcol;
+        if (zp.ok) {
+          zg[{zp.rmax, zp.k}].push_back(t);
+          continue;
+        }
         const StairPlan& sp = B.S[t]->p.stair;
         if (sp.ok) {
           sg[{sp.rmax, sp.ns}].push_back(t);
@@ -1660,6 +1668,24 @@ void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpq
         }
         const TsqrPlan pl = tsqr_plan(ts[t].M, ts[t].R);
         tg[std::make_tuple(qr_rmax(ts[t].R), pl.leaf_rpt, pl.P > 1 ? pl.top_rpt : 0)].push_back(t);
+      }
+      // one launch per rank class and order: the group takes its largest
+      // member's rows per lane (smaller members leave the extra rows zero)
+      for (auto& g : zg) {
+        BatchItem it;
+        it.kind = 7;
+        it.members = g.second;
+        it.zp = B.S[g.second[0]]->p.zcol;
+        for (int t : g.second)
+          if (B.S[t]->p.zcol.rpl > it.zp.rpl) it.zp = B.S[t]->p.zcol;
+        std::vector<ZcolArgs> za;
+        for (int t : g.second) {
+          const Problem& pp = B.S[t]->p;
+          za.push_back(ZcolArgs{ts[t].N, ts[t].n, ts[t].R, ts[t].M, ts[t].rf, pp.smap, ts[t].R0, ts[t].Q0,
+                                const_cast<double*>(as[t].meta_p), 1});
+        }
+        it.off[0] = blob_put(*blob, za);
+        items->push_back(it);
       }
       for (auto& g : sg) {
         BatchItem it;
@@ -1720,20 +1746,43 @@ void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpq
         it.off[0] = blob_put(*blob, ad);
         items->push_back(it);
       }
-      // finish groups: rank class and rows per thread
-      std::map<std::pair<int, int>, std::vector<int>> fg;
-      for (int t = 0; t < count; ++t) fg[{qr_rmax(fs[t].R), factor_rpt(fs[t].I)}].push_back(t);
+      // finish groups: the column-distributed kernel (factors of at most
+      // 256 rows) by rank class and rows per lane, the row-distributed one
+      // by rank class and rows per thread; then the explicit Q_n of the
+      // column-layout groups (kind 6), which the next update's Z QR does not
+      // wait for
+      // (column-layout groups: one per rank class at the largest member's
+      // rows per lane)
+      std::map<std::tuple<int, int, int>, std::vector<int>> fg;
+      std::map<int, int> col_rpl_max;
+      for (int t = 0; t < count; ++t) {
+        const int rm = qr_rmax(fs[t].R), cr = finish_col_rpl(fs[t].I);
+        if (cr > 0 && fs[t].qn != nullptr) {
+          fg[std::make_tuple(1, rm, 0)].push_back(t);
+          col_rpl_max[rm] = std::max(col_rpl_max[rm], cr);
+        } else {
+          fg[std::make_tuple(0, rm, factor_rpt(fs[t].I))].push_back(t);
+        }
+      }
+      std::vector<BatchItem> tails;
       for (auto& g : fg) {
         BatchItem it;
         it.kind = 3;
         it.members = g.second;
         std::vector<FinishArgs> fv;
         for (int t : g.second) fv.push_back(fs[t]);
-        it.fin_rmax = g.first.first;
-        it.fin_rpt = g.first.second;
+        it.fin_col = std::get<0>(g.first) == 1;
+        it.fin_rmax = std::get<1>(g.first);
+        it.fin_rpt = it.fin_col ? col_rpl_max[it.fin_rmax] : std::get<2>(g.first);
         it.off[0] = blob_put(*blob, fv);
         items->push_back(it);
+        if (it.fin_col) {
+          BatchItem tl = it;
+          tl.kind = 6;
+          tails.push_back(tl);
+        }
       }
+      for (const BatchItem& tl : tails) items->push_back(tl);
     }
   }
 }
@@ -1760,7 +1809,16 @@ hipError_t launch_item(const BatchItem& it, const char* base, hipStream_t s) {
     case 4:
       return launch_zqr_stair_batched(it.sp, (int)it.members.size(),
                                       reinterpret_cast<const StairArgs*>(base + it.off[0]), s);
+    case 6:
+      return launch_form_qn_batched((int)it.members.size(), it.fin_rmax,
+                                    reinterpret_cast<const FinishArgs*>(base + it.off[0]), s);
+    case 7:
+      return launch_zqr_col_batched(it.zp, (int)it.members.size(),
+                                    reinterpret_cast<const ZcolArgs*>(base + it.off[0]), s);
     default:
+      if (it.fin_col)
+        return launch_finish_col_batched((int)it.members.size(), it.fin_rmax, it.fin_rpt,
+                                         reinterpret_cast<const FinishArgs*>(base + it.off[0]), s);
       return launch_finish_batched((int)it.members.size(), it.fin_rmax, it.fin_rpt,
                                    reinterpret_cast<const FinishArgs*>(base + it.off[0]), s);
   }
@@ -1900,8 +1958,8 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
       char* dblob = nullptr;
       WS(h, "batch:args:" + key, blob.size() + 64, dblob);
       HIP_TRY(h, hipMemcpy(dblob, blob.data(), blob.size(), hipMemcpyHostToDevice));
-      // As in the single-problem sweep, each update's Z QR groups (kinds 1
-      // and 4, contiguous in the plan) run on the side stream beside the
+      // As in the single-problem sweep, each update's Z QR groups (kinds 1,
+      // 4 and 7, contiguous in the plan) run on the side stream beside the
       // TTM groups of the same update, forked after the previous update's
       // finish groups and joined before the update's first Y*Q0 group.
       const bool bfork = (h->side != nullptr) ||
@@ -1923,7 +1981,7 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
           }
       }
       const size_t ni = items.size();
-      auto is_qr = [&](size_t i) { return items[i].kind == 1 || items[i].kind == 4; };
+      auto is_qr = [&](size_t i) { return items[i].kind == 1 || items[i].kind == 4 || items[i].kind == 7; };
       hipGraph_t g;
       HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipSuccess;

@@ -967,6 +967,18 @@ hipError_t launch_finish_batched(int count, int rmax, int rpt, const FinishArgs*
   return finish_launch(rmax, rpt, (unsigned)count, FinishArgs{}, args, st);
 }
 
+int finish_col_rpl(int I) { return col_rpl(I); }
+
+hipError_t launch_finish_col_batched(int count, int rmax, int rpl, const FinishArgs* args, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  return finish_col_launch(rmax, rpl, (unsigned)count, FinishArgs{}, args, st);
+}
+
+hipError_t launch_form_qn_batched(int count, int rmax, const FinishArgs* args, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  return form_qn_launch(rmax, (unsigned)count, FinishArgs{}, args, st);
+}
+
 // ------------------------------------------------------------------- norms
 static constexpr int NORM_BLOCKS = 1024;
 static constexpr int NORM_THREADS = 256;
