@@ -47,6 +47,9 @@ struct cpqr_handle {
   hipEvent_t ready = nullptr;
   // second stream (default priority) for the Z QR branch of captured sweeps
   hipStream_t side = nullptr;
+  // more streams (default priority) for the independent groups of a
+  // batched sweep, which the captured graph runs as parallel branches
+  std::vector<hipStream_t> pool;
   std::string err;
   std::map<std::string, DevBuf> bufs;
   bool busy = false;                  // a session is using the workspace
@@ -724,6 +727,7 @@ cpqr_status cpqr_destroy(cpqr_handle* h) {
     if (kv.second.ptr) (void)hipFree(kv.second.ptr);
   if (h->ready) (void)hipEventDestroy(h->ready);
   if (h->side) (void)hipStreamDestroy(h->side);
+  for (hipStream_t q : h->pool) (void)hipStreamDestroy(q);
   if (h->own_stream) (void)hipStreamDestroy(h->stream);
   delete h;
   return CPQR_OK;
@@ -1959,61 +1963,114 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
       WS(h, "batch:args:" + key, blob.size() + 64, dblob);
       HIP_TRY(h, hipMemcpy(dblob, blob.data(), blob.size(), hipMemcpyHostToDevice));
       // As in the single-problem sweep, each update's Z QR groups (kinds 1,
-      // 4 and 7, contiguous in the plan) run on the side stream beside the
-      // TTM groups of the same update, forked after the previous update's
-      // finish groups and joined before the update's first Y*Q0 group.
-      const bool bfork = (h->side != nullptr) ||
-                         (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess);
-      if (!bfork) {
-        (void)hipGetLastError();
-        h->side = nullptr;
+      // 4 and 7, contiguous in the plan) run beside the TTM groups of the
+      // same update, forked after the previous update's finish groups and
+      // joined before the update's first Y*Q0 group.  The groups of one
+      // phase (the Z QR groups, the Y*Q0 groups, the finish groups, the Q_n
+      // groups) are independent, one per kernel class, so each runs on a
+      // branch of its own: the phase then takes as long as its slowest
+      // group instead of their sum.
+      size_t width = 1;
+      for (size_t i = 0; i < items.size();) {
+        size_t j = i + 1;
+        const int ki = items[i].kind == 4 || items[i].kind == 7 ? 1 : items[i].kind;
+        while (j < items.size()) {
+          const int kj = items[j].kind == 4 || items[j].kind == 7 ? 1 : items[j].kind;
+          if (kj != ki || ki == 0) break;
+          ++j;
+        }
+        width = std::max(width, j - i);
+        i = j;
       }
+      bool bfork = (h->side != nullptr) ||
+                   (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) == hipSuccess);
+      // the Z QR branches (h->side and pool[0, width - 1)) run beside the
+      // main stream while the previous update's Q_n groups do: the other
+      // phases take pool[width - 1, 2 width - 1)
+      while (bfork && h->pool.size() + 1 < 2 * width) {
+        hipStream_t q = nullptr;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) {
+          bfork = false;
+          break;
+        }
+        h->pool.push_back(q);
+      }
+      if (!bfork) (void)hipGetLastError();
+      // events: two per item are more than the branches can use
       std::vector<hipEvent_t> bev;
       if (bfork) {
-        for (const BatchItem& it : items)
-          if (it.kind == 2) {
-            for (int r = 0; r < 2; ++r) {
-              hipEvent_t ev;
-              HIP_TRY(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-              B.fork_evs.push_back(ev);
-              bev.push_back(ev);
-            }
-          }
+        for (size_t r = 0; r < 2 * items.size() + 2; ++r) {
+          hipEvent_t ev;
+          HIP_TRY(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+          B.fork_evs.push_back(ev);
+          bev.push_back(ev);
+        }
       }
       const size_t ni = items.size();
       auto is_qr = [&](size_t i) { return items[i].kind == 1 || items[i].kind == 4 || items[i].kind == 7; };
+      auto branch = [&](size_t r, bool qr) {
+        return qr ? (r == 0 ? h->side : h->pool[r - 1]) : h->pool[width - 1 + r];
+      };
       hipGraph_t g;
       HIP_TRY(h, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       hipError_t e = hipSuccess;
-      size_t qr_end = 0, bnext = 0;   // end of the forked QR groups; next event pair
-      hipEvent_t join = nullptr;
+      size_t qr_end = 0, bnext = 0;   // end of the forked QR groups; next free event
+      std::vector<hipEvent_t> joins;  // ends of the forked QR branches
+      auto next_ev = [&]() -> hipEvent_t { return bnext < bev.size() ? bev[bnext++] : nullptr; };
+      // items [j, j2) on branches of their own, forked from the main stream;
+      // the events marking their ends are appended to *ends
+      auto run_branches = [&](size_t j, size_t j2, bool qr, std::vector<hipEvent_t>* ends) -> hipError_t {
+        hipEvent_t a = next_ev();
+        if (!a) return hipErrorInvalidValue;
+        hipError_t ee;
+        if ((ee = hipEventRecord(a, s)) != hipSuccess) return ee;
+        for (size_t q = j; q < j2; ++q) {
+          hipStream_t br = branch(q - j, qr);
+          hipEvent_t en = next_ev();
+          if (!en) return hipErrorInvalidValue;
+          if ((ee = hipStreamWaitEvent(br, a, 0)) != hipSuccess) return ee;
+          if ((ee = launch_item(items[q], dblob, br)) != hipSuccess) return ee;
+          if ((ee = hipEventRecord(en, br)) != hipSuccess) return ee;
+          ends->push_back(en);
+        }
+        return hipSuccess;
+      };
       auto fork_from = [&](size_t from) -> hipError_t {
         size_t j = from;
         while (j < ni && !is_qr(j) && items[j].kind != 2) ++j;
         if (j == ni || !is_qr(j)) return hipSuccess;
         size_t j2 = j;
         while (j2 < ni && is_qr(j2)) ++j2;
-        if (bnext + 2 > bev.size()) return hipErrorInvalidValue;
-        hipEvent_t a = bev[bnext++], b = bev[bnext++];
-        hipError_t ee;
-        if ((ee = hipEventRecord(a, s)) != hipSuccess) return ee;
-        if ((ee = hipStreamWaitEvent(h->side, a, 0)) != hipSuccess) return ee;
-        for (size_t q = j; q < j2; ++q)
-          if ((ee = launch_item(items[q], dblob, h->side)) != hipSuccess) return ee;
-        if ((ee = hipEventRecord(b, h->side)) != hipSuccess) return ee;
-        join = b;
         qr_end = j2;
-        return hipSuccess;
+        return run_branches(j, j2, true, &joins);
       };
       if (bfork) e = fork_from(0);
-      for (size_t i = 0; i < ni && e == hipSuccess; ++i) {
-        if (bfork && is_qr(i) && i < qr_end) continue;   // already on the side branch
-        if (bfork && items[i].kind == 2 && join != nullptr) {
-          if ((e = hipStreamWaitEvent(s, join, 0)) != hipSuccess) break;
-          join = nullptr;
+      for (size_t i = 0; i < ni && e == hipSuccess;) {
+        if (bfork && is_qr(i) && i < qr_end) {   // already on the side branches
+          ++i;
+          continue;
         }
-        if ((e = launch_item(items[i], dblob, s)) != hipSuccess) break;
-        if (bfork && items[i].kind == 3 && (i + 1 == ni || items[i + 1].kind != 3)) e = fork_from(i + 1);
+        if (bfork && items[i].kind == 2 && !joins.empty()) {
+          for (hipEvent_t je : joins)
+            if ((e = hipStreamWaitEvent(s, je, 0)) != hipSuccess) break;
+          joins.clear();
+          if (e != hipSuccess) break;
+        }
+        // a run of independent groups of one phase: parallel branches
+        size_t i2 = i + 1;
+        if (bfork && (items[i].kind == 2 || items[i].kind == 3 || items[i].kind == 6))
+          while (i2 < ni && items[i2].kind == items[i].kind) ++i2;
+        if (i2 - i > 1) {
+          std::vector<hipEvent_t> ends;
+          if ((e = run_branches(i, i2, false, &ends)) != hipSuccess) break;
+          for (hipEvent_t en : ends)
+            if ((e = hipStreamWaitEvent(s, en, 0)) != hipSuccess) break;
+          if (e != hipSuccess) break;
+        } else {
+          if ((e = launch_item(items[i], dblob, s)) != hipSuccess) break;
+        }
+        if (bfork && items[i].kind == 3 && (i2 == ni || items[i2].kind != 3)) e = fork_from(i2);
+        i = i2;
       }
       hipError_t e2 = hipStreamEndCapture(s, &g);
       if (e != hipSuccess) return fail(h, CPQR_EHIP, "batched launch during capture failed: %s", hipGetErrorString(e));
