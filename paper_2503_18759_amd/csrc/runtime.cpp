@@ -1558,6 +1558,7 @@ struct BatchItem {
   ApplyBatch ab{};
   int fin_rmax = 0, fin_rpt = 0;
   bool fin_col = false;         // kind 3: finish_col (fin_rpt = its rows per lane)
+  int step = -1;                // kind 0: index of the TTM step in the sweep
   StairPlan sp{};
   ZcolPlan zp{};
   size_t off[3] = {0, 0, 0};
@@ -1628,6 +1629,7 @@ void build_sweep_plan(BatchRun& B, int k, const std::vector<Step>& sw, const cpq
         std::vector<std::array<int64_t, 4>> shapes;
         for (const TtmArgs& a : args) shapes.push_back({a.L, (int64_t)a.I, a.S, (int64_t)a.R});
         it.tune_sig = ttm_key_batch(o->prec, g.first, args[0].L == 1, shapes);
+        it.step = (int)i;
         it.tb.count = (int)args.size();
         it.tb.kc = args[0].L == 1;
         it.tb.vec = vec;
@@ -1970,15 +1972,16 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
       // groups) are independent, one per kernel class, so each runs on a
       // branch of its own: the phase then takes as long as its slowest
       // group instead of their sum.
+      // items i and j belong to one phase of independent groups
+      auto same_phase = [&](size_t i, size_t j) {
+        auto cls = [&](size_t x) { return items[x].kind == 4 || items[x].kind == 7 ? 1 : items[x].kind; };
+        if (cls(i) != cls(j)) return false;
+        return cls(i) != 0 || items[i].step == items[j].step;   // TTM groups of one step
+      };
       size_t width = 1;
       for (size_t i = 0; i < items.size();) {
         size_t j = i + 1;
-        const int ki = items[i].kind == 4 || items[i].kind == 7 ? 1 : items[i].kind;
-        while (j < items.size()) {
-          const int kj = items[j].kind == 4 || items[j].kind == 7 ? 1 : items[j].kind;
-          if (kj != ki || ki == 0) break;
-          ++j;
-        }
+        while (j < items.size() && same_phase(i, j)) ++j;
         width = std::max(width, j - i);
         i = j;
       }
@@ -2058,8 +2061,8 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
         }
         // a run of independent groups of one phase: parallel branches
         size_t i2 = i + 1;
-        if (bfork && (items[i].kind == 2 || items[i].kind == 3 || items[i].kind == 6))
-          while (i2 < ni && items[i2].kind == items[i].kind) ++i2;
+        if (bfork && (items[i].kind == 0 || items[i].kind == 2 || items[i].kind == 3 || items[i].kind == 6))
+          while (i2 < ni && same_phase(i, i2)) ++i2;
         if (i2 - i > 1) {
           std::vector<hipEvent_t> ends;
           if ((e = run_branches(i, i2, false, &ends)) != hipSuccess) break;
