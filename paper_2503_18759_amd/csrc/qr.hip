@@ -9,6 +9,10 @@
 //               triangles).  Also used on an explicit matrix.
 //  * zqr_top:   QR of the stacked leaf triangles; writes R0 (diag >= 0) and
 //               the explicit Q of the stack with the sign fix applied.
+//  * zqr_leaf_col, zqr_top_col: the same two steps by the column-distributed
+//               Householder QR (eight waves own whole columns, two columns
+//               per step) where they are faster (rank class 32 leaves, and
+//               tops of up to 512 rows in rank class 32 or 1024 rows in 16).
 //  * form_q0:   explicit Q0 rows of each leaf: Q0_p = E Qtop_p - V_p (T_p V_p1^T Qtop_p).
 //  * factor_qr: QR of an I x R factor held by one workgroup; writes R_n and
 //               the explicit Q_n in float64 / float32 / bf16 hi+lo.
@@ -122,6 +126,110 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_leaf(LeafArgs a0, const LeafArgs* __res
   }
 }
 
+// The same leaf by the column-distributed Householder QR with two columns
+// per step (col_qr_pair: eight waves, RMAX / 8 columns each, every wave holds
+// all B = 64 RPL rows of its columns), for rank class 32.  Same inputs and outputs as zqr_leaf:
+// V rows, T, and the leaf's R in the stack (or, for a single leaf, R0 = D R
+// and the trivial Qtop = D).
+static constexpr int LEAF_COL_NW = 8;
+
+template <int RMAX, int RPL>
+__global__ __launch_bounds__(64 * LEAF_COL_NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void zqr_leaf_col(LeafArgs a0, const LeafArgs* __restrict__ batch) {
+  const LeafArgs args = kernel_args(a0, batch, blockIdx.y);
+  if ((int)blockIdx.x >= args.P) return;
+  using Cfg = ColCfg<RMAX, LEAF_COL_NW>;
+  constexpr int CPW = Cfg::CPW, NT = Cfg::NT, B = 64 * RPL;
+  const int N = args.N, n = args.n, R = args.R;
+  const gdouble* __restrict__ rf = (const gdouble*)args.rf;
+  const gdouble* __restrict__ src = (const gdouble*)args.src;
+  const int64_t M = args.M, ldstack = args.ldstack, ldv = args.ldv;
+  gdouble* __restrict__ V = (gdouble*)args.V;
+  gdouble* __restrict__ Tbuf = (gdouble*)args.T;
+  gdouble* __restrict__ stack = (gdouble*)args.stack;
+  gdouble* __restrict__ R0 = (gdouble*)args.R0;
+  gdouble* __restrict__ Qtop = (gdouble*)args.Qtop;
+  __shared__ QrSmem<RMAX> sm;
+  __shared__ double srf[qr_max_other_modes(RMAX) * RMAX * RMAX];
+  __shared__ double xp[2][2][B];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = CPW * wave;
+  const int nm = (src == nullptr) ? N - 1 : 0;
+  if (src == nullptr) {
+    // R factors of the other modes (ascending mode order), zero-padded to
+    // RMAX x RMAX so that columns c >= R of every product vanish
+    for (int e = tid; e < nm * RMAX * RMAX; e += NT) {
+      const int q = e / (RMAX * RMAX), rem = e % (RMAX * RMAX);
+      const int i = rem % RMAX, c = rem / RMAX;
+      const int mode = (q < n) ? q : q + 1;
+      srf[e] = (i < R && c < R) ? rf[(int64_t)mode * R * R + i + (int64_t)R * c] : 0.0;
+    }
+    __syncthreads();
+  }
+  // this wave's columns of the leaf's rows: Z[row][c] = prod_k R_k[digit_k(row)][c]
+  // (digits of row in base R, first remaining mode fastest), or the source
+  double a[RPL][CPW];
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int pp = decltype(pc)::value;
+    const int64_t row = (int64_t)p * B + lane + 64 * pp;
+    const bool in = row < M;
+    if (src == nullptr) {
+      double v[CPW];
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) v[q] = in ? 1.0 : 0.0;
+      int64_t rr = row;
+      for (int k = 0; k < nm; ++k) {
+        const int d = (int)(rr % R);
+        rr /= R;
+        const double* rk = srf + k * RMAX * RMAX + d + RMAX * c0;
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) v[q] *= rk[RMAX * q];
+      }
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) a[pp][q] = v[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        const int c = c0 + q;
+        a[pp][q] = (in && c < R) ? src[row + M * c] : 0.0;
+      }
+    }
+  });
+  col_qr_pair<RMAX, RPL, LEAF_COL_NW>(a, R, xp, sm);
+  if (wave == 0) block_qr_build_t_wave0<RMAX>(R, sm);
+  // V rows (unit lower trapezoidal) for all B rows of the leaf
+  static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+    constexpr int q = decltype(qc)::value;
+    const int c = c0 + q;
+    const double sc_c = sm.scale[c < R ? c : 0];
+    static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int pp = decltype(pc)::value;
+      const int lr = lane + 64 * pp;
+      const double v = (lr > c) ? a[pp][q] * sc_c : ((lr == c) ? 1.0 : 0.0);
+      if (c < R) V[(int64_t)p * B + lr + ldv * c] = v;
+    });
+    // the leaf's R (rows 0..R-1 are lanes of chunk 0)
+    if (lane < R && c < R) {
+      const int i = lane;
+      const double rr = (c > i) ? a[0][q] : ((c == i) ? sm.beta[i] : 0.0);
+      if (R0 != nullptr) {
+        // single leaf: R0 = D R and the trivial Qtop = D
+        const double sg = (sm.beta[i] < 0.0) ? -1.0 : 1.0;
+        R0[i + R * c] = sg * rr;
+        Qtop[i + R * c] = (c == i) ? sg : 0.0;
+      } else {
+        stack[(int64_t)p * R + i + ldstack * c] = rr;
+      }
+    }
+  });
+  __syncthreads();   // T from wave 0
+  for (int e = tid; e < R * R; e += NT) {
+    const int k = e % R, c = e / R;
+    Tbuf[(int64_t)p * R * R + e] = sm.T[k][c];
+  }
+}
+
 // --------------------------------------------------------------------- top
 // QR of the P*R x R stack.  Writes R0 (R x R column-major, diag >= 0) and
 // Qtop (P*R x R column-major) = explicit Q of the stack times the sign fix.
@@ -157,6 +265,118 @@ __global__ CPQR_QR_KERNEL(RMAX) void zqr_top(TopArgs a0, const TopArgs* __restri
     if (row < rows)
       block_qr_q_row<RMAX>(a[q], (int)row, R, sm, wy, [&](int c, double val) { Qtop[row + rows * c] = val; });
   }
+}
+
+// QR of the P*R x R stack by the same column-distributed scheme (eight
+// waves, two columns per step).  Writes what zqr_top writes: R0 = D R and
+// Qtop = Q D = (E - V T V1^T) D, E the first R columns of the identity.  With
+// Md = T V1^T D (R x R, in LDS), row r of Qtop is e_r^T D - V[r][:] Md; the
+// rows of V pass through LDS 64 at a time (the QR leaves them distributed by
+// column), and each wave forms its own columns of Qtop for those rows.
+template <int RMAX, int RPL>
+__global__ __launch_bounds__(64 * LEAF_COL_NW) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void zqr_top_col(TopArgs a0, const TopArgs* __restrict__ batch) {
+  const TopArgs args = kernel_args(a0, batch, blockIdx.y);
+  if (!args.active) return;
+  using Cfg = ColCfg<RMAX, LEAF_COL_NW>;
+  constexpr int CPW = Cfg::CPW, NT = Cfg::NT, MR = 64 * RPL;
+  const int R = args.R;
+  const int rows = (int)args.rows;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c0 = CPW * wave;
+  const gdouble* __restrict__ stack = (const gdouble*)args.stack;
+  gdouble* __restrict__ gR0 = (gdouble*)args.R0;
+  gdouble* __restrict__ gQ = (gdouble*)args.Qtop;
+  __shared__ QrSmem<RMAX> sm;
+  __shared__ double xp[2][2][MR];
+  __shared__ double vb[2][64][RMAX + 1];   // 64 rows of V
+  __shared__ double smd[RMAX][RMAX + 1];   // Md
+  double a[RPL][CPW];
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    const int row = lane + 64 * p;
+    static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      const int c = c0 + q;
+      const bool in = row < rows && c < R;
+      const double v = stack[in ? row + (int64_t)rows * c : 0];
+      a[p][q] = in ? v : 0.0;
+    });
+  });
+  col_qr_pair<RMAX, RPL, LEAF_COL_NW>(a, R, xp, sm);
+  if (tid < RMAX) sm.sgn[tid] = (tid < R && sm.beta[tid] < 0.0) ? -1.0 : 1.0;
+  // R0 = D R from the first R rows (chunk 0)
+  static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+    constexpr int q = decltype(qc)::value;
+    const int c = c0 + q;
+    if (lane < R && c < R) {
+      const int j = lane;
+      const double sg = (sm.beta[j] < 0.0) ? -1.0 : 1.0;
+      const double rr = (c > j) ? a[0][q] : ((c == j) ? sm.beta[j] : 0.0);
+      gR0[j + R * c] = sg * rr;
+    }
+  });
+  // rows of V of chunk p (this wave's columns) into vb[p & 1]
+  auto put_v = [&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    const int row = lane + 64 * p;
+    static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      const int c = c0 + q;
+      const double sc_c = sm.scale[c < R ? c : 0];
+      const double v = (row > c) ? a[p][q] * sc_c : ((row == c) ? 1.0 : 0.0);
+      vb[p & 1][lane][c] = (c < R && row < rows) ? v : 0.0;
+    });
+  };
+  if (wave == 0) block_qr_build_t_wave0<RMAX>(R, sm);
+  put_v(std::integral_constant<int, 0>{});
+  __syncthreads();
+  // Md[m][c] = sgn_c sum_k T[m][k] V1[c][k]  (V1 = rows 0..R-1 of V, in vb[0])
+  for (int e = tid; e < RMAX * RMAX; e += NT) {
+    const int m = e % RMAX, c = e / RMAX;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < RMAX; ++k) acc = fma(sm.T[m][k], vb[0][c][k], acc);
+    smd[m][c] = (m < R && c < R) ? acc * sm.sgn[c] : 0.0;
+  }
+  __syncthreads();
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    if constexpr (p > 0) {
+      put_v(pc);
+      __syncthreads();
+    }
+    const int row = lane + 64 * p;
+    double v[RMAX];
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m) v[m] = vb[p & 1][lane][m];
+    static_for<0, CPW>([&](auto qc) __attribute__((always_inline)) {
+      constexpr int q = decltype(qc)::value;
+      const int c = c0 + q;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < RMAX; ++m) acc = fma(v[m], smd[m][c], acc);
+      const double e = (row == c) ? sm.sgn[c] : 0.0;
+      if (row < rows && c < R) gQ[row + (int64_t)rows * c] = e - acc;
+    });
+  });
+}
+
+// The column-distributed top for stacks of up to `rows` rows (the largest
+// stack of the launch): rank class 32 up to 512 rows, rank class 16 from 513
+// to 1024 rows; false: zqr_top then.
+static bool top_col_launch(int rm, int64_t rows, dim3 grid, const TopArgs& ta, const TopArgs* batch,
+                           hipStream_t st) {
+  const dim3 blk(64 * LEAF_COL_NW);
+  if (rm == 32 && rows <= 256)
+    hipLaunchKernelGGL((zqr_top_col<32, 4>), grid, blk, 0, st, ta, batch);
+  else if (rm == 32 && rows <= 512)
+    hipLaunchKernelGGL((zqr_top_col<32, 8>), grid, blk, 0, st, ta, batch);
+  else if (rm == 16 && rows > 512 && rows <= 1024)
+    hipLaunchKernelGGL((zqr_top_col<16, 16>), grid, blk, 0, st, ta, batch);
+  else
+    return false;
+  return true;
 }
 
 // ------------------------------------------------------------------ form Q0
@@ -812,6 +1032,22 @@ void tsqr_args(const TsqrArgs& t, const TsqrPlan& pl, LeafArgs* la, TopArgs* ta,
                  t.V, t.T, t.Qtop, t.Q0};
 }
 
+// The column-distributed leaf for leaves of `rows` rows in rank class 32
+// (measured: 37 against 58 us for 512-row leaves at rank 20; in rank class
+// 16 with 1024-row leaves it only ties zqr_leaf); false: zqr_leaf then.
+static bool leaf_col_launch(int rm, int64_t rows, dim3 grid, const LeafArgs& la, const LeafArgs* batch,
+                            hipStream_t st) {
+  const dim3 blk(64 * LEAF_COL_NW);
+#define CPQR_LC(RMV, RPV)                                                             \
+  if (rm == RMV && rows == 64 * RPV) {                                                \
+    hipLaunchKernelGGL((zqr_leaf_col<RMV, RPV>), grid, blk, 0, st, la, batch);        \
+    return true;                                                                      \
+  }
+  CPQR_LC(32, 4) CPQR_LC(32, 8)
+#undef CPQR_LC
+  return false;
+}
+
 hipError_t launch_tsqr(const TsqrArgs& t, hipStream_t st) {
   const TsqrPlan pl = tsqr_plan(t.M, t.R);
   if (!pl.ok || pl.P != t.P) return hipErrorInvalidValue;
@@ -820,10 +1056,12 @@ hipError_t launch_tsqr(const TsqrArgs& t, hipStream_t st) {
   TopArgs ta;
   FormArgs fa;
   tsqr_args(t, pl, &la, &ta, &fa);
-  CPQR_QR_SWITCH(rm, pl.leaf_rpt, {
-    hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3(t.P), dim3(QrCfg<RM>::NT), 0, st, la, nullptr);
-  });
-  if (t.P > 1) {
+  if (!leaf_col_launch(rm, pl.leaf_rows, dim3(t.P), la, nullptr, st)) {
+    CPQR_QR_SWITCH(rm, pl.leaf_rpt, {
+      hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3(t.P), dim3(QrCfg<RM>::NT), 0, st, la, nullptr);
+    });
+  }
+  if (t.P > 1 && !top_col_launch(rm, ta.rows, dim3(1), ta, nullptr, st)) {
     CPQR_QR_SWITCH(rm, pl.top_rpt, {
       hipLaunchKernelGGL((zqr_top<RM, RP>), dim3(1), dim3(QrCfg<RM>::NT), 0, st, ta, nullptr);
     });
@@ -839,11 +1077,15 @@ hipError_t launch_tsqr(const TsqrArgs& t, hipStream_t st) {
 hipError_t launch_tsqr_batched(const TsqrBatch& b, hipStream_t st) {
   if (b.count <= 0) return hipSuccess;
   const dim3 nb(1, (unsigned)b.count);
-  CPQR_QR_SWITCH(b.rmax, b.leaf_rpt, {
-    hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3((unsigned)b.Pmax, (unsigned)b.count), dim3(QrCfg<RM>::NT), 0,
-                       st, LeafArgs{}, b.leaf);
-  });
-  if (b.any_top) {
+  if (!leaf_col_launch(b.rmax, (int64_t)QrCfg<32>::NT * b.leaf_rpt, dim3((unsigned)b.Pmax, (unsigned)b.count),
+                       LeafArgs{}, b.leaf, st)) {
+    CPQR_QR_SWITCH(b.rmax, b.leaf_rpt, {
+      hipLaunchKernelGGL((zqr_leaf<RM, RP>), dim3((unsigned)b.Pmax, (unsigned)b.count), dim3(QrCfg<RM>::NT), 0,
+                         st, LeafArgs{}, b.leaf);
+    });
+  }
+  if (b.any_top &&
+      !top_col_launch(b.rmax, (int64_t)QrCfg<32>::NT * b.top_rpt, nb, TopArgs{}, b.top, st)) {
     CPQR_QR_SWITCH(b.rmax, b.top_rpt, {
       hipLaunchKernelGGL((zqr_top<RM, RP>), nb, dim3(QrCfg<RM>::NT), 0, st, TopArgs{}, b.top);
     });
