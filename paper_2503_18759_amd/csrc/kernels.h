@@ -178,11 +178,35 @@ struct ZcolArgs {
   double* V;            // M x R out (Kolda row order)
   double* meta;         // R^2 + 2R doubles out
   int active;           // 0: nothing to do (batched entries of other plans)
+  const double* rf_hi;  // non-null: the last remaining factor (the slowest digit) from here
 };
 // Staircase row table (host): out[2s] = Kolda row, out[2s+1] = digits (5 bits each).
 void stair_table(int R, int K, int64_t M, int* out);
 hipError_t launch_zqr_col(const ZcolPlan& pl, const ZcolArgs& a, hipStream_t st);
 hipError_t launch_zqr_col_batched(const ZcolPlan& pl, int count, const ZcolArgs* args, hipStream_t st);
+// Khatri-Rao QR of Z_n at order N >= 4 by nested two-factor QRs.  With the
+// remaining modes m_1 < ... < m_{N-1}: W_1 = R_{m_2} (.) R_{m_1} = Q_1 T_1 and
+// W_k = R_{m_{k+1}} (.) T_{k-1} = Q_k T_k (k = 2 .. L = N - 2), each an R^2-row
+// staircase QR by zqr_col (compact Q_k).  Column c of Z_n is
+// r_{m_{N-1},c} (x) ... (x) r_{m_2,c} (x) r_{m_1,c}, and replacing the two fastest
+// factors by Q_k t_{k,c} level by level gives
+//   Z_n = (I (x) Q_1)(I (x) Q_2) ... Q_L T_L,
+// a product of matrices with orthonormal columns times an upper triangular
+// T_L with diag >= 0: R0 = T_L and Q0 = that product (form_q0_nested).
+struct NestPlan {
+  bool ok;
+  int L;          // levels (N - 2)
+  ZcolPlan zp;    // plan of the two-factor staircase QRs
+};
+NestPlan nest_plan(int N, int R);
+struct NestArgs {
+  int L, R;
+  int64_t M;                              // R^(N-1)
+  const double* V[CPQR_MAX_ORDER];        // level k: R^2 x R reflectors (Kolda rows)
+  const double* meta[CPQR_MAX_ORDER];     // level k: [Md, D, piv]
+  double* Q0;                             // M x R out
+};
+hipError_t launch_form_q0_nested(const NestArgs& a, hipStream_t st);
 hipError_t launch_factor_qr(int I, int R, const double* A, double* Rn, double* q64, float* q32,
                             hipStream_t st);
 

@@ -28,6 +28,8 @@ namespace cpqr {
 // class: R = 17 for 32 columns, 9 for 16, 2 for 8; capped by the order limit).
 constexpr int qr_max_other_modes(int rmax) { return rmax >= 32 ? 3 : (rmax >= 16 ? 5 : CPQR_MAX_ORDER - 1); }
 int qr_max_order(int R) { return qr_max_other_modes(qr_rmax(R)) + 1; }
+// Levels of the nested Khatri-Rao QR at the largest order of the class.
+constexpr int nest_max_levels(int rmax) { return qr_max_other_modes(rmax) - 1; }
 
 // ----------------------------------------------------------------- leaves
 // src == nullptr: build rows of Z from the R factors in `rf` (N x R x R,
@@ -734,7 +736,9 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
       const int i = rem % RMAX, c = rem / RMAX;
       const int mode = (q < n) ? q : q + 1;
       const bool in = i < R && c < R;
-      const double x = rf[in ? (int64_t)mode * R * R + i + (int64_t)R * c : 0];
+      const gdouble* __restrict__ f =
+          (q == K - 1 && args.rf_hi != nullptr) ? (const gdouble*)args.rf_hi : rf + (int64_t)mode * R * R;
+      const double x = f[in ? i + (int64_t)R * c : 0];
       u.srf[e] = in ? x : 0.0;
     }
   }
@@ -928,6 +932,175 @@ hipError_t launch_zqr_col(const ZcolPlan& pl, const ZcolArgs& a, hipStream_t st)
 hipError_t launch_zqr_col_batched(const ZcolPlan& pl, int count, const ZcolArgs* args, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   return zcol_launch(pl, (unsigned)count, ZcolArgs{}, args, st);
+}
+
+// ------------------------------------------------------- nested Khatri-Rao QR
+NestPlan nest_plan(int N, int R) {
+  NestPlan pl{};
+  if (N < 4 || qr_rmax(R) == 0 || N - 2 > nest_max_levels(qr_rmax(R))) return pl;
+  pl.zp = zcol_plan(3, R);
+  if (!pl.zp.ok) return pl;
+  pl.ok = true;
+  pl.L = N - 2;
+  return pl;
+}
+
+// Explicit Q0 of the nested QR.  In the compact form of zqr_col, Q_k =
+// E_k D_k - V_k Md_k (E_k: the unit vectors of the Kolda rows piv_k).  Row
+// r + R^2 t of Q0 (r: the digits of m_1 and m_2; t: those of m_3 .. m_{N-1},
+// Kolda order) is Q_1[r, :] B_2(t_0) B_3(t_1) ... B_L(t_{L-2}), B_k(d) being
+// rows dR .. dR + R - 1 of Q_k and t_i the base-R digits of t.  Workgroup
+// (t, chunk) stages the blocks of V_k, every Md_k, D_k and piv_k in LDS (all
+// loads in flight together), forms P = B_2 ... B_L and W = Md_1 P there, then
+// one row of its chunk per thread: Q0[r + R^2 t][c] = D_1[j] P[j][c]
+// [r = piv_1(j)] - sum_m V_1[r][m] W[m][c].
+template <int RMAX>
+__global__ __launch_bounds__(256) void form_q0_nested(NestArgs a) {
+  constexpr int LM = nest_max_levels(RMAX);
+  constexpr int LD = RMAX + 1;
+  // level k >= 1: rows d_k R .. of V_k, then B_k; every level: Md_k.  All
+  // R x R blocks are zero-padded to RMAX x RMAX so that the inner loops run
+  // over RMAX terms, unrolled.
+  __shared__ double vb[LM][RMAX][LD];
+  __shared__ double md[LM][RMAX][LD];
+  __shared__ double P[RMAX][LD], W[RMAX][LD];
+  __shared__ double dv[LM][RMAX];
+  __shared__ int pv[LM][RMAX];
+  __shared__ int jof[RMAX * RMAX];   // j with piv_1(j) = r, else -1
+  __shared__ int dig[LM];            // level k >= 1: digit t_{k-1} of t
+  const int R = a.R, L = a.L, R2 = R * R;
+  const int64_t t = blockIdx.x;
+  const int tid = threadIdx.x;
+  // sum_m x(m) y(m) over RMAX terms in four independent chains
+  auto dot = [](auto x, auto y) __attribute__((always_inline)) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m) s[m & 3] = fma(x(m), y(m), s[m & 3]);
+    return (s[0] + s[1]) + (s[2] + s[3]);
+  };
+  // this thread's row of V_1 (independent of everything below: in flight first)
+  const int r = blockIdx.y * 256 + tid;
+  double v[RMAX];
+  {
+    const gdouble* __restrict__ V1 = (const gdouble*)a.V[0];
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m) v[m] = (m < R && r < R2) ? V1[r + (int64_t)R2 * m] : 0.0;
+  }
+  if (tid == 0) {
+    int64_t rem = t;
+    for (int k = 1; k < LM; ++k) {
+      dig[k] = (int)(rem % R);
+      rem /= R;
+    }
+  }
+  for (int e = tid; e < R2; e += 256) jof[e] = -1;
+  for (int e = tid; e < RMAX * LD; e += 256) {
+    (&P[0][0])[e] = 0.0;
+    (&W[0][0])[e] = 0.0;
+  }
+  __syncthreads();
+  // every level's blocks, loads in flight together
+#pragma unroll
+  for (int k = 0; k < LM; ++k) {
+    if (k < L) {
+      const gdouble* __restrict__ V = (const gdouble*)a.V[k];
+      const gdouble* __restrict__ meta = (const gdouble*)a.meta[k];
+      const int row0 = (k > 0) ? dig[k] * R : 0;
+      constexpr int IT = (RMAX * RMAX + 255) / 256;
+      double x[IT], y[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = tid + 256 * it;
+        const int i = e % RMAX, c = e / RMAX;
+        const bool in = e < RMAX * RMAX && i < R && c < R;
+        x[it] = meta[in ? i + R * c : 0];
+        y[it] = (k > 0) ? V[in ? row0 + i + (int64_t)R2 * c : 0] : 0.0;
+      }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = tid + 256 * it;
+        const int i = e % RMAX, c = e / RMAX;
+        const bool in = e < RMAX * RMAX && i < R && c < R;
+        if (e < RMAX * RMAX) {
+          md[k][i][c] = in ? x[it] : 0.0;
+          if (k > 0) vb[k][i][c] = in ? y[it] : 0.0;
+        }
+      }
+      if (tid < RMAX) {
+        const bool in = tid < R;
+        const double d = meta[in ? R2 + tid : 0];
+        const double pr = meta[in ? R2 + R + tid : 0];
+        dv[k][tid] = in ? d : 0.0;
+        pv[k][tid] = in ? (int)pr : -1;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < R && pv[0][tid] >= 0 && pv[0][tid] < R2) jof[pv[0][tid]] = tid;
+  // B_k(d)[j][c] = [dR + j = piv_k(c)] D_k[c] - sum_m vb_k[j][m] Md_k[m][c]
+  // (into W, then over vb_k)
+  for (int k = 1; k < L; ++k) {
+    for (int e = tid; e < RMAX * RMAX; e += 256) {
+      const int j = e % RMAX, c = e / RMAX;
+      const double acc = dot([&](int m) { return vb[k][j][m]; }, [&](int m) { return md[k][m][c]; });
+      W[j][c] = (j < R && c < R) ? (((pv[k][c] == dig[k] * R + j) ? dv[k][c] : 0.0) - acc) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < RMAX * RMAX; e += 256) vb[k][e % RMAX][e / RMAX] = W[e % RMAX][e / RMAX];
+    __syncthreads();
+  }
+  // P = B_L, then P = B_k P for k = L - 1 .. 2 (1-based levels)
+  for (int e = tid; e < RMAX * RMAX; e += 256) P[e % RMAX][e / RMAX] = vb[L - 1][e % RMAX][e / RMAX];
+  __syncthreads();
+  for (int k = L - 2; k >= 1; --k) {
+    for (int e = tid; e < RMAX * RMAX; e += 256) {
+      const int j = e % RMAX, c = e / RMAX;
+      W[j][c] = dot([&](int m) { return vb[k][j][m]; }, [&](int m) { return P[m][c]; });
+    }
+    __syncthreads();
+    for (int e = tid; e < RMAX * RMAX; e += 256) P[e % RMAX][e / RMAX] = W[e % RMAX][e / RMAX];
+    __syncthreads();
+  }
+  // W = Md_1 P
+  for (int e = tid; e < RMAX * RMAX; e += 256) {
+    const int m = e % RMAX, c = e / RMAX;
+    W[m][c] = dot([&](int j) { return md[0][m][j]; }, [&](int j) { return P[j][c]; });
+  }
+  __syncthreads();
+  if (r >= R2) return;
+  const int j = jof[r];
+  const double dj = (j >= 0) ? dv[0][j] : 0.0;
+  gdouble* __restrict__ Q0 = (gdouble*)a.Q0;
+  const int64_t row = r + (int64_t)R2 * t;
+  // four columns at a time (independent chains)
+  for (int c0 = 0; c0 < R; c0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < RMAX; ++m)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = fma(v[m], W[m][(c0 + u) & (RMAX - 1)], acc[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + u;
+      if (c < R) Q0[row + a.M * c] = ((j >= 0) ? dj * P[j][c] : 0.0) - acc[u];
+    }
+  }
+}
+
+hipError_t launch_form_q0_nested(const NestArgs& a, hipStream_t st) {
+  const int rm = qr_rmax(a.R);
+  if (rm == 0 || a.L < 2 || a.L > nest_max_levels(rm)) return hipErrorInvalidValue;
+  int64_t tails = 1;
+  for (int k = 2; k <= a.L; ++k) tails *= a.R;
+  if (a.M != tails * a.R * a.R) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tails, (unsigned)((a.R * a.R + 255) / 256));
+  if (rm == 8)
+    hipLaunchKernelGGL((form_q0_nested<8>), grid, dim3(256), 0, st, a);
+  else if (rm == 16)
+    hipLaunchKernelGGL((form_q0_nested<16>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((form_q0_nested<32>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------- factor QR

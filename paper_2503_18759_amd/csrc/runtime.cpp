@@ -170,6 +170,9 @@ struct Problem {
   StairPlan stair{};      // staircase Z_n QR (ok == false: dense TSQR)
   ZcolPlan zcol{};        // column-distributed staircase Z_n QR, compact Q0 (preferred)
   int* smap = nullptr;    // staircase row table of zqr_col (M x 2 ints)
+  NestPlan nest{};        // nested two-factor Z_n QR (order >= 4 where neither plan above fits)
+  int* nsmap = nullptr;   // its R^2-row staircase table
+  double *nV = nullptr, *nMeta = nullptr, *nT = nullptr;   // per level: V, [Md, D, piv], T
   std::map<uint32_t, TtmShape> ttm_ks;   // TTM step (src | mode << 16) -> launch shape
   int nchunks_max = 0;
   int Imax = 0;
@@ -283,6 +286,19 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
       HIP_TRY(h, hipMemsetAsync(p.q0buf[k], 0, (size_t)2 * p.M * R * 8, h->stream));
       HIP_TRY(h, hipMemsetAsync(p.q0meta[k], 0, (size_t)2 * (R * R + 2 * R) * 8, h->stream));
     }
+  }
+  if (p.nest.ok) {
+    // the levels' staircase table and reflector buffers (cleared once, as above)
+    const int64_t R2 = (int64_t)R * R;
+    const int L = p.nest.L;
+    std::vector<int> tab((size_t)2 * R2);
+    stair_table(R, 2, R2, tab.data());
+    WS(h, p.prefix + "nsmap", tab.size() * sizeof(int), p.nsmap);
+    HIP_TRY(h, hipMemcpy(p.nsmap, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice));
+    WS(h, p.prefix + "nestV", (size_t)L * R2 * R * 8, p.nV);
+    WS(h, p.prefix + "nestMeta", (size_t)L * (R2 + 2 * R) * 8, p.nMeta);
+    WS(h, p.prefix + "nestT", (size_t)(L - 1) * R2 * 8, p.nT);
+    HIP_TRY(h, hipMemsetAsync(p.nV, 0, (size_t)L * R2 * R * 8, h->stream));
   }
   WS(h, p.prefix + "tsqrV", (size_t)p.P * p.leaf_rows * R * 8, p.tV);
   WS(h, p.prefix + "tsqrT", (size_t)p.P * R * R * 8, p.tT);
@@ -541,10 +557,61 @@ StairArgs stair_args(const TsqrArgs& t) {
   return StairArgs{t.N, t.n, t.R, t.M, t.rf, t.R0, t.Q0, 1};
 }
 
+// The nested Z QR of an order >= 4 update (NestPlan): the levels' staircase
+// QRs, each reading the previous level's T, then the explicit Q0.
+hipError_t launch_zqr_nested(const Problem& p, const TsqrArgs& t, hipStream_t s) {
+  const int R = p.R, L = p.nest.L, n = t.n;
+  const int64_t R2 = (int64_t)R * R;
+  const size_t mw = (size_t)R2 + 2 * R;
+  int m[CPQR_MAX_ORDER];   // remaining modes, ascending
+  int nm = 0;
+  for (int k = 0; k < p.N; ++k)
+    if (k != n) m[nm++] = k;
+  NestArgs na{};
+  na.L = L;
+  na.R = R;
+  na.M = p.M;
+  na.Q0 = t.Q0;
+  for (int k = 0; k < L; ++k) {
+    ZcolArgs za{};
+    za.N = 3;
+    za.R = R;
+    za.M = R2;
+    za.smap = p.nsmap;
+    za.V = p.nV + (size_t)k * R2 * R;
+    za.meta = p.nMeta + (size_t)k * mw;
+    za.R0 = (k + 1 < L) ? p.nT + (size_t)k * R2 : t.R0;
+    za.active = 1;
+    if (k == 0) {
+      // W_1 = R_{m_2} (.) R_{m_1}: the first two remaining factors of the
+      // full array, read as the order-3 array at t.rf (or t.rf + R^2)
+      // without mode za.n
+      if (n == 0) {
+        za.rf = t.rf + R2;   // m_1 = 1, m_2 = 2
+        za.n = 2;
+      } else {
+        za.rf = t.rf;        // m_1 = 0, m_2 = 1 (n >= 2) or 2 (n = 1)
+        za.n = (n == 1) ? 1 : 2;
+      }
+    } else {
+      // W_{k+1} = R_{m_{k+2}} (.) T_k
+      za.rf = p.nT + (size_t)(k - 1) * R2;
+      za.n = 2;
+      za.rf_hi = t.rf + (size_t)m[k + 1] * R2;
+    }
+    hipError_t e = launch_zqr_col(p.nest.zp, za, s);
+    if (e != hipSuccess) return e;
+    na.V[k] = za.V;
+    na.meta[k] = za.meta;
+  }
+  return launch_form_q0_nested(na, s);
+}
+
 // The Z QR of a mode update on the path its problem takes: the
 // column-distributed staircase kernel (compact Q0), the one-workgroup
-// staircase kernel, or the two-level TSQR.
+// staircase kernel, the nested two-factor QRs, or the two-level TSQR.
 hipError_t launch_zqr_any(const Problem& p, const TsqrArgs& t, const ApplyArgs& a, hipStream_t s) {
+  if (p.nest.ok) return launch_zqr_nested(p, t, s);
   if (p.zcol.ok)
     return launch_zqr_col(p.zcol, ZcolArgs{t.N, t.n, t.R, t.M, t.rf, p.smap, t.R0, t.Q0,
                                            const_cast<double*>(a.meta_p), 1}, s);
@@ -873,6 +940,7 @@ cpqr_status session_create_impl(cpqr_handle* h, const cpqr_tensor* X, int rank, 
   if (!(o->flags & CPQR_FLAG_DENSE_ZQR)) {
     p.stair = stair_plan(N, rank);
     p.zcol = zcol_plan(N, rank);
+    if (!p.stair.ok && !p.zcol.ok) p.nest = nest_plan(N, rank);
   }
   cpqr_status stt = setup(h, p, o->iters, S.sched);
   if (stt != CPQR_OK) return stt;

@@ -101,6 +101,31 @@ def test_fp64_staircase_zqr_order3(P, dims, R, seed):
         assert np.max(np.abs(a - b)) <= 1e-10
 
 
+@pytest.mark.parametrize("dims,R,seed", [([12, 10, 11, 9], 11, 81), ([9, 10, 8, 11], 17, 82),
+                                         ([7, 8, 6, 9, 7], 6, 83), ([6, 5, 7, 5, 6], 12, 85),
+                                         ([5, 4, 6, 5, 4, 5], 4, 84), ([4, 5, 4, 3, 5, 4], 9, 86)])
+def test_fp64_nested_zqr_orders_4_to_6(P, dims, R, seed):
+    """Orders 4..6 where Z_n (R^(N-1) = 1024..59049 rows) fits no
+    one-workgroup kernel: Z_n = (I (x) Q_1)(I (x) Q_2) ... Q_L T_L by L = N - 2
+    nested two-factor staircase QRs (rank classes 8, 16 and 32; 2, 3 and 4
+    levels) and the explicit Q0 formed from their compact forms.  float64
+    parity with the oracle, whose Householder QR runs on the explicit Z_n,
+    and with the dense two-level TSQR."""
+    prob = G.make_problem(dims, R, seed=seed, rho=0.01, dtype=np.float64)
+    g, o = _run(P, prob, 6, prec="fp64", tree="restructured", extrap="paper")
+    assert g["orders"] == o["orders"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+    x, d = P.to_device(prob.X)
+    dz = P.cp_als_qr(x, R, prob.init, 6, dims=d, tree="restructured", prec="fp64", zqr="dense",
+                     extrapolate="paper")
+    assert np.max(np.abs(g["fits"] - dz["fits"])) <= 1e-12
+    for a, b in zip(g["factors"], dz["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-10
+
+
 @pytest.mark.parametrize("zqr", ["stair", "dense"])
 @pytest.mark.parametrize("dims,R,seed", [([3, 30, 28], 5, 71), ([40, 40, 4], 8, 74),
                                          ([2, 17, 3, 19], 6, 72), ([4, 9, 3, 8, 5], 4, 73),
