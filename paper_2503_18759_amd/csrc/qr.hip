@@ -891,7 +891,7 @@ ZcolPlan zcol_plan(int N, int R) {
   // four waves (one per SIMD) up to 256 rows; eight (two per SIMD, half the
   // columns each) beyond, where the column steps are bound by instruction
   // issue
-  pl.nw = pl.rpl >= 8 ? 8 : 4;
+  pl.nw = (pl.rpl >= 8 || (pl.rpl == 4 && rm == 16 && K == 2)) ? 8 : 4;
   return pl;
 }
 
@@ -909,6 +909,7 @@ static hipError_t zcol_launch(const ZcolPlan& pl, unsigned blocks, const ZcolArg
   if (!pl.ok) return hipErrorInvalidValue;
   if (pl.k == 2) {
     if (pl.rmax == 8) { CPQR_ZC_RPL(8, 2) }
+    else if (pl.rmax == 16 && pl.nw == 8 && pl.rpl == 4) CPQR_ZC(16, 4, 8, 2);
     else if (pl.rmax == 16) { CPQR_ZC_RPL(16, 2) }
     else if (pl.rmax == 32) { CPQR_ZC_RPL(32, 2) }
     else return hipErrorInvalidValue;

@@ -828,10 +828,16 @@ static int ttm_pick_ks(int64_t tiles, int I, int NB) {
   return ks;
 }
 
+// A full two-per-CU grid leaves no CU room for another kernel's workgroup
+// (registers), so the Z QR that runs beside a TTM would wait for the whole
+// TTM; the grid keeps TTM_RESERVE slots free for it.
+static constexpr int TTM_RESERVE = 4;
+
 static dim3 ttm_grid(int64_t tiles, int ks, int wpc) {
   const int tpw = 4 / ks;
   int64_t wgs = (tiles + tpw - 1) / tpw;
-  const int64_t cap = (int64_t)device_cu_count() * (wpc > 0 ? wpc : TTM_WG_PER_CU);
+  const int w = wpc > 0 ? wpc : TTM_WG_PER_CU;
+  const int64_t cap = (int64_t)device_cu_count() * w - (w >= 2 ? TTM_RESERVE : 0);
   if (wgs > cap) wgs = cap;
   return dim3((unsigned)(wgs > 0 ? wgs : 1));
 }
