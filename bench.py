@@ -297,7 +297,7 @@ def paper_shapes_study(sweeps: int = 20, real_rank: int = 16):
     import paper_2503_18759_amd as P
     import synthgen as G
 
-    cases = [("table8_row%d" % r, lambda r=r: G.table8_problem(r)) for r in (1, 4, 7, 8, 10, 11)]
+    cases = [("table8_row%d" % r, lambda r=r: G.table8_problem(r)) for r in (1, 4, 7, 8, 9, 10, 11, 12)]
     cases += [(name + "_standin", lambda name=name: G.real_shape_problem(name, real_rank))
               for name in G.REAL_SHAPES]
     out = {}

@@ -95,8 +95,9 @@ typedef enum { CPQR_DTYPE_F64 = 0, CPQR_DTYPE_F32 = 1 } cpqr_dtype;
                                         of 8 back-to-back launches (it is idempotent) between two events */
 #define CPQR_FLAG_NO_GRAPH     0x4u  /* launch kernels one by one instead of replaying HIP graphs */
 #define CPQR_FLAG_DENSE_ZQR    0x8u  /* factor Z_n by the dense two-level TSQR even where the
-                                        one-workgroup staircase QR applies (Z_n of at most 256
-                                        rows, or order 3 at ranks 17..32); for comparison */
+                                        one-workgroup staircase QR (Z_n of at most 1024 rows) or
+                                        the nested two-factor QR (order >= 4) applies; for
+                                        comparison */
 #define CPQR_FLAG_TIME_PHASES  0x10u /* fill cpqr_result.phase_seconds: kernels launch one by one
                                         (no graphs) with HIP events between kernel groups, and the
                                         host waits after every sweep; excludes TIME_KERNELS */
@@ -201,8 +202,12 @@ typedef struct {
  * its size must fit that TSQR: I_n <= 8192 at R <= 32, 65536 at R <= 16,
  * 524288 at R <= 8 (CPQR_EUNSUPPORTED otherwise; the batched entry point
  * keeps I_n <= 512).
- * Limits of this build: 1 <= R <= 32; Z_n
- * (R^(N-1) x R, including the zero rows of padded modes) must fit a
+ * Limits of this build: 1 <= R <= 32, and the order N at most 4 for
+ * 17 <= R <= 32, 6 for 9 <= R <= 16 and 7 for R <= 8 (Z_n of order N >= 4
+ * is factored by N - 2 nested two-factor QRs of R^2 rows, Section 2.4's
+ * QR of the Khatri-Rao product taken level by level).  With
+ * CPQR_FLAG_DENSE_ZQR, and for every problem of cpqr_als_qr_batched, Z_n
+ * (R^(N-1) x R, including the zero rows of padded modes) must also fit a
  * two-level TSQR: ceil(R^(N-1) / B) * R <= B with B = 2048, 1024, 512 rows
  * for R <= 8, 16, 32 (for example 40^5 at R = 16 and 256^3 at R = 32 fit).
  * On a runtime error (CPQR_ERANKDEF, CPQR_ENONFINITE, CPQR_EHIP) the outputs

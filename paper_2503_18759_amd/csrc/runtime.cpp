@@ -268,10 +268,12 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
   WS(h, p.prefix + "rf", (size_t)N * R * R * 8, p.rf);
   WS(h, p.prefix + "lambda", (size_t)R * 8, p.lambda);
   p.M = ipow(R, N - 1);
+  // the two-level TSQR's buffers, unless the nested QR takes every Z_n and
+  // the TSQR has no plan at this size
   const TsqrPlan pl = tsqr_plan(p.M, R);
-  if (!pl.ok) return fail(h, CPQR_EUNSUPPORTED, "no TSQR plan for %lld x %d", (long long)p.M, R);
-  p.leaf_rows = pl.leaf_rows;
-  p.P = pl.P;
+  if (!pl.ok && !p.nest.ok) return fail(h, CPQR_EUNSUPPORTED, "no Z QR plan for %lld x %d", (long long)p.M, R);
+  p.leaf_rows = pl.ok ? pl.leaf_rows : 0;
+  p.P = pl.ok ? pl.P : 0;
   for (int k = 0; k < N; ++k) WS(h, p.prefix + "q0_" + std::to_string(k), (size_t)2 * p.M * R * 8, p.q0buf[k]);
   p.q0meta.assign(N, nullptr);
   if (p.zcol.ok) {
@@ -300,10 +302,12 @@ cpqr_status setup(cpqr_handle* h, Problem& p, int iters,
     WS(h, p.prefix + "nestT", (size_t)(L - 1) * R2 * 8, p.nT);
     HIP_TRY(h, hipMemsetAsync(p.nV, 0, (size_t)L * R2 * R * 8, h->stream));
   }
-  WS(h, p.prefix + "tsqrV", (size_t)p.P * p.leaf_rows * R * 8, p.tV);
-  WS(h, p.prefix + "tsqrT", (size_t)p.P * R * R * 8, p.tT);
-  WS(h, p.prefix + "tsqrS", (size_t)p.P * R * R * 8, p.tStack);
-  WS(h, p.prefix + "tsqrQ", (size_t)p.P * R * R * 8, p.tQtop);
+  if (pl.ok) {
+    WS(h, p.prefix + "tsqrV", (size_t)p.P * p.leaf_rows * R * 8, p.tV);
+    WS(h, p.prefix + "tsqrT", (size_t)p.P * R * R * 8, p.tT);
+    WS(h, p.prefix + "tsqrS", (size_t)p.P * R * R * 8, p.tStack);
+    WS(h, p.prefix + "tsqrQ", (size_t)p.P * R * R * 8, p.tQtop);
+  }
   WS(h, p.prefix + "R0", (size_t)R * R * 8, p.R0);
   if (p.Imax > CPQR_MAX_FACTOR_ROWS) {
     // a smaller mode can take more, shorter leaves than a larger one, so the
@@ -723,7 +727,12 @@ cpqr_status check_args(cpqr_handle* h, const cpqr_tensor* X, int rank, const cpq
       return fail(h, CPQR_EUNSUPPORTED, "mode %d of size %lld is beyond the two-level factor TSQR at rank %d", k,
                   (long long)X->dims[k], rank);
   }
-  if (N > qr_max_order(rank) || !tsqr_plan(ipow(rank, N - 1), rank).ok)
+  // Z_n of R^(N-1) rows: the nested two-factor QR covers every order up to
+  // qr_max_order at R <= 32; CPQR_FLAG_DENSE_ZQR asks for the two-level TSQR,
+  // which bounds R^(N-1)
+  if (N > qr_max_order(rank))
+    return fail(h, CPQR_EUNSUPPORTED, "order %d is beyond the Z QR kernels at rank %d", N, rank);
+  if ((o->flags & CPQR_FLAG_DENSE_ZQR) && !tsqr_plan(ipow(rank, N - 1), rank).ok)
     return fail(h, CPQR_EUNSUPPORTED, "R^(N-1) too large for a two-level TSQR at this rank");
   if (o->prec == CPQR_PREC_BF16X3)
     for (int k = 0; k < N; ++k)
@@ -1989,6 +1998,9 @@ cpqr_status cpqr_als_qr_batched(cpqr_handle* h, int count, const cpqr_tensor* Xs
         o.prec != o0.prec || o.iters != o0.iters)
       return fail(h, CPQR_EINVAL, "batched problem %d: order and options must match problem 0", t);
     if (o.tol != 0.0) return fail(h, CPQR_EINVAL, "batched runs a fixed number of sweeps: tol must be 0");
+    // the batched driver factors Z_n of order >= 4 by the two-level TSQR
+    if (!tsqr_plan(ipow(ranks[t], Xs[t].order - 1), ranks[t]).ok)
+      return fail(h, CPQR_EUNSUPPORTED, "batched problem %d: R^(N-1) too large for the batched Z QR", t);
   }
   if (o0.prec == CPQR_PREC_FP64) return fail(h, CPQR_EUNSUPPORTED, "batched: FP32 or BF16X3 TTMs only");
   for (int t = 0; t < count; ++t)

@@ -89,7 +89,11 @@ def test_schedule_rejects_bad_arguments():
     (dict(dims=[2048, 256, 256], rank=32), C.OK),              # Density-sized
     (dict(dims=[8192, 40, 40], rank=32), C.OK),                # largest two-level factor TSQR at R 32
     (dict(dims=[8193, 40, 40], rank=32), C.EUNSUPPORTED),
-    (dict(dims=[40] * 5, rank=32), C.EUNSUPPORTED),            # R^(N-1) beyond two-level TSQR
+    (dict(dims=[40] * 5, rank=32), C.EUNSUPPORTED),            # order 5 beyond the Z QR at rank 32
+    (dict(dims=[100] * 4, rank=30), C.OK),                     # Z_n 27,000 x 30: nested QR only
+    (dict(dims=[100] * 4, rank=30, flags=0x8), C.EUNSUPPORTED),  # ... beyond the dense TSQR
+    (dict(dims=[6] * 6, rank=16), C.OK),                       # order 6, Z_n of 16^5 rows
+    (dict(dims=[6] * 7, rank=16), C.EUNSUPPORTED),             # order 7 beyond the Z QR at rank 16
     (dict(dims=[40, 40, 40], rank=0), C.EINVAL),
     (dict(dims=[40, 40, 40], rank=5, prec="fp64"), C.EINVAL),  # f32 data with fp64 precision
     (dict(dims=[40, 40, 40], rank=5, dtype="f64"), C.EINVAL),  # f64 data with fp32 precision

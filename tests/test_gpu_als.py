@@ -126,6 +126,20 @@ def test_fp64_nested_zqr_orders_4_to_6(P, dims, R, seed):
         assert np.max(np.abs(a - b)) <= 1e-10
 
 
+@pytest.mark.parametrize("dims,R,seed", [([34, 32, 31, 33], 30, 87), ([5, 6, 5, 6, 5, 6], 12, 88)])
+def test_fp64_nested_zqr_beyond_the_tsqr(P, dims, R, seed):
+    """Z_n beyond the two-level TSQR (27,000 x 30 at order 4; 12^5 = 248,832
+    rows at order 6, with modes below the rank): only the nested QR applies.
+    float64 parity with the oracle."""
+    prob = G.make_problem(dims, R, seed=seed, rho=0.01, dtype=np.float64)
+    g, o = _run(P, prob, 5, prec="fp64", tree="restructured", extrap="paper")
+    assert g["orders"] == o["orders"]
+    assert np.max(np.abs(g["fits"] - o["fits"])) <= 1e-10
+    assert abs(g["fit_explicit"] - o["fitx"]) <= 1e-10
+    for a, b in zip(g["factors"], o["factors"]):
+        assert np.max(np.abs(a - b)) <= 1e-8
+
+
 @pytest.mark.parametrize("zqr", ["stair", "dense"])
 @pytest.mark.parametrize("dims,R,seed", [([3, 30, 28], 5, 71), ([40, 40, 4], 8, 74),
                                          ([2, 17, 3, 19], 6, 72), ([4, 9, 3, 8, 5], 4, 73),
@@ -189,10 +203,13 @@ def test_fp32_real_data_shaped_standins(P, name, scale):
     _check_fp32(g, o)
 
 
-@pytest.mark.parametrize("row,dims", [(4, [40, 36, 32]), (10, [24, 22, 21, 20]), (8, [22, 21, 20, 23])])
+@pytest.mark.parametrize("row,dims", [(4, [40, 36, 32]), (10, [24, 22, 21, 20]), (8, [22, 21, 20, 23]),
+                                      (9, [34, 32, 31, 33]), (12, [33, 34, 32, 31])])
 def test_fp32_table8_recipes(P, row, dims):
     """Table 8 recipes (per-mode congruence, true rank 20, the second noise
-    term) at reduced mode sizes, paper extrapolation, against the oracle."""
+    term) at reduced mode sizes, paper extrapolation, against the oracle.
+    Rows 9 and 12 (rank 30 at order 4: Z_n of 27,000 rows) are beyond the
+    two-level TSQR and take the nested QR."""
     prob = G.table8_problem(row, dims=dims)
     g, o = _run(P, prob, 8, prec="fp32", tree="restructured", extrap="paper")
     _check_fp32(g, o)
