@@ -173,6 +173,13 @@ struct Problem {
   NestPlan nest{};        // nested two-factor Z_n QR (order >= 4 where neither plan above fits)
   int* nsmap = nullptr;   // its R^2-row staircase table
   double *nV = nullptr, *nMeta = nullptr, *nT = nullptr;   // per level: V, [Md, D, piv], T
+  // Host-side bookkeeping of the sweep being enqueued, for reusing nested
+  // levels: what each level's buffers hold (a signature of its remaining
+  // modes and their factors' versions; 0: nothing valid) and the version of
+  // every R factor (bumped when an update rewrites it)
+  mutable std::vector<uint64_t> nest_sig;
+  mutable std::vector<uint64_t> fac_ver;
+  mutable uint64_t ver_clock = 0;
   std::map<uint32_t, TtmShape> ttm_ks;   // TTM step (src | mode << 16) -> launch shape
   int nchunks_max = 0;
   int Imax = 0;
@@ -576,7 +583,35 @@ hipError_t launch_zqr_nested(const Problem& p, const TsqrArgs& t, hipStream_t s)
   na.R = R;
   na.M = p.M;
   na.Q0 = t.Q0;
+  // Level k (0-based) reads R_{m_1} .. R_{m_{k+2}} only.  Within a sweep, a
+  // level whose buffers were written from the same factors at the same
+  // versions (an earlier update with the same first remaining modes, none
+  // of them rewritten since) is kept; the last level always runs, as it
+  // writes R0.
+  uint64_t sig[CPQR_MAX_ORDER] = {};
+  int k0 = 0;
+  if ((int)p.nest_sig.size() == L && (int)p.fac_ver.size() == p.N) {
+    uint64_t hsh = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+      for (int b = 0; b < 8; ++b) {
+        hsh ^= (v >> (8 * b)) & 0xff;
+        hsh *= 1099511628211ull;
+      }
+    };
+    mix((uint64_t)m[0]);
+    mix(p.fac_ver[m[0]]);
+    for (int k = 0; k < L; ++k) {
+      mix((uint64_t)m[k + 1]);
+      mix(p.fac_ver[m[k + 1]]);
+      sig[k] = hsh | 1u;
+    }
+    while (k0 < L - 1 && p.nest_sig[k0] == sig[k0]) ++k0;
+  }
   for (int k = 0; k < L; ++k) {
+    na.V[k] = p.nV + (size_t)k * R2 * R;
+    na.meta[k] = p.nMeta + (size_t)k * mw;
+  }
+  for (int k = k0; k < L; ++k) {
     ZcolArgs za{};
     za.N = 3;
     za.R = R;
@@ -605,8 +640,7 @@ hipError_t launch_zqr_nested(const Problem& p, const TsqrArgs& t, hipStream_t s)
     }
     hipError_t e = launch_zqr_col(p.nest.zp, za, s);
     if (e != hipSuccess) return e;
-    na.V[k] = za.V;
-    na.meta[k] = za.meta;
+    if ((int)p.nest_sig.size() == L) p.nest_sig[k] = sig[k];
   }
   return launch_form_q0_nested(na, s);
 }
@@ -1102,6 +1136,11 @@ cpqr_status run_sweep(cpqr_session* S, int k, bool capture_only = false) {
     return hipSuccess;
   };
   auto enqueue = [&](hipStream_t q) -> hipError_t {
+    if (p.nest.ok) {
+      // nested levels are reused within a sweep only
+      p.nest_sig.assign(p.nest.L, 0);
+      p.fac_ver.assign(p.N, 0);
+    }
     hipEvent_t join = nullptr;   // end of the forked Z QR of the next update
     bool forked = false;         // the next update's Z QR is on the side branch
     auto fork_next = [&](size_t from) -> hipError_t {
@@ -1174,12 +1213,14 @@ cpqr_status run_sweep(cpqr_session* S, int k, bool capture_only = false) {
         bool tail = false;
         if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q, z, &ft, &tail)) != hipSuccess)
           return e;
+        if (p.nest.ok) p.fac_ver[st.mode] = ++p.ver_clock;   // R_n rewritten
         if ((e = fork_next(i + 1)) != hipSuccess) return e;
         if (tail && (e = launch_finish_tail(ft, q)) != hipSuccess) return e;
       } else {
         if ((e = launch_update(p, st.mode, k, (int)i == last_update, o, q, false, nullptr, nullptr,
                                phases ? &mark : nullptr)) != hipSuccess)
           return e;
+        if (p.nest.ok) p.fac_ver[st.mode] = ++p.ver_clock;   // R_n rewritten
       }
     }
     return hipSuccess;
