@@ -727,6 +727,22 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
     double srf[K * RMAX * RMAX];   // R factors of the other modes (Z build)
     double v1[RMAX][RMAX + 1];     // first R rows of V (epilogue)
   } u;
+  __shared__ int skrow[64 * RPL];  // Kolda row of each staircase row, for the epilogue
+  // Kolda row and digits of this lane's rows (all loads in flight together,
+  // beside those of the R factors)
+  typedef __attribute__((address_space(1))) const int2 gint2;
+  const gint2* __restrict__ smap = (const gint2*)args.smap;
+  int2 tab[RPL];
+  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+    constexpr int p = decltype(pc)::value;
+    const int s = lane + 64 * p;
+    int2 t = make_int2(-1, 0);
+    if (s < M) {
+      t.x = smap[s].x;
+      t.y = smap[s].y;
+    }
+    tab[p] = t;
+  });
   {
     // R factors of the other modes (ascending mode order), zero-padded to
     // RMAX x RMAX so that columns c >= R of every product vanish
@@ -746,19 +762,12 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
   // Z[s][c] = prod_k R_k[d_k(s)][c] for this wave's columns c = NW q + wave,
   // rows s = lane + 64 p < 64 L(q) in staircase order (digits from the
   // staircase table, 5 bits each)
-  typedef __attribute__((address_space(1))) const int2 gint2;
-  const gint2* __restrict__ smap = (const gint2*)args.smap;
-  int2 tab[RPL];   // Kolda row and digits of this lane's rows (all loads in flight together)
-  static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
-    constexpr int p = decltype(pc)::value;
-    const int s = lane + 64 * p;
-    int2 t = make_int2(-1, 0);
-    if (s < M) {
-      t.x = smap[s].x;
-      t.y = smap[s].y;
-    }
-    tab[p] = t;
-  });
+  if (wave == 0) {
+    static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
+      constexpr int p = decltype(pc)::value;
+      skrow[lane + 64 * p] = tab[p].x;
+    });
+  }
   double a[SC::TOT];
   static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
     constexpr int p = decltype(pc)::value;
@@ -804,12 +813,11 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
       u.v1[j][c] = (j < R && c < R) ? v1 : 0.0;
     }
   });
-  // the Kolda rows again (not held through the factorisation)
+  // the Kolda rows again (not held through the factorisation: from LDS)
   int krow[RPL];
   static_for<0, RPL>([&](auto pc) __attribute__((always_inline)) {
     constexpr int p = decltype(pc)::value;
-    const int s = lane + 64 * p;
-    krow[p] = (s < M) ? smap[s].x : -1;
+    krow[p] = skrow[lane + 64 * p];
   });
   // wave 0 builds T while the other waves write their rows of V
   if (wave == 0) block_qr_build_t_wave0<RMAX>(R, sm);
@@ -828,7 +836,7 @@ void zqr_col(ZcolArgs a0, const ZcolArgs* __restrict__ batch) {
   });
   gdouble* __restrict__ meta = (gdouble*)args.meta;
   if (tid < R) {
-    meta[R * R + R + tid] = (double)smap[tid].x;
+    meta[R * R + R + tid] = (double)skrow[tid];
     meta[R * R + tid] = (sm.beta[tid] < 0.0) ? -1.0 : 1.0;
   }
   __syncthreads();
