@@ -959,10 +959,13 @@ NestPlan nest_plan(int N, int R) {
 // r + R^2 t of Q0 (r: the digits of m_1 and m_2; t: those of m_3 .. m_{N-1},
 // Kolda order) is Q_1[r, :] B_2(t_0) B_3(t_1) ... B_L(t_{L-2}), B_k(d) being
 // rows dR .. dR + R - 1 of Q_k and t_i the base-R digits of t.  Workgroup
-// (t, chunk) stages the blocks of V_k, every Md_k, D_k and piv_k in LDS (all
-// loads in flight together), forms P = B_2 ... B_L and W = Md_1 P there, then
-// one row of its chunk per thread: Q0[r + R^2 t][c] = D_1[j] P[j][c]
-// [r = piv_1(j)] - sum_m V_1[r][m] W[m][c].
+// (t, chunk, column group) stages the blocks of V_k, every Md_k, D_k and
+// piv_k in LDS (all loads in flight together), forms its columns of
+// P = B_2 ... B_L and W = Md_1 P there, then one row of its chunk per thread:
+// Q0[r + R^2 t][c] = D_1[j] P[j][c] [r = piv_1(j)] - sum_m V_1[r][m] W[m][c].
+// Columns of Q0 per workgroup of form_q0_nested.
+static constexpr int FQ_CW = 8;
+
 template <int RMAX>
 __global__ __launch_bounds__(256) void form_q0_nested(NestArgs a) {
   constexpr int LM = nest_max_levels(RMAX);
@@ -1046,33 +1049,39 @@ __global__ __launch_bounds__(256) void form_q0_nested(NestArgs a) {
   }
   __syncthreads();
   if (tid < R && pv[0][tid] >= 0 && pv[0][tid] < R2) jof[pv[0][tid]] = tid;
+  // This workgroup writes the columns [cb, cb + FQ_CW) of Q0, which need
+  // only those columns of P and W, and so only those of the last block.
+  const int cb = blockIdx.z * FQ_CW;
   // B_k(d)[j][c] = [dR + j = piv_k(c)] D_k[c] - sum_m vb_k[j][m] Md_k[m][c]
-  // (into W, then over vb_k)
+  // (into W, then over vb_k; the last level on this workgroup's columns)
   for (int k = 1; k < L; ++k) {
-    for (int e = tid; e < RMAX * RMAX; e += 256) {
-      const int j = e % RMAX, c = e / RMAX;
+    const int c0 = (k == L - 1) ? cb : 0;
+    const int n = RMAX * ((k == L - 1) ? FQ_CW : RMAX);
+    for (int e = tid; e < n; e += 256) {
+      const int j = e % RMAX, c = c0 + e / RMAX;
       const double acc = dot([&](int m) { return vb[k][j][m]; }, [&](int m) { return md[k][m][c]; });
       W[j][c] = (j < R && c < R) ? (((pv[k][c] == dig[k] * R + j) ? dv[k][c] : 0.0) - acc) : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < RMAX * RMAX; e += 256) vb[k][e % RMAX][e / RMAX] = W[e % RMAX][e / RMAX];
+    for (int e = tid; e < n; e += 256) vb[k][e % RMAX][c0 + e / RMAX] = W[e % RMAX][c0 + e / RMAX];
     __syncthreads();
   }
-  // P = B_L, then P = B_k P for k = L - 1 .. 2 (1-based levels)
-  for (int e = tid; e < RMAX * RMAX; e += 256) P[e % RMAX][e / RMAX] = vb[L - 1][e % RMAX][e / RMAX];
+  // P = B_L, then P = B_k P for k = L - 1 .. 2 (1-based levels); columns
+  // outside [cb, cb + FQ_CW) stay zero
+  for (int e = tid; e < RMAX * FQ_CW; e += 256) P[e % RMAX][cb + e / RMAX] = vb[L - 1][e % RMAX][cb + e / RMAX];
   __syncthreads();
   for (int k = L - 2; k >= 1; --k) {
-    for (int e = tid; e < RMAX * RMAX; e += 256) {
-      const int j = e % RMAX, c = e / RMAX;
+    for (int e = tid; e < RMAX * FQ_CW; e += 256) {
+      const int j = e % RMAX, c = cb + e / RMAX;
       W[j][c] = dot([&](int m) { return vb[k][j][m]; }, [&](int m) { return P[m][c]; });
     }
     __syncthreads();
-    for (int e = tid; e < RMAX * RMAX; e += 256) P[e % RMAX][e / RMAX] = W[e % RMAX][e / RMAX];
+    for (int e = tid; e < RMAX * FQ_CW; e += 256) P[e % RMAX][cb + e / RMAX] = W[e % RMAX][cb + e / RMAX];
     __syncthreads();
   }
   // W = Md_1 P
-  for (int e = tid; e < RMAX * RMAX; e += 256) {
-    const int m = e % RMAX, c = e / RMAX;
+  for (int e = tid; e < RMAX * FQ_CW; e += 256) {
+    const int m = e % RMAX, c = cb + e / RMAX;
     W[m][c] = dot([&](int j) { return md[0][m][j]; }, [&](int j) { return P[j][c]; });
   }
   __syncthreads();
@@ -1082,7 +1091,7 @@ __global__ __launch_bounds__(256) void form_q0_nested(NestArgs a) {
   gdouble* __restrict__ Q0 = (gdouble*)a.Q0;
   const int64_t row = r + (int64_t)R2 * t;
   // four columns at a time (independent chains)
-  for (int c0 = 0; c0 < R; c0 += 4) {
+  for (int c0 = cb; c0 < R && c0 < cb + FQ_CW; c0 += 4) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < RMAX; ++m)
@@ -1102,7 +1111,7 @@ hipError_t launch_form_q0_nested(const NestArgs& a, hipStream_t st) {
   int64_t tails = 1;
   for (int k = 2; k <= a.L; ++k) tails *= a.R;
   if (a.M != tails * a.R * a.R) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)tails, (unsigned)((a.R * a.R + 255) / 256));
+  const dim3 grid((unsigned)tails, (unsigned)((a.R * a.R + 255) / 256), (unsigned)((a.R + FQ_CW - 1) / FQ_CW));
   if (rm == 8)
     hipLaunchKernelGGL((form_q0_nested<8>), grid, dim3(256), 0, st, a);
   else if (rm == 16)
